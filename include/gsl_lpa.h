@@ -1,0 +1,159 @@
+/*
+ * gsl_lpa.h -- C ABI of the MI355X (gfx950) GSL-LPA library, libgsl_lpa.so.
+ *
+ * GSL-LPA (Sahu, arXiv:2403.01261) is label-propagation community detection
+ * followed by a split pass that breaks every internally-disconnected community
+ * into its connected pieces.  The library runs every step in HIP kernels.
+ *
+ * Conventions shared by all entry points
+ * -------------------------------------
+ *  - Graphs are CSR: offsets int64[n+1] (offsets[0] == 0, non-decreasing),
+ *    cols int32[nnz] with nnz = offsets[n] and 0 <= cols[e] < n, weights
+ *    uint32[nnz] or NULL meaning every weight is 1.  The graph must be
+ *    symmetric: an entry (i, j, w) implies an entry (j, i, w) (the paper
+ *    adds reverse edges, Sec. 5.1.3).  This is the caller's promise; it is not
+ *    checked.  Rows need not be sorted; self loops and duplicate entries are
+ *    allowed (a self loop never votes, duplicates add their weights).
+ *  - Every array argument is a DEVICE pointer on the current HIP device,
+ *    allocated and owned by the caller.  Outputs must not alias inputs.
+ *  - Vertex ids and labels are int32: 0 <= n < 2^31.
+ *  - Work is enqueued on the stream given to gsl_set_stream (default: the
+ *    null stream) and every call returns only after that work has finished.
+ *  - Scratch memory is owned by the library, cached per device and grown on
+ *    demand; gsl_release() frees it.
+ *  - Calls return a gsl_status.  No C++ exception crosses the ABI.  On error
+ *    gsl_last_error() returns a message for the calling thread; outputs are
+ *    unspecified.
+ *  - Calls are not re-entrant on one device: two threads must not run calls
+ *    on the same device at the same time.
+ */
+#ifndef GSL_LPA_H
+#define GSL_LPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gsl_status {
+  GSL_OK = 0,
+  GSL_EINVAL = -1,    /* bad argument (size, range, NULL where not allowed) */
+  GSL_ENOMEM = -2,    /* device allocation of scratch failed */
+  GSL_EDEVICE = -3,   /* a HIP runtime call failed; see gsl_last_error() */
+  GSL_EOVERFLOW = -4  /* a row's summed weight reaches 2^32 (see gsl_lpa) */
+} gsl_status;
+
+#define GSL_STATS_MAX_ITERS 64
+
+typedef struct gsl_options {
+  int32_t prune;  /* nonzero (default 1): pruning, Alg. 3 -- only vertices with a
+                     neighbour that changed in the previous sweep are processed.
+                     Results are identical either way; it only saves work. */
+  int32_t split;  /* nonzero (default 1): run the split pass (Alg. 2) after the
+                     sweeps, as GSL-LPA does; 0 returns the raw LPA labels. */
+  int32_t timing; /* nonzero: fill the ms_* fields of gsl_stats (records HIP
+                     events between phases). */
+  int32_t reserved;
+} gsl_options;
+
+typedef struct gsl_stats {
+  int32_t iterations;                       /* sweeps performed */
+  int32_t split_rounds;                     /* hook rounds of the split */
+  int64_t changed[GSL_STATS_MAX_ITERS];     /* dN of each sweep (Alg. 3) */
+  int64_t processed[GSL_STATS_MAX_ITERS];   /* vertices scanned in each sweep */
+  int64_t edges[GSL_STATS_MAX_ITERS];       /* row entries scanned in each sweep */
+  int64_t marked[GSL_STATS_MAX_ITERS];      /* 1 if the sweep marked neighbours */
+  int64_t nnz;                              /* offsets[n] */
+  int64_t max_degree;
+  float ms_plan, ms_sweeps, ms_split, ms_total;
+  float ms_sweep[GSL_STATS_MAX_ITERS];
+} gsl_stats;
+
+/*
+ * gsl_lpa -- GSL-LPA (Alg. 3): label-propagation sweeps, then the split.
+ *
+ * Labels start as C[i] = i.  Each sweep gives every processed vertex i the
+ * label c maximising sum_{j in row i, j != i, C[j] = c} w_ij (Eq. 2), the
+ * smallest such label on ties; a vertex with no entry j != i keeps its label.
+ * Sweeps are synchronous: all vertices read the labels of the previous sweep.
+ * dN counts the vertices whose label changed; the loop stops after max_iters
+ * sweeps or as soon as dN / n <= tolerance (evaluated exactly as that double
+ * comparison).  Finally the split (Alg. 2) relabels every vertex with the
+ * smallest vertex id of its connected piece inside its community, so no
+ * output community is internally disconnected.
+ *
+ *   offsets, cols, weights, n : graph (see conventions); weights may be NULL
+ *   max_iters  : MAX_ITERATIONS, >= 0
+ *   tolerance  : tau, 0 <= tolerance <= 1
+ *   labels_out : int32[n] device array receiving the labels
+ *
+ * Returns GSL_EOVERFLOW when some vertex's summed row weight is >= 2^32 (label
+ * weights are summed exactly in 32-bit integers).  n == 0 is a no-op.
+ */
+int gsl_lpa(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+            int32_t max_iters, double tolerance, int32_t *labels_out);
+
+/*
+ * gsl_lpa_ex -- gsl_lpa with options (NULL: defaults {1, 1, 0}) and optional
+ * statistics (stats may be NULL; per-sweep arrays hold the first
+ * GSL_STATS_MAX_ITERS sweeps).
+ */
+int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+               int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
+               int32_t *labels_out);
+
+/*
+ * gsl_split -- the split pass alone (Alg. 2; Alg. 1 reaches the same fixed
+ * point): labels_out[i] = the smallest vertex id v such that v and i are joined
+ * by a path whose vertices all carry label labels_in[i].
+ *
+ *   labels_in  : int32[n] device array, each value in [0, n)
+ *   labels_out : int32[n] device array
+ * Returns GSL_EINVAL if a label is outside [0, n).
+ */
+int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels_in,
+              int32_t *labels_out);
+
+/*
+ * gsl_modularity -- modularity Q of a labelling (Eq. 1, second form):
+ *   Q = sum_c [ sigma_c / 2m - (Sigma_c / 2m)^2 ]
+ * where sigma_c sums w over CSR entries (i, j) with C_i = C_j = c, Sigma_c
+ * sums w over entries with C_i = c and 2m sums w over all entries.  The sums
+ * are exact integers; Q = I/2m - S2/(2m)^2 with I = sum sigma_c and
+ * S2 = sum Sigma_c^2 is evaluated once in IEEE double precision.  Q = 0 when
+ * 2m = 0.
+ *
+ *   labels : int32[n] device array, each value in [0, n)
+ *   q_out  : HOST pointer receiving Q
+ */
+int gsl_modularity(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+                   const int32_t *labels, double *q_out);
+
+/*
+ * gsl_convergence_limit -- host-only helper: the largest k in [0, n] with
+ * (double)k / (double)n <= tolerance (0 for n == 0, -1 for a tolerance
+ * outside [0, 1]).  The device loop stops when dN <= this limit, which is the
+ * same test as dN / n <= tolerance (Alg. 3) because correctly rounded
+ * division is monotone in k.
+ */
+int64_t gsl_convergence_limit(int64_t n, double tolerance);
+
+/* Stream for all subsequent calls of this process (a hipStream_t; NULL = the
+ * null stream). */
+int gsl_set_stream(void *hip_stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *gsl_last_error(void);
+
+/* Frees the cached scratch memory of every device. */
+void gsl_release(void);
+
+/* Library version string. */
+const char *gsl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSL_LPA_H */

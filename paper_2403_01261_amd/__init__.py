@@ -1,0 +1,179 @@
+"""Python binding of libgsl_lpa.so: GSL-LPA community detection on MI355X.
+
+The functions keep the names of the C ABI (include/gsl_lpa.h) and only marshal
+arguments: every step runs in the library's HIP kernels.  Tensors are torch
+device tensors (int64 offsets, int32 cols, uint32-valued weights stored as
+torch.int32 or torch.uint32, int32 labels) and calls run on torch's current
+stream.  If the native library is missing the import fails loudly: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_split", "gsl_modularity", "gsl_convergence_limit",
+           "gsl_set_stream", "gsl_release", "gsl_version", "GslError", "LIB_PATH", "load"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgsl_lpa.so")
+STATS_MAX_ITERS = 64
+
+GSL_OK, GSL_EINVAL, GSL_ENOMEM, GSL_EDEVICE, GSL_EOVERFLOW = 0, -1, -2, -3, -4
+
+
+class GslError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("gsl error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("prune", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("split_rounds", ctypes.c_int32),
+                ("changed", ctypes.c_int64 * STATS_MAX_ITERS),
+                ("processed", ctypes.c_int64 * STATS_MAX_ITERS),
+                ("edges", ctypes.c_int64 * STATS_MAX_ITERS),
+                ("marked", ctypes.c_int64 * STATS_MAX_ITERS),
+                ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
+                ("ms_plan", ctypes.c_float), ("ms_sweeps", ctypes.c_float),
+                ("ms_split", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("ms_sweep", ctypes.c_float * STATS_MAX_ITERS)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load(path: str = LIB_PATH):
+    """Loads the native library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libgsl_lpa.so not found at %s: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`" % path)
+    lib = ctypes.CDLL(path)
+    lib.gsl_lpa.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _VP]
+    lib.gsl_lpa_ex.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                               ctypes.POINTER(_Options), ctypes.POINTER(_Stats), _VP]
+    lib.gsl_split.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP]
+    lib.gsl_modularity.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]
+    lib.gsl_convergence_limit.argtypes = [ctypes.c_int64, ctypes.c_double]
+    lib.gsl_convergence_limit.restype = ctypes.c_int64
+    lib.gsl_set_stream.argtypes = [_VP]
+    lib.gsl_last_error.restype = ctypes.c_char_p
+    lib.gsl_version.restype = ctypes.c_char_p
+    lib.gsl_release.restype = None
+    for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream):
+        f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != GSL_OK:
+        raise GslError(rc, _lib.gsl_last_error().decode())
+
+
+def _dev(t, dtypes, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise TypeError("%s must be a tensor" % name)
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a GPU tensor" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise TypeError("%s must be contiguous" % name)
+    return t.data_ptr() if t.numel() else None
+
+
+_U32 = tuple(d for d in (getattr(torch, "uint32", None), torch.int32) if d is not None)
+
+
+def _bind_stream():
+    lib = load()
+    _check(lib.gsl_set_stream(_VP(torch.cuda.current_stream().cuda_stream)))
+    return lib
+
+
+def _graph_args(offsets, cols, weights):
+    n = offsets.numel() - 1
+    if n < 0:
+        raise ValueError("offsets must hold n + 1 entries")
+    return (_dev(offsets, (torch.int64,), "offsets"), _dev(cols, (torch.int32,), "cols"),
+            _dev(weights, _U32, "weights", allow_none=True), n)
+
+
+def gsl_lpa(offsets, cols, weights=None, max_iters=20, tolerance=0.05, out=None):
+    """GSL-LPA labels (int32 tensor).  See include/gsl_lpa.h."""
+    labels, _ = gsl_lpa_ex(offsets, cols, weights, max_iters, tolerance, out=out)
+    return labels
+
+
+def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=True, split=True,
+               timing=False, out=None):
+    """Returns (labels, stats dict)."""
+    lib = _bind_stream()
+    po, pc, pw, n = _graph_args(offsets, cols, weights)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    if out.numel() != n:
+        raise ValueError("out must hold n labels")
+    pl = _dev(out, (torch.int32,), "out")
+    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), 0)
+    st = _Stats()
+    _check(lib.gsl_lpa_ex(po, pc, pw, n, int(max_iters), float(tolerance), ctypes.byref(opt),
+                          ctypes.byref(st), pl))
+    it = st.iterations
+    k = min(it, STATS_MAX_ITERS)
+    stats = {"iterations": it, "changed": list(st.changed[:k]), "processed": list(st.processed[:k]),
+             "edges": list(st.edges[:k]), "marked": list(st.marked[:k]), "nnz": st.nnz,
+             "max_degree": st.max_degree, "ms_plan": st.ms_plan, "ms_sweeps": st.ms_sweeps,
+             "ms_split": st.ms_split, "ms_total": st.ms_total}
+    return out, stats
+
+
+def gsl_split(offsets, cols, labels_in, out=None):
+    lib = _bind_stream()
+    po, pc, _, n = _graph_args(offsets, cols, None)
+    if labels_in.numel() != n:
+        raise ValueError("labels_in must hold n labels")
+    pin = _dev(labels_in, (torch.int32,), "labels_in")
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    _check(lib.gsl_split(po, pc, n, pin, _dev(out, (torch.int32,), "out")))
+    return out
+
+
+def gsl_modularity(offsets, cols, weights, labels) -> float:
+    lib = _bind_stream()
+    po, pc, pw, n = _graph_args(offsets, cols, weights)
+    if labels.numel() != n:
+        raise ValueError("labels must hold n labels")
+    q = ctypes.c_double(0.0)
+    _check(lib.gsl_modularity(po, pc, pw, n, _dev(labels, (torch.int32,), "labels"), ctypes.byref(q)))
+    return q.value
+
+
+def gsl_convergence_limit(n: int, tolerance: float) -> int:
+    return int(load().gsl_convergence_limit(int(n), float(tolerance)))
+
+
+def gsl_set_stream(stream) -> None:
+    _check(load().gsl_set_stream(_VP(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)))
+
+
+def gsl_release() -> None:
+    load().gsl_release()
+
+
+def gsl_version() -> str:
+    return load().gsl_version().decode()

@@ -1,0 +1,442 @@
+// C ABI of libgsl_lpa.so (declared in include/gsl_lpa.h): argument checks,
+// per-device scratch cache and the host loop that enqueues the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/gsl_lpa.h"
+#include "gsl_internal.h"
+
+namespace {
+
+using gsl::Counters;
+
+thread_local std::string g_err;
+hipStream_t g_stream = nullptr;
+std::mutex g_mu;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      return fail(GSL_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),      \
+                  __FILE__, __LINE__);                                                     \
+  } while (0)
+
+// Scratch cached per device; grown on demand, freed by gsl_release().
+struct Scratch {
+  int64_t n_cap = -1;
+  int32_t *Cn = nullptr;
+  uint8_t *chg = nullptr;
+  uint8_t *act[2] = {nullptr, nullptr};
+  int32_t *list = nullptr;
+  int32_t *parent = nullptr;
+  int64_t *blk_counts = nullptr;
+  unsigned long long *sigma = nullptr;
+  unsigned long long *partials = nullptr;
+  int partial_blocks = 0;
+  int64_t ctr_bytes = 0;
+  Counters *ctr = nullptr;
+  Counters *ctr_host = nullptr;  // pinned mirror (with the per-sweep arrays)
+  uint64_t *hub_tab = nullptr;
+  int64_t hub_slots = 0;
+  int hub_log2cap = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+std::map<int, Scratch> g_scratch;
+
+void free_scratch(Scratch &s) {
+  hipFree(s.Cn);
+  hipFree(s.chg);
+  hipFree(s.act[0]);
+  hipFree(s.act[1]);
+  hipFree(s.list);
+  hipFree(s.parent);
+  hipFree(s.blk_counts);
+  hipFree(s.sigma);
+  hipFree(s.partials);
+  hipFree(s.ctr);
+  hipFree(s.hub_tab);
+  if (s.ctr_host) hipHostFree(s.ctr_host);
+  for (auto &e : s.ev)
+    if (e) hipEventDestroy(e);
+  s = Scratch();
+}
+
+template <class T>
+hipError_t dmalloc(T **p, int64_t count) {
+  return hipMalloc(reinterpret_cast<void **>(p), (size_t)(count > 0 ? count : 1) * sizeof(T));
+}
+
+// Makes sure per-vertex scratch holds n vertices and the counters block holds
+// max_iters sweeps.
+int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
+  if (n > s.n_cap) {
+    const int64_t cap = n;
+    hipFree(s.Cn);
+    hipFree(s.chg);
+    hipFree(s.act[0]);
+    hipFree(s.act[1]);
+    hipFree(s.list);
+    hipFree(s.parent);
+    hipFree(s.blk_counts);
+    hipFree(s.sigma);
+    s.Cn = nullptr; s.chg = nullptr; s.act[0] = s.act[1] = nullptr; s.list = nullptr;
+    s.parent = nullptr; s.blk_counts = nullptr; s.sigma = nullptr;
+    s.n_cap = -1;
+    const int64_t flag_bytes = (cap + 3) / 4 * 4 + 16;
+    if (dmalloc(&s.Cn, cap) != hipSuccess || dmalloc(&s.chg, flag_bytes) != hipSuccess ||
+        dmalloc(&s.act[0], flag_bytes) != hipSuccess || dmalloc(&s.act[1], flag_bytes) != hipSuccess ||
+        dmalloc(&s.list, cap) != hipSuccess || dmalloc(&s.parent, cap) != hipSuccess ||
+        dmalloc(&s.blk_counts, gsl::plan_blocks(cap) * gsl::kNumTiers) != hipSuccess ||
+        dmalloc(&s.sigma, cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "device allocation of scratch for %lld vertices failed", (long long)n);
+    }
+    s.n_cap = cap;
+  }
+  if (!s.partials) {
+    s.partial_blocks = 4096;
+    if (dmalloc(&s.partials, 2 * (int64_t)s.partial_blocks) != hipSuccess)
+      return fail(GSL_ENOMEM, "device allocation failed");
+  }
+  const int64_t need = (int64_t)sizeof(Counters) + 3 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
+  if (need > s.ctr_bytes) {
+    hipFree(s.ctr);
+    if (s.ctr_host) hipHostFree(s.ctr_host);
+    s.ctr = nullptr;
+    s.ctr_host = nullptr;
+    s.ctr_bytes = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&s.ctr), (size_t)need) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&s.ctr_host), (size_t)need, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "counter allocation failed");
+    }
+    s.ctr_bytes = need;
+  }
+  if (!s.ev[0])
+    for (auto &e : s.ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(GSL_EDEVICE, "hipEventCreate failed");
+  return GSL_OK;
+}
+
+unsigned long long *sweep_array(Counters *c, int which, int32_t max_iters) {
+  auto *base = reinterpret_cast<unsigned long long *>(c + 1);
+  return base + (size_t)which * (size_t)(max_iters > 0 ? max_iters : 1);
+}
+
+int get_scratch(Scratch **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  *out = &g_scratch[dev];
+  return GSL_OK;
+}
+
+bool bad_tolerance(double t) { return !(t >= 0.0 && t <= 1.0); }
+
+// Reads offsets[0] and offsets[n]; checks offsets[0] == 0 and nnz >= 0.
+int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st) {
+  int64_t ends[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&ends[1], offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ends[0] != 0) return fail(GSL_EINVAL, "offsets[0] must be 0 (got %lld)", (long long)ends[0]);
+  if (ends[1] < 0) return fail(GSL_EINVAL, "offsets[n] must be >= 0");
+  *nnz = ends[1];
+  return GSL_OK;
+}
+
+// Runs the degree plan and copies the counters block to the host mirror.
+int run_plan(Scratch &s, const int64_t *offsets, int64_t n, hipStream_t st) {
+  HIP_TRY(hipMemsetAsync(s.ctr, 0, (size_t)s.ctr_bytes, st));
+  HIP_TRY(gsl::launch_plan(offsets, n, s.list, s.blk_counts, s.ctr, st));
+  HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return GSL_OK;
+}
+
+int ensure_hub_table(Scratch &s, int64_t hubs, uint64_t max_degree, hipStream_t st) {
+  if (hubs <= 0) return GSL_OK;
+  int log2cap = 1;
+  while (((uint64_t)1 << log2cap) < 2 * max_degree) ++log2cap;
+  // One table of 2^log2cap slots per resident hub workgroup: at most 512
+  // workgroups and at most kHubTableBytes in total (at least one table).
+  constexpr int64_t kHubTableBytes = (int64_t)4 << 30;
+  int64_t slots = hubs < 512 ? hubs : 512;
+  const int64_t fit = kHubTableBytes / ((int64_t)sizeof(uint64_t) << log2cap);
+  if (slots > fit) slots = fit > 0 ? fit : 1;
+  if (log2cap > s.hub_log2cap || slots > s.hub_slots) {
+    hipFree(s.hub_tab);
+    s.hub_tab = nullptr;
+    const int lc = log2cap > s.hub_log2cap ? log2cap : s.hub_log2cap;
+    const int64_t sl = slots > s.hub_slots ? slots : s.hub_slots;
+    const int64_t words = sl << lc;
+    if (dmalloc(&s.hub_tab, words) != hipSuccess) {
+      (void)hipGetLastError();
+      s.hub_log2cap = 0;
+      s.hub_slots = 0;
+      return fail(GSL_ENOMEM, "hub table allocation (%lld slots) failed", (long long)words);
+    }
+    HIP_TRY(gsl::launch_fill_u64(s.hub_tab, 0xFFFFFFFF00000000ull, words, st));
+    s.hub_log2cap = lc;
+    s.hub_slots = sl;
+  }
+  return GSL_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms;
+}
+
+int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+             int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
+             int32_t *labels_out) {
+  gsl_options o = {1, 1, 0, 0};
+  if (opt) o = *opt;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n = %lld out of range", (long long)n);
+  if (max_iters < 0) return fail(GSL_EINVAL, "max_iters must be >= 0");
+  if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
+  if (n == 0) return GSL_OK;
+  if (!offsets || !labels_out) return fail(GSL_EINVAL, "offsets and labels_out must not be NULL");
+  const hipStream_t st = g_stream;
+  Scratch *sp = nullptr;
+  int rc = get_scratch(&sp);
+  if (rc) return rc;
+  Scratch &s = *sp;
+  int64_t nnz = 0;
+  if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
+  if ((rc = ensure_scratch(s, n, max_iters))) return rc;
+  if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
+  if ((rc = run_plan(s, offsets, n, st))) return rc;
+  Counters plan = *s.ctr_host;
+  if ((rc = ensure_hub_table(s, plan.tier_count[gsl::kHubTier], plan.max_degree, st))) return rc;
+  const int64_t limit = gsl_convergence_limit(n, tolerance);
+  int32_t *C = labels_out;
+  HIP_TRY(gsl::launch_init_labels(C, s.Cn, n, st));
+  const int64_t flag_bytes = (n + 3) / 4 * 4;
+  HIP_TRY(gsl::launch_fill_u8(s.chg, 0, flag_bytes, st));
+  HIP_TRY(gsl::launch_fill_u8(s.act[0], 0, flag_bytes, st));
+  HIP_TRY(gsl::launch_fill_u8(s.act[1], 0, flag_bytes, st));
+  if (o.timing) HIP_TRY(hipEventRecord(s.ev[1], st));
+  unsigned long long *dn_arr = sweep_array(s.ctr, 0, max_iters);
+  unsigned long long *pr_arr = sweep_array(s.ctr, 1, max_iters);
+  unsigned long long *ed_arr = sweep_array(s.ctr, 2, max_iters);
+  int32_t it = 0;
+  bool marked_prev = false;
+  int64_t dn_prev = n;
+  int overflow = 0;
+  while (it < max_iters) {
+    // Pruning: sweep `it` processes only flagged vertices if the previous
+    // sweep marked; this sweep marks if the previous one changed few vertices
+    // (otherwise the next sweep simply runs dense).
+    const bool dense = !(o.prune && marked_prev);
+    const bool mark = o.prune && it >= 1 && dn_prev * 8 <= n;
+    gsl::SweepArgs a;
+    a.off = offsets;
+    a.cols = cols;
+    a.w = weights;
+    a.C = C;
+    a.Cn = s.Cn;
+    a.chg = s.chg;
+    a.act = s.act[it & 1];
+    a.nact = s.act[(it + 1) & 1];
+    a.dense = dense ? 1 : 0;
+    a.mark = mark ? 1 : 0;
+    a.dn = dn_arr + it;
+    a.processed = pr_arr + it;
+    a.edges = ed_arr + it;
+    a.overflow = reinterpret_cast<unsigned long long *>(&s.ctr->overflow);
+    for (int t = 1; t < gsl::kNumTiers; ++t) {
+      const int64_t cnt = plan.tier_count[t];
+      if (cnt <= 0) continue;
+      const int32_t *l = s.list + (plan.tier_start[t] - plan.tier_start[1]);
+      HIP_TRY(gsl::launch_sweep_tier(t, a, l, cnt, s.hub_tab, s.hub_log2cap, (int)s.hub_slots, st));
+    }
+    HIP_TRY(gsl::launch_apply(C, s.Cn, s.chg, dense ? nullptr : s.act[it & 1], n, st));
+    unsigned long long dn_host[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&dn_host[0], dn_arr + it, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&dn_host[1], &s.ctr->overflow, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (stats && it < GSL_STATS_MAX_ITERS) stats->marked[it] = mark ? 1 : 0;
+    ++it;
+    if (dn_host[1]) {
+      overflow = 1;
+      break;
+    }
+    marked_prev = mark;
+    dn_prev = (int64_t)dn_host[0];
+    if ((int64_t)dn_host[0] <= limit) break;
+  }
+  if (o.timing) HIP_TRY(hipEventRecord(s.ev[2], st));
+  if (overflow)
+    return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; weights are summed in 32 bits");
+  if (o.split)
+    HIP_TRY(gsl::launch_split(offsets, cols, n, C, s.parent, labels_out, s.list, plan.tier_count,
+                              plan.tier_start, st));
+  if (o.timing) HIP_TRY(hipEventRecord(s.ev[3], st));
+  if (stats) {
+    HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, (size_t)s.ctr_bytes, hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (stats) {
+    stats->iterations = it;
+    stats->split_rounds = o.split ? 1 : 0;
+    stats->nnz = nnz;
+    stats->max_degree = (int64_t)plan.max_degree;
+    const unsigned long long *hd = sweep_array(s.ctr_host, 0, max_iters);
+    const unsigned long long *hp = sweep_array(s.ctr_host, 1, max_iters);
+    const unsigned long long *he = sweep_array(s.ctr_host, 2, max_iters);
+    for (int k = 0; k < it && k < GSL_STATS_MAX_ITERS; ++k) {
+      stats->changed[k] = (int64_t)hd[k];
+      stats->processed[k] = (int64_t)hp[k];
+      stats->edges[k] = (int64_t)he[k];
+    }
+    if (o.timing) {
+      stats->ms_plan = elapsed(s.ev[0], s.ev[1]);
+      stats->ms_sweeps = elapsed(s.ev[1], s.ev[2]);
+      stats->ms_split = elapsed(s.ev[2], s.ev[3]);
+      stats->ms_total = elapsed(s.ev[0], s.ev[3]);
+    }
+  }
+  return GSL_OK;
+}
+
+int check_labels(Scratch &s, const int32_t *labels, int64_t n, hipStream_t st) {
+  HIP_TRY(hipMemsetAsync(&s.ctr->bad_label, 0, sizeof(uint64_t), st));
+  HIP_TRY(gsl::launch_check_labels(labels, n, reinterpret_cast<unsigned long long *>(&s.ctr->bad_label), st));
+  uint64_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, &s.ctr->bad_label, sizeof(bad), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (bad) return fail(GSL_EINVAL, "a label is outside [0, n)");
+  return GSL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gsl_lpa(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+            int32_t max_iters, double tolerance, int32_t *labels_out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return lpa_impl(offsets, cols, weights, n, max_iters, tolerance, nullptr, nullptr, labels_out);
+}
+
+int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+               int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
+               int32_t *labels_out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return lpa_impl(offsets, cols, weights, n, max_iters, tolerance, opt, stats, labels_out);
+}
+
+int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels_in,
+              int32_t *labels_out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n out of range");
+  if (n == 0) return GSL_OK;
+  if (!offsets || !labels_in || !labels_out) return fail(GSL_EINVAL, "NULL argument");
+  if (labels_in == labels_out) return fail(GSL_EINVAL, "labels_out must not alias labels_in");
+  const hipStream_t st = g_stream;
+  Scratch *sp = nullptr;
+  int rc = get_scratch(&sp);
+  if (rc) return rc;
+  Scratch &s = *sp;
+  int64_t nnz = 0;
+  if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
+  if ((rc = ensure_scratch(s, n, 1))) return rc;
+  if ((rc = check_labels(s, labels_in, n, st))) return rc;
+  if ((rc = run_plan(s, offsets, n, st))) return rc;
+  Counters plan = *s.ctr_host;
+  HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list,
+                            plan.tier_count, plan.tier_start, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return GSL_OK;
+}
+
+int gsl_modularity(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+                   const int32_t *labels, double *q_out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!q_out) return fail(GSL_EINVAL, "q_out must not be NULL");
+  *q_out = 0.0;
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n out of range");
+  if (n == 0) return GSL_OK;
+  if (!offsets || !labels) return fail(GSL_EINVAL, "NULL argument");
+  const hipStream_t st = g_stream;
+  Scratch *sp = nullptr;
+  int rc = get_scratch(&sp);
+  if (rc) return rc;
+  Scratch &s = *sp;
+  int64_t nnz = 0;
+  if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
+  if ((rc = ensure_scratch(s, n, 1))) return rc;
+  if ((rc = check_labels(s, labels, n, st))) return rc;
+  HIP_TRY(hipMemsetAsync(s.ctr, 0, sizeof(Counters), st));
+  HIP_TRY(hipMemsetAsync(s.sigma, 0, (size_t)n * sizeof(unsigned long long), st));
+  HIP_TRY(gsl::launch_modularity(offsets, cols, weights, n, labels, s.sigma, s.partials,
+                                 s.partial_blocks, s.ctr, st));
+  HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *q_out = s.ctr_host->q;
+  return GSL_OK;
+}
+
+int64_t gsl_convergence_limit(int64_t n, double tolerance) {
+  if (!(tolerance >= 0.0 && tolerance <= 1.0)) return -1;
+  if (n <= 0) return 0;
+  const double dn = (double)n;
+  int64_t k = (int64_t)std::floor(tolerance * dn);
+  if (k < 0) k = 0;
+  if (k > n) k = n;
+  while (k > 0 && !((double)k / dn <= tolerance)) --k;
+  while (k < n && (double)(k + 1) / dn <= tolerance) ++k;
+  // k == 0 may itself fail only if tolerance < 0, excluded above.
+  return k;
+}
+
+int gsl_set_stream(void *hip_stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return GSL_OK;
+}
+
+const char *gsl_last_error(void) { return g_err.c_str(); }
+
+void gsl_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto &kv : g_scratch) {
+    if (hipSetDevice(kv.first) == hipSuccess) free_scratch(kv.second);
+  }
+  g_scratch.clear();
+  if (have) (void)hipSetDevice(cur);
+}
+
+const char *gsl_version(void) { return "gsl_lpa 0.1 (gfx950)"; }
+
+}  // extern "C"

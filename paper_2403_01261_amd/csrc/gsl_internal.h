@@ -1,0 +1,86 @@
+// Internal declarations shared by the HIP translation units of libgsl_lpa.so.
+// Not part of the public ABI (that is include/gsl_lpa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gsl {
+
+// ----------------------------------------------------------------------------
+// Degree tiers.  Every vertex with degree d > 0 is processed by the kernel of
+// the smallest tier whose bound is >= d; tier 0 holds isolated vertices, which
+// never change label and are not listed.
+//   tier 1        : one thread per vertex, labels held in registers
+//   tiers 2 - 6   : a group of G lanes per vertex, LDS hash table per group
+//   tiers 7, 8    : one workgroup per vertex, LDS hash table per workgroup
+//   tier 9 (hub)  : one workgroup per vertex, hash table in global memory
+// ----------------------------------------------------------------------------
+constexpr int kNumTiers = 10;
+constexpr int kHubTier = 9;
+constexpr int64_t kTierMaxDeg[kNumTiers] = {0, 8, 16, 32, 64, 128, 512, 2048, 8192,
+                                            (int64_t)0x7fffffffffffffffLL};
+
+// Device-side counters; one block of memory zeroed at the start of every call.
+struct Counters {
+  int64_t tier_count[16];   // vertices per tier
+  int64_t tier_start[16];   // first index of each tier in the vertex list
+  uint64_t max_degree;
+  uint64_t overflow;        // set when a row's weight sum reaches 2^32
+  uint64_t split_changed;   // hook round: nonzero if any union happened
+  uint64_t bad_label;       // set when an input label is outside [0, n)
+  uint64_t two_m, intra;    // modularity integer parts
+  uint64_t s2_lo, s2_hi;
+  double q;
+  uint64_t pad[3];
+  // followed by per-sweep arrays dn[max_iters], processed[], edges[]
+};
+
+// Per-sweep counter triple location inside the counters block.
+struct SweepCounters {
+  unsigned long long *dn;
+  unsigned long long *processed;
+  unsigned long long *edges;
+};
+
+// Arguments common to every sweep kernel.
+struct SweepArgs {
+  const int64_t *off;
+  const int32_t *cols;
+  const uint32_t *w;      // NULL: unit weights
+  const int32_t *C;       // labels read by this sweep
+  int32_t *Cn;            // new label of each changed vertex
+  uint8_t *chg;           // 1 where the vertex changed in this sweep
+  const uint8_t *act;     // processed set of this sweep (ignored when dense)
+  uint8_t *nact;          // marks for the next sweep (written when mark)
+  int dense;              // process every listed vertex
+  int mark;               // mark neighbours of changed vertices in nact
+  unsigned long long *dn, *processed, *edges, *overflow;
+};
+
+// ---- launchers (stream-ordered, no synchronisation) ----
+hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *blk_counts,
+                       Counters *ctr, hipStream_t s);
+int64_t plan_blocks(int64_t n);
+
+hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t count,
+                             uint64_t *hub_tab, int hub_log2cap, int hub_slots, hipStream_t s);
+hipError_t launch_apply(int32_t *C, const int32_t *Cn, uint8_t *chg, uint8_t *act_clear,
+                        int64_t n, hipStream_t s);
+hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
+
+hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
+                        int32_t *parent, int32_t *out, const int32_t *list,
+                        const int64_t *tier_count_host, const int64_t *tier_start_host,
+                        hipStream_t s);
+hipError_t launch_check_labels(const int32_t *labels, int64_t n, unsigned long long *bad,
+                               hipStream_t s);
+
+hipError_t launch_modularity(const int64_t *off, const int32_t *cols, const uint32_t *w, int64_t n,
+                             const int32_t *labels, unsigned long long *sigma_tot,
+                             unsigned long long *partials, int partial_blocks, Counters *ctr,
+                             hipStream_t s);
+
+}  // namespace gsl

@@ -1,0 +1,469 @@
+// Label-propagation sweep kernels (lpaMove + scanCommunities of Alg. 3, the
+// label rule of Eq. 2), synchronous form.
+//
+// Every kernel processes the vertices of one degree tier.  For a vertex i it
+// sums w over the row entries (i, j), j != i, per label C[j], takes the label
+// of largest sum (smallest label on ties; a row without such entries keeps its
+// label) and, if that label differs from C[i], writes it to Cn[i], sets
+// chg[i] and counts the change.  C is only read during a sweep; a separate
+// apply kernel copies Cn into C for the changed vertices afterwards, so every
+// vertex reads the labels of the previous sweep.
+//
+// Pruning: with `dense` clear, only vertices flagged in `act` are processed;
+// with `mark` set, every neighbour of a changed vertex is flagged in `nact`
+// for the next sweep.  Processing more vertices than flagged never changes a
+// result (an unflagged vertex already holds the argmax of its unchanged
+// neighbourhood), so the host may run a sweep dense instead of marking.
+//
+// Weights are summed exactly in 32-bit integers; every sweep checks that no
+// row's total weight reaches 2^32 and raises `overflow` otherwise.
+#include "device_common.h"
+#include "gsl_internal.h"
+
+namespace gsl {
+
+namespace {
+
+__device__ __forceinline__ void record_change(const SweepArgs &a, int32_t v, uint32_t cstar,
+                                              LocalCounts &lc) {
+  a.Cn[v] = (int32_t)cstar;
+  a.chg[v] = 1;
+  lc.dn += 1;
+}
+
+__device__ __forceinline__ void mark_row(const SweepArgs &a, int64_t b, int64_t e, int64_t first,
+                                         int64_t step) {
+  for (int64_t p = b + first; p < e; p += step) {
+    const int32_t j = a.cols[p];
+    if (!a.nact[j]) a.nact[j] = 1;
+  }
+}
+
+__device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCounts &lc,
+                                             unsigned long long *red) {
+  const unsigned long long dn = block_sum(lc.dn, red);
+  const unsigned long long pr = block_sum(lc.processed, red);
+  const unsigned long long ed = block_sum(lc.edges, red);
+  const unsigned long long ov = block_sum(lc.overflow, red);
+  if (threadIdx.x == 0) {
+    if (dn) atomicAdd(a.dn, dn);
+    if (pr) atomicAdd(a.processed, pr);
+    if (ed) atomicAdd(a.edges, ed);
+    if (ov) atomicAdd(a.overflow, ov);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tier 1: one thread per vertex, degree <= D.  The row's labels and weights
+// stay in registers; the weight of a label is the sum over equal entries.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *__restrict__ list,
+                                                    int64_t count) {
+  __shared__ unsigned long long red[256 / kWave];
+  LocalCounts lc;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
+    const int32_t v = list[idx];
+    if (!a.dense && !a.act[v]) continue;
+    const int64_t b = a.off[v];
+    const int d = (int)(a.off[v + 1] - b);
+    int32_t col[D];
+    uint32_t lab[D], w[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) col[k] = k < d ? a.cols[b + k] : v;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      lab[k] = col[k] != v ? (uint32_t)a.C[col[k]] : kNoLabel;
+      w[k] = k < d ? (a.w ? a.w[b + k] : 1u) : 0u;
+    }
+    unsigned long long rowsum = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) rowsum += w[k];
+    unsigned long long best = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if (lab[k] == kNoLabel) continue;
+      uint32_t s = 0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) s += lab[m] == lab[k] ? w[m] : 0u;
+      const unsigned long long key = argmax_key(lab[k], s);
+      best = key > best ? key : best;
+    }
+    lc.processed += 1;
+    lc.edges += (unsigned long long)d;
+    lc.overflow += rowsum >> 32 ? 1 : 0;
+    if (best) {
+      const uint32_t cstar = key_label(best);
+      if (cstar != (uint32_t)a.C[v]) {
+        record_change(a, v, cstar, lc);
+        if (a.mark)
+#pragma unroll
+          for (int k = 0; k < D; ++k)
+            if (k < d && !a.nact[col[k]]) a.nact[col[k]] = 1;
+      }
+    }
+  }
+  flush_counts(a, lc, red);
+}
+
+// ---------------------------------------------------------------------------
+// Tiers 2-6: a group of G lanes (G <= 64, inside one wavefront) per vertex,
+// with a private LDS table of 2^LOG2S slots per group.  All groups of a block
+// move through insert / scan phases together, separated by block barriers.
+// ---------------------------------------------------------------------------
+template <int G, int LOG2S, int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) void sweep_group(SweepArgs a, const int32_t *__restrict__ list,
+                                                     int64_t count) {
+  constexpr int GPB = BLOCK / G;
+  constexpr int S = 1 << LOG2S;
+  __shared__ unsigned long long tab[GPB * S];
+  __shared__ unsigned long long red[BLOCK / kWave];
+  for (int s = threadIdx.x; s < GPB * S; s += BLOCK) tab[s] = kEmptySlot;
+  __syncthreads();
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  unsigned long long *T = tab + g * S;
+  LocalCounts lc;
+  for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
+    const int64_t idx = base + g;
+    int32_t v = -1;
+    int64_t b = 0, e = 0;
+    int log2s = 1;
+    if (idx < count) {
+      v = list[idx];
+      if (!a.dense && !a.act[v]) v = -1;
+      if (v >= 0) {
+        b = a.off[v];
+        e = a.off[v + 1];
+        log2s = table_log2(e - b, 1, LOG2S);
+      }
+    }
+    unsigned long long rowsum = 0;
+    if (v >= 0) {
+      for (int64_t p0 = b + lane; p0 < e; p0 += (int64_t)G * U) {
+        int32_t j[U];
+        uint32_t lab[U], w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t p = p0 + (int64_t)u * G;
+          j[u] = p < e ? a.cols[p] : v;
+          w[u] = p < e ? (a.w ? a.w[p] : 1u) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) lab[u] = j[u] != v ? (uint32_t)a.C[j[u]] : kNoLabel;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          rowsum += w[u];
+          if (lab[u] != kNoLabel) lds_table_add(T, log2s, lab[u], w[u]);
+        }
+      }
+    }
+    __syncthreads();
+    unsigned long long best = 0;
+    if (v >= 0) {
+      for (int s = lane; s < (1 << log2s); s += G) {
+        const unsigned long long x = T[s];
+        if (x != kEmptySlot) {
+          const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
+          best = key > best ? key : best;
+          T[s] = kEmptySlot;
+        }
+      }
+    }
+    best = group_max<G>(best);
+    rowsum = group_sum<G>(rowsum);
+    if (v >= 0) {
+      if (lane == 0) {
+        lc.processed += 1;
+        lc.edges += (unsigned long long)(e - b);
+        lc.overflow += rowsum >> 32 ? 1 : 0;
+      }
+      if (best) {
+        const uint32_t cstar = key_label(best);
+        if (cstar != (uint32_t)a.C[v]) {
+          if (lane == 0) record_change(a, v, cstar, lc);
+          if (a.mark) mark_row(a, b, e, lane, G);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  flush_counts(a, lc, red);
+}
+
+// ---------------------------------------------------------------------------
+// Tiers 7, 8: one workgroup per vertex, LDS table of up to 2^LOG2S slots.
+// ---------------------------------------------------------------------------
+template <int LOG2S, int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) void sweep_block(SweepArgs a, const int32_t *__restrict__ list,
+                                                     int64_t count) {
+  constexpr int S = 1 << LOG2S;
+  __shared__ unsigned long long tab[S];
+  __shared__ unsigned long long red[BLOCK / kWave];
+  __shared__ unsigned long long bestw[BLOCK / kWave];
+  for (int s = threadIdx.x; s < S; s += BLOCK) tab[s] = kEmptySlot;
+  __syncthreads();
+  LocalCounts lc;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int32_t v = list[idx];
+    if (!a.dense && !a.act[v]) continue;  // uniform across the block
+    const int64_t b = a.off[v], e = a.off[v + 1];
+    const int log2s = table_log2(e - b, 1, LOG2S);
+    unsigned long long rowsum = 0;
+    for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += (int64_t)BLOCK * U) {
+      int32_t j[U];
+      uint32_t lab[U], w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = p0 + (int64_t)u * BLOCK;
+        j[u] = p < e ? a.cols[p] : v;
+        w[u] = p < e ? (a.w ? a.w[p] : 1u) : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) lab[u] = j[u] != v ? (uint32_t)a.C[j[u]] : kNoLabel;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rowsum += w[u];
+        if (lab[u] != kNoLabel) lds_table_add(tab, log2s, lab[u], w[u]);
+      }
+    }
+    __syncthreads();
+    unsigned long long best = 0;
+    for (int s = threadIdx.x; s < (1 << log2s); s += BLOCK) {
+      const unsigned long long x = tab[s];
+      if (x != kEmptySlot) {
+        const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
+        best = key > best ? key : best;
+        tab[s] = kEmptySlot;
+      }
+    }
+    best = group_max<kWave>(best);
+    rowsum = wave_sum(rowsum);
+    if (lane == 0) {
+      bestw[wid] = best;
+      red[wid] = rowsum;
+    }
+    __syncthreads();
+    best = 0;
+    rowsum = 0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / kWave; ++k) {
+      best = bestw[k] > best ? bestw[k] : best;
+      rowsum += red[k];
+    }
+    if (threadIdx.x == 0) {
+      lc.processed += 1;
+      lc.edges += (unsigned long long)(e - b);
+      lc.overflow += rowsum >> 32 ? 1 : 0;
+    }
+    if (best) {
+      const uint32_t cstar = key_label(best);
+      if (cstar != (uint32_t)a.C[v]) {
+        if (threadIdx.x == 0) record_change(a, v, cstar, lc);
+        if (a.mark) mark_row(a, b, e, threadIdx.x, BLOCK);
+      }
+    }
+    __syncthreads();
+  }
+  flush_counts(a, lc, red);
+}
+
+// ---------------------------------------------------------------------------
+// Tier 9 (hubs): one workgroup per vertex; the table lives in global memory,
+// one region of 2^log2cap slots per resident workgroup, kept all-empty
+// between vertices.
+// ---------------------------------------------------------------------------
+template <int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) void sweep_hub(SweepArgs a, const int32_t *__restrict__ list,
+                                                   int64_t count, unsigned long long *hub_tab,
+                                                   int log2cap) {
+  __shared__ unsigned long long red[BLOCK / kWave];
+  __shared__ unsigned long long bestw[BLOCK / kWave];
+  unsigned long long *tab = hub_tab + ((size_t)blockIdx.x << log2cap);
+  LocalCounts lc;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int32_t v = list[idx];
+    if (!a.dense && !a.act[v]) continue;
+    const int64_t b = a.off[v], e = a.off[v + 1];
+    const int log2s = table_log2(e - b, 1, log2cap);
+    unsigned long long rowsum = 0;
+    for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += (int64_t)BLOCK * U) {
+      int32_t j[U];
+      uint32_t lab[U], w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = p0 + (int64_t)u * BLOCK;
+        j[u] = p < e ? a.cols[p] : v;
+        w[u] = p < e ? (a.w ? a.w[p] : 1u) : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) lab[u] = j[u] != v ? (uint32_t)a.C[j[u]] : kNoLabel;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rowsum += w[u];
+        if (lab[u] != kNoLabel) global_table_add(tab, log2s, lab[u], w[u]);
+      }
+    }
+    __syncthreads();
+    unsigned long long best = 0;
+    for (int64_t s = threadIdx.x; s < ((int64_t)1 << log2s); s += BLOCK) {
+      const unsigned long long x = __hip_atomic_load(&tab[s], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+      if (x != kEmptySlot) {
+        const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
+        best = key > best ? key : best;
+        __hip_atomic_store(&tab[s], kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+    best = group_max<kWave>(best);
+    rowsum = wave_sum(rowsum);
+    if (lane == 0) {
+      bestw[wid] = best;
+      red[wid] = rowsum;
+    }
+    __syncthreads();
+    best = 0;
+    rowsum = 0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / kWave; ++k) {
+      best = bestw[k] > best ? bestw[k] : best;
+      rowsum += red[k];
+    }
+    if (threadIdx.x == 0) {
+      lc.processed += 1;
+      lc.edges += (unsigned long long)(e - b);
+      lc.overflow += rowsum >> 32 ? 1 : 0;
+    }
+    if (best) {
+      const uint32_t cstar = key_label(best);
+      if (cstar != (uint32_t)a.C[v]) {
+        if (threadIdx.x == 0) record_change(a, v, cstar, lc);
+        if (a.mark) mark_row(a, b, e, threadIdx.x, BLOCK);
+      }
+    }
+    __syncthreads();
+  }
+  flush_counts(a, lc, red);
+}
+
+// Copies the new label of every changed vertex into C, clears chg and, when
+// requested, clears the active flags consumed by the sweep.  Four vertices per
+// thread; the flag arrays are padded to a multiple of 4 bytes.
+__global__ __launch_bounds__(256) void apply_changes(int32_t *__restrict__ C,
+                                                     const int32_t *__restrict__ Cn,
+                                                     uint8_t *__restrict__ chg,
+                                                     uint8_t *__restrict__ act_clear, int64_t n) {
+  const int64_t quads = (n + 3) / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
+    uint32_t word = reinterpret_cast<uint32_t *>(chg)[q];
+    if (act_clear) reinterpret_cast<uint32_t *>(act_clear)[q] = 0u;
+    if (!word) continue;
+    reinterpret_cast<uint32_t *>(chg)[q] = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if ((word >> (8 * k)) & 0xffu) {
+        const int64_t v = 4 * q + k;
+        C[v] = Cn[v];
+      }
+  }
+}
+
+__global__ void init_labels(int32_t *C, int32_t *Cn, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    C[i] = (int32_t)i;
+    Cn[i] = (int32_t)i;
+  }
+}
+
+__global__ void fill_u64(uint64_t *p, uint64_t v, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+__global__ void fill_u8(uint8_t *p, uint8_t v, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint32_t v4 = 0x01010101u * v;
+  const int64_t words = count / 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    reinterpret_cast<uint32_t *>(p)[i] = v4;
+  for (int64_t i = words * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    p[i] = v;
+}
+
+int grid_for(int64_t items, int per_block, int cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  return (int)(g > cap ? cap : g);
+}
+
+}  // namespace
+
+hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t count,
+                             uint64_t *hub_tab, int hub_log2cap, int hub_slots, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  constexpr int kCap = 256 * 16;
+  switch (tier) {
+    case 1:
+      sweep_thread<8><<<grid_for(count, 256, kCap), 256, 0, s>>>(a, list, count);
+      break;
+    case 2:
+      sweep_group<8, 5, 256, 2><<<grid_for(count, 256 / 8, kCap), 256, 0, s>>>(a, list, count);
+      break;
+    case 3:
+      sweep_group<16, 6, 256, 2><<<grid_for(count, 256 / 16, kCap), 256, 0, s>>>(a, list, count);
+      break;
+    case 4:
+      sweep_group<32, 7, 256, 2><<<grid_for(count, 256 / 32, kCap), 256, 0, s>>>(a, list, count);
+      break;
+    case 5:
+      sweep_group<64, 8, 256, 2><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
+      break;
+    case 6:
+      sweep_group<64, 10, 256, 4><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
+      break;
+    case 7:
+      sweep_block<12, 256, 4><<<grid_for(count, 1, kCap), 256, 0, s>>>(a, list, count);
+      break;
+    case 8:
+      sweep_block<14, 1024, 4><<<grid_for(count, 1, 256 * 2), 1024, 0, s>>>(a, list, count);
+      break;
+    case kHubTier:
+      sweep_hub<1024, 4><<<grid_for(count, 1, hub_slots), 1024, 0, s>>>(
+          a, list, count, reinterpret_cast<unsigned long long *>(hub_tab), hub_log2cap);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(int32_t *C, const int32_t *Cn, uint8_t *chg, uint8_t *act_clear, int64_t n,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  apply_changes<<<grid_for((n + 3) / 4, 256, 256 * 32), 256, 0, s>>>(C, Cn, chg, act_clear, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  init_labels<<<grid_for(n, 256, 256 * 32), 256, 0, s>>>(C, Cn, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  fill_u64<<<grid_for(count, 256, 256 * 32), 256, 0, s>>>(p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  fill_u8<<<grid_for((count + 3) / 4, 256, 256 * 32), 256, 0, s>>>(p, v, count);
+  return hipGetLastError();
+}
+
+}  // namespace gsl

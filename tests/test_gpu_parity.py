@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Labels are integers computed with exact integer weight sums, so the bar is
+bit-exact equality of labels, sweep counts and per-sweep change counts.
+Modularity is compared to 1e-12 relative (both sides evaluate the same exact
+integers with the same IEEE double formula, so they agree exactly in
+practice).  Paper references: Alg. 3 / Eq. 2 (sweeps), Alg. 2 (split),
+Eq. 1 (modularity).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+from graphgen import workloads  # noqa: E402
+from tests import brute  # noqa: E402
+from tests.gpu_util import graph_hash, labels_hash, say, to_device  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "workloads.json")
+
+
+@pytest.fixture(scope="module")
+def gsl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_01261_amd as m
+    m.load()  # raises if the native library is missing: no fallback
+    return m
+
+
+def run_gpu(gsl, g, max_iters=20, tol=0.05, prune=True, split=True, weights="as-is"):
+    off, cols, w = to_device(g, weights=weights)
+    lab, st = gsl.gsl_lpa_ex(off, cols, w, max_iters, tol, prune=prune, split=split)
+    return lab.cpu().numpy(), st
+
+
+def assert_same(gsl, g, max_iters=20, tol=0.05, tag=""):
+    for split in (False, True):
+        r = oracle.lpa(g, max_iters, tol, split=split)
+        lab, st = run_gpu(gsl, g, max_iters, tol, split=split)
+        assert st["iterations"] == r.iterations, (tag, split)
+        k = min(r.iterations, 64)
+        assert list(st["changed"][:k]) == list(r.dn[:k]), (tag, split)
+        np.testing.assert_array_equal(lab, r.labels, err_msg="%s split=%s" % (tag, split))
+
+
+def test_every_graph_up_to_5_vertices(gsl):
+    for n in range(1, 6):
+        A = brute.all_graphs(n)
+        for b in range(A.shape[0]):
+            r, c = np.nonzero(A[b])
+            g = graphgen.from_entries(n, r, c)
+            assert_same(gsl, g, 20, 0.2, tag="n=%d graph=%d" % (n, b))
+
+
+def test_random_multigraphs_self_loops_duplicates_zero_weights(gsl):
+    rng = np.random.default_rng(5)
+    for trial in range(150):
+        n = int(rng.integers(1, 40))
+        m = int(rng.integers(0, 4 * n + 1))
+        edges = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(m)]
+        ws = rng.integers(0, 5, size=m)
+        g = graphgen.from_undirected(n, edges, ws)
+        assert_same(gsl, g, int(rng.choice([1, 3, 20])), float(rng.choice([0.0, 0.05, 0.3])),
+                    tag="trial %d" % trial)
+
+
+def _tier_graph(seed, weighted):
+    """Planted background plus vertices whose degrees sit on both sides of
+    every tier bound (8, 16, 32, 64, 128, 512, 2048, 8192) and two hubs."""
+    rng = np.random.default_rng(seed)
+    n = 30_000
+    base = graphgen.planted(n, 300, 0.05, n, seed)
+    rows = np.repeat(np.arange(n), np.diff(base.offsets))
+    keep = rows < base.cols
+    edges = set(zip(rows[keep].tolist(), base.cols[keep].tolist()))
+    special = []
+    for bound in (8, 16, 32, 64, 128, 512, 2048, 8192):
+        special += [bound, bound + 1]
+    special += [20_000, 29_000]
+    for k, deg in enumerate(special):
+        v = 1000 * k + 7
+        nb = rng.choice(n, size=deg + 50, replace=False)
+        nb = [int(x) for x in nb if x != v][:deg]
+        for u in nb:
+            edges.add((min(u, v), max(u, v)))
+    edges = sorted(edges)
+    ws = rng.integers(1, 9, size=len(edges)) if weighted else None
+    return graphgen.from_undirected(n, edges, ws)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_tier_boundaries_and_hubs(gsl, weighted):
+    g = _tier_graph(3 + weighted, weighted)
+    say("tier graph n=%d nnz=%d maxdeg=%d" % (g.n, g.nnz, np.diff(g.offsets).max()))
+    assert_same(gsl, g, 20, 0.05, tag="tiers")
+    assert_same(gsl, g, 20, 0.0, tag="tiers tol0")
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3, 4])
+def test_small_workloads(gsl, idx):
+    g = workloads.make(idx, small=True)
+    say("workload %d small: n=%d nnz=%d" % (idx, g.n, g.nnz))
+    assert_same(gsl, g, workloads.MAX_ITERS, workloads.TOLERANCE, tag=workloads.describe(idx, True))
+
+
+def test_batch_members(gsl):
+    b = workloads.make(5, small=True)
+    for k in range(0, b.num_graphs, 7):
+        assert_same(gsl, b.subgraph(k), tag="batch member %d" % k)
+
+
+def test_pruning_does_not_change_results(gsl):
+    for idx in (1, 3):
+        g = workloads.make(idx, small=True)
+        a, sa = run_gpu(gsl, g, prune=True)
+        b, sb = run_gpu(gsl, g, prune=False)
+        np.testing.assert_array_equal(a, b)
+        assert sa["changed"] == sb["changed"]
+        assert sum(sa["processed"]) <= sum(sb["processed"])
+
+
+def test_unit_weights_null_equals_ones(gsl):
+    g = workloads.make(1)
+    a, _ = run_gpu(gsl, g, weights="as-is")
+    b, _ = run_gpu(gsl, g, weights="ones")
+    np.testing.assert_array_equal(a, b)
+
+
+def test_deterministic_across_runs(gsl):
+    g = workloads.make(2, small=True)
+    first, _ = run_gpu(gsl, g)
+    for _ in range(3):
+        again, _ = run_gpu(gsl, g)
+        np.testing.assert_array_equal(first, again)
+
+
+def test_degenerate_graphs(gsl):
+    # one vertex, isolated vertices only, a self loop only, K2, stars
+    cases = [graphgen.from_entries(1, [], []), graphgen.from_entries(7, [], []),
+             graphgen.from_undirected(3, [(1, 1)]), graphgen.from_undirected(2, [(0, 1)]),
+             graphgen.from_undirected(11, [(0, j) for j in range(1, 11)]),
+             graphgen.cliques([3, 4, 5], perm=np.random.default_rng(1).permutation(12))]
+    for t, g in enumerate(cases):
+        assert_same(gsl, g, tag="degenerate %d" % t)
+        assert_same(gsl, g, 0, 0.05, tag="degenerate %d max_iters 0" % t)
+
+
+def test_empty_graph(gsl):
+    off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cols = torch.zeros(0, dtype=torch.int32, device="cuda")
+    lab = gsl.gsl_lpa(off, cols, None)
+    assert lab.numel() == 0
+
+
+def test_split_alone_matches_alg2(gsl):
+    rng = np.random.default_rng(8)
+    for trial in range(30):
+        g = workloads.make(1) if trial % 3 == 0 else graphgen.planted(
+            int(rng.integers(2, 3000)), int(rng.integers(1, 30)), 0.02, 500, 40 + trial)
+        C = rng.integers(0, max(1, g.n // int(rng.integers(1, 20))), size=g.n).astype(np.int32)
+        off, cols, _ = to_device(g)
+        out = gsl.gsl_split(off, cols, torch.from_numpy(C).cuda())
+        np.testing.assert_array_equal(out.cpu().numpy(), oracle.split_bfs(g, C))
+
+
+def test_split_rejects_out_of_range_labels(gsl):
+    g = graphgen.from_undirected(3, [(0, 1)])
+    off, cols, _ = to_device(g)
+    with pytest.raises(gsl.GslError) as e:
+        gsl.gsl_split(off, cols, torch.tensor([0, 1, 3], dtype=torch.int32, device="cuda"))
+    assert e.value.code == gsl.GSL_EINVAL
+
+
+def test_modularity_matches_oracle(gsl):
+    rng = np.random.default_rng(4)
+    graphs = [workloads.make(1), workloads.make(2, small=True), graphgen.cliques([5] * 7)]
+    for g in graphs:
+        for labels in (oracle.lpa(g).labels, np.arange(g.n, dtype=np.int32),
+                       np.zeros(g.n, dtype=np.int32),
+                       rng.integers(0, g.n, size=g.n).astype(np.int32)):
+            off, cols, w = to_device(g)
+            q = gsl.gsl_modularity(off, cols, w, torch.from_numpy(labels).cuda())
+            qo = oracle.modularity(g, labels)
+            assert abs(q - qo) <= 1e-12 * max(1.0, abs(qo)), (g.name, q, qo)
+
+
+def test_overflowing_weights_are_reported(gsl):
+    g = graphgen.from_undirected(3, [(0, 1), (0, 2)], [1 << 31, 1 << 31])
+    off, cols, w = to_device(g)
+    with pytest.raises(gsl.GslError) as e:
+        gsl.gsl_lpa(off, cols, w)
+    assert e.value.code == gsl.GSL_EOVERFLOW
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("no golden file")
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_full_workload_matches_oracle_hash(gsl, idx):
+    gold = _golden().get(str(idx))
+    if gold is None:
+        pytest.skip("workload %d not in golden file" % idx)
+    g = workloads.make(idx)
+    assert g.n == gold["n"] and g.nnz == gold["nnz"]
+    assert graph_hash(g) == gold["graph_xxh128"], "generator output differs from the golden graph"
+    say("workload %d: n=%d nnz=%d" % (idx, g.n, g.nnz))
+    lab, st = run_gpu(gsl, g, gold["max_iters"], gold["tolerance"])
+    assert st["iterations"] == gold["iterations"]
+    assert list(st["changed"][:st["iterations"]]) == gold["dn"]
+    assert labels_hash(lab) == gold["labels_xxh128"]
+    off, cols, w = to_device(g)
+    q = gsl.gsl_modularity(off, cols, w, torch.from_numpy(lab).cuda())
+    assert abs(q - gold["modularity"]) <= 1e-12 * max(1.0, abs(gold["modularity"]))
