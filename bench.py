@@ -1,0 +1,196 @@
+"""Benchmark: GSL-LPA (label-propagation sweeps + split) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+
+A step is one full gsl_lpa call (degree plan, synchronous sweeps with pruning
+until dN/N <= 0.05 or 20 sweeps, split) on a graph already resident in HBM.
+value = |E| / time per step, |E| = directed CSR entries (every undirected edge
+twice, as the paper counts edges after adding reverse edges).
+
+Extra objects on the JSON line:
+  roofline      the dominant sweep kernel: algorithmic bytes per launch over
+                its average launch time (HIP events on the library's stream,
+                taken over the timed steps) against the 8 TB/s HBM peak;
+                traffic = measured HBM bytes per launch from rocprofv3 counters
+                (profiles/traffic.json), null when absent or stale.
+  cpu_baseline  the CPU oracle (single thread, untuned) timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    1: "planted partition: 10,000 vertices, 100 blocks of 100, intra prob 0.1, ~2 inter edges "
+       "per vertex, unit weights",
+    2: "R-MAT scale 22 (4,194,304 vertices), edge factor 16, a/b/c/d 0.57/0.19/0.19/0.05, "
+       "symmetrised, no self loops or duplicates, uint32 weights uniform in [1,16]",
+    3: "road-like 2-D random geometric graph, 24M vertices, union-symmetrised 2 nearest "
+       "neighbours, unit weights",
+    4: "web-scale R-MAT scale 26 (67,108,864 vertices), edge factor 32, a/b/c/d "
+       "0.57/0.19/0.19/0.05, symmetrised, unit weights",
+}
+TIER_KERNEL = {1: "sweep_thread<8>", 2: "sweep_group<8,5,256,2>", 3: "sweep_group<16,6,256,2>",
+               4: "sweep_group<32,7,256,2>", 5: "sweep_group<64,8,256,2>",
+               6: "sweep_group<64,10,256,4>", 7: "sweep_block<12,256,4>",
+               8: "sweep_block<14,1024,4>", 9: "sweep_hub<1024,4>"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def tier_bytes(t: dict, weighted: bool) -> int:
+    """Algorithmic bytes a sweep kernel moves for one tier, summed over its
+    launches: per listed vertex the 4 B list entry (+1 B active flag in sparse
+    launches); per processed vertex two 8 B offsets and its own 4 B label; per
+    row entry a 4 B column, a 4 B gathered label (+4 B weight); per changed
+    vertex its 4 B new label and 1 B change flag; 1 B per neighbour flag set."""
+    listed = t["vertices"] * t["launches"]
+    return (listed * 4 + t["vertices"] * t["sparse_launches"] * 1
+            + t["processed"] * (16 + 4)
+            + t["edges"] * (8 + (4 if weighted else 0))
+            + t["changed"] * 5 + t["marked"] * 1)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2403_01261_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    entry = rec.get(workload, {}).get(kernel)
+    if not entry or entry.get("source_hash") != source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(g, max_iters, tol):
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.lpa(g, max_iters, tol)
+    dt = time.perf_counter() - t0
+    return {"value": g.nnz / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "one full oracle GSL-LPA run (sweeps + split) of the whole workload, "
+                      "single thread, %.1f s; host has %d CPUs" % (dt, os.cpu_count()),
+            "iterations": int(r.iterations)}, r
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2403_01261_amd as gsl
+    from graphgen import workloads
+
+    gsl.load()
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    g = workloads.make(args.workload)
+    log("generated %s: n=%d nnz=%d in %.1fs" % (workloads.NAMES[args.workload], g.n, g.nnz,
+                                                 time.time() - t0))
+    weighted = g.weights is not None
+    off = torch.from_numpy(g.offsets).to(dev)
+    cols = torch.from_numpy(g.cols).to(dev)
+    w = torch.from_numpy(g.weights.view(np.int32)).to(dev) if weighted else None
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    mi, tol = workloads.MAX_ITERS, workloads.TOLERANCE
+    torch.cuda.synchronize()
+
+    for k in range(args.warmup):
+        gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels)
+        log("warmup %d done" % k)
+    torch.cuda.synchronize()
+    stats = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        _, st = gsl.gsl_lpa_ex(off, cols, w, mi, tol, timing=True, out=labels)
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1000.0 * elapsed / max(args.steps, 1)
+    value = g.nnz * args.steps / elapsed
+    log("timed %d steps: %.3f ms/step, %.3g edges/s" % (args.steps, ms_per_step, value))
+
+    # Dominant sweep kernel over the timed steps.
+    ms_tier = [sum(st["tiers"][t]["ms"] for st in stats) for t in range(10)]
+    dom = max(range(1, 10), key=lambda t: ms_tier[t])
+    agg = {key: sum(st["tiers"][dom][key] for st in stats)
+           for key in ("vertices", "launches", "processed", "edges", "changed", "marked",
+                       "sparse_launches")}
+    agg["vertices"] = stats[0]["tiers"][dom]["vertices"]
+    launches = agg["launches"]
+    bytes_total = tier_bytes(agg, weighted)
+    avg_ms = ms_tier[dom] / max(launches, 1)
+    achieved = bytes_total / max(launches, 1) / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
+    kernel = TIER_KERNEL[dom]
+    wname = workloads.NAMES[args.workload]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel),
+                "kernel": kernel, "tier": dom, "launches_per_step": launches // max(args.steps, 1),
+                "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": bytes_total // max(launches, 1)}
+    # Whole sweep phase (all tier kernels + apply) for context.
+    sweep_ms = sum(st["ms_sweeps"] for st in stats) / len(stats)
+    sweep_bytes = sum(tier_bytes(dict(st["tiers"][t], vertices=st["tiers"][t]["vertices"]), weighted)
+                      for st in stats for t in range(1, 10)) / len(stats)
+    last = stats[-1]
+    phases = {"ms_plan": round(sum(s["ms_plan"] for s in stats) / len(stats), 3),
+              "ms_sweeps": round(sweep_ms, 3),
+              "ms_split": round(sum(s["ms_split"] for s in stats) / len(stats), 3),
+              "sweep_phase_GBps": round(sweep_bytes / (sweep_ms / 1000.0) / 1e9, 1) if sweep_ms else None,
+              "iterations": last["iterations"], "changed": last["changed"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        cpu, ref = cpu_baseline(g, mi, tol)
+        got = labels.cpu().numpy()
+        cpu["labels_match_gpu"] = bool(np.array_equal(got, ref.labels))
+        log("oracle: %.3g edges/s, labels match: %s" % (cpu["value"], cpu["labels_match_gpu"]))
+
+    line = {"metric": "edges/s (|E|/time) on 1 MI355X + % HBM peak", "value": value,
+            "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "%s: %s" % (wname, WORKLOAD_TEXT[args.workload]), "n": g.n,
+                       "nnz": g.nnz, "max_iters": mi, "tolerance": tol,
+                       "weights": "uint32 array" if weighted else "NULL (unit)"},
+            "roofline": roofline, "cpu_baseline": cpu, "phases": phases,
+            "context": "paper: 844M edges/s, sk-2005 3.8B edges, 2x Xeon Gold 6226R, 64 threads"}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

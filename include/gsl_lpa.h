@@ -45,6 +45,7 @@ typedef enum gsl_status {
 } gsl_status;
 
 #define GSL_STATS_MAX_ITERS 64
+#define GSL_STATS_TIERS 10
 
 typedef struct gsl_options {
   int32_t prune;  /* nonzero (default 1): pruning, Alg. 3 -- only vertices with a
@@ -68,6 +69,16 @@ typedef struct gsl_stats {
   int64_t max_degree;
   float ms_plan, ms_sweeps, ms_split, ms_total;
   float ms_sweep[GSL_STATS_MAX_ITERS];
+  /* Per degree tier (index 0 = isolated vertices, 1..9 = the sweep kernels
+   * in order of increasing degree), summed over all sweeps of the call. */
+  int64_t tier_vertices[GSL_STATS_TIERS];   /* vertices in the tier */
+  int64_t tier_launches[GSL_STATS_TIERS];   /* sweep kernel launches */
+  int64_t tier_processed[GSL_STATS_TIERS];  /* vertices scanned */
+  int64_t tier_edges[GSL_STATS_TIERS];      /* row entries scanned */
+  int64_t tier_changed[GSL_STATS_TIERS];    /* vertices that changed label */
+  int64_t tier_marked[GSL_STATS_TIERS];     /* neighbour flags written */
+  int64_t tier_sparse[GSL_STATS_TIERS];     /* launches that read the active flags */
+  float ms_tier[GSL_STATS_TIERS];           /* kernel time (timing != 0) */
 } gsl_stats;
 
 /*

@@ -19,6 +19,7 @@ __all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_split", "gsl_modularity", "gsl_converge
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgsl_lpa.so")
 STATS_MAX_ITERS = 64
+STATS_TIERS = 10
 
 GSL_OK, GSL_EINVAL, GSL_ENOMEM, GSL_EDEVICE, GSL_EOVERFLOW = 0, -1, -2, -3, -4
 
@@ -43,7 +44,15 @@ class _Stats(ctypes.Structure):
                 ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("ms_plan", ctypes.c_float), ("ms_sweeps", ctypes.c_float),
                 ("ms_split", ctypes.c_float), ("ms_total", ctypes.c_float),
-                ("ms_sweep", ctypes.c_float * STATS_MAX_ITERS)]
+                ("ms_sweep", ctypes.c_float * STATS_MAX_ITERS),
+                ("tier_vertices", ctypes.c_int64 * STATS_TIERS),
+                ("tier_launches", ctypes.c_int64 * STATS_TIERS),
+                ("tier_processed", ctypes.c_int64 * STATS_TIERS),
+                ("tier_edges", ctypes.c_int64 * STATS_TIERS),
+                ("tier_changed", ctypes.c_int64 * STATS_TIERS),
+                ("tier_marked", ctypes.c_int64 * STATS_TIERS),
+                ("tier_sparse", ctypes.c_int64 * STATS_TIERS),
+                ("ms_tier", ctypes.c_float * STATS_TIERS)]
 
 
 _lib = None
@@ -137,7 +146,12 @@ def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=
     stats = {"iterations": it, "changed": list(st.changed[:k]), "processed": list(st.processed[:k]),
              "edges": list(st.edges[:k]), "marked": list(st.marked[:k]), "nnz": st.nnz,
              "max_degree": st.max_degree, "ms_plan": st.ms_plan, "ms_sweeps": st.ms_sweeps,
-             "ms_split": st.ms_split, "ms_total": st.ms_total}
+             "ms_split": st.ms_split, "ms_total": st.ms_total, "ms_sweep": list(st.ms_sweep[:k]),
+             "tiers": [{"vertices": st.tier_vertices[t], "launches": st.tier_launches[t],
+                        "processed": st.tier_processed[t], "edges": st.tier_edges[t],
+                        "changed": st.tier_changed[t], "marked": st.tier_marked[t],
+                        "sparse_launches": st.tier_sparse[t], "ms": st.ms_tier[t]}
+                       for t in range(STATS_TIERS)]}
     return out, stats
 
 

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/gsl_lpa.h"
 #include "gsl_internal.h"
@@ -54,11 +55,28 @@ struct Scratch {
   int64_t ctr_bytes = 0;
   Counters *ctr = nullptr;
   Counters *ctr_host = nullptr;  // pinned mirror (with the per-sweep arrays)
-  uint64_t *hub_tab = nullptr;
-  int64_t hub_slots = 0;
-  int hub_log2cap = 0;
+  // hub tier layout (prefix sums over the hubs of the current graph)
+  int64_t hub_cap = 0;
+  int64_t *hub_chunk_start = nullptr, *hub_tab_start = nullptr, *hub_tchunk_start = nullptr;
+  unsigned long long *hub_best = nullptr, *hub_rowsum = nullptr;
+  unsigned long long *hub_pool = nullptr;
+  int64_t hub_pool_slots = 0;
+  bool hub_pool_dirty = false;  // a call stopped while hub tables may hold entries
+  std::vector<int64_t> h_chunk, h_tab, h_tchunk;  // host copies
+  std::vector<std::pair<int64_t, int64_t>> hub_batches;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> pool;  // per-launch timing events
 };
+
+// Returns event k of the pool, creating events on demand.
+hipEvent_t pool_event(Scratch &s, size_t k) {
+  while (s.pool.size() <= k) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s.pool.push_back(e);
+  }
+  return s.pool[k];
+}
 
 std::map<int, Scratch> g_scratch;
 
@@ -73,10 +91,16 @@ void free_scratch(Scratch &s) {
   hipFree(s.sigma);
   hipFree(s.partials);
   hipFree(s.ctr);
-  hipFree(s.hub_tab);
+  hipFree(s.hub_chunk_start);
+  hipFree(s.hub_tab_start);
+  hipFree(s.hub_tchunk_start);
+  hipFree(s.hub_best);
+  hipFree(s.hub_rowsum);
+  hipFree(s.hub_pool);
   if (s.ctr_host) hipHostFree(s.ctr_host);
   for (auto &e : s.ev)
     if (e) hipEventDestroy(e);
+  for (auto &e : s.pool) hipEventDestroy(e);
   s = Scratch();
 }
 
@@ -172,31 +196,73 @@ int run_plan(Scratch &s, const int64_t *offsets, int64_t n, hipStream_t st) {
   return GSL_OK;
 }
 
-int ensure_hub_table(Scratch &s, int64_t hubs, uint64_t max_degree, hipStream_t st) {
-  if (hubs <= 0) return GSL_OK;
-  int log2cap = 1;
-  while (((uint64_t)1 << log2cap) < 2 * max_degree) ++log2cap;
-  // One table of 2^log2cap slots per resident hub workgroup: at most 512
-  // workgroups and at most kHubTableBytes in total (at least one table).
-  constexpr int64_t kHubTableBytes = (int64_t)4 << 30;
-  int64_t slots = hubs < 512 ? hubs : 512;
-  const int64_t fit = kHubTableBytes / ((int64_t)sizeof(uint64_t) << log2cap);
-  if (slots > fit) slots = fit > 0 ? fit : 1;
-  if (log2cap > s.hub_log2cap || slots > s.hub_slots) {
-    hipFree(s.hub_tab);
-    s.hub_tab = nullptr;
-    const int lc = log2cap > s.hub_log2cap ? log2cap : s.hub_log2cap;
-    const int64_t sl = slots > s.hub_slots ? slots : s.hub_slots;
-    const int64_t words = sl << lc;
-    if (dmalloc(&s.hub_tab, words) != hipSuccess) {
+// Builds the hub layout of the current graph and splits the hubs into
+// batches whose global tables fit in the pool (kHubPoolBytes, or the largest
+// single table if that is bigger).
+int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_t H, hipStream_t st) {
+  s.hub_batches.clear();
+  if (H <= 0) return GSL_OK;
+  if (H > s.hub_cap) {
+    hipFree(s.hub_chunk_start);
+    hipFree(s.hub_tab_start);
+    hipFree(s.hub_tchunk_start);
+    hipFree(s.hub_best);
+    hipFree(s.hub_rowsum);
+    s.hub_chunk_start = s.hub_tab_start = s.hub_tchunk_start = nullptr;
+    s.hub_best = s.hub_rowsum = nullptr;
+    s.hub_cap = 0;
+    if (dmalloc(&s.hub_chunk_start, H + 1) != hipSuccess || dmalloc(&s.hub_tab_start, H + 1) != hipSuccess ||
+        dmalloc(&s.hub_tchunk_start, H + 1) != hipSuccess || dmalloc(&s.hub_best, H) != hipSuccess ||
+        dmalloc(&s.hub_rowsum, H) != hipSuccess) {
       (void)hipGetLastError();
-      s.hub_log2cap = 0;
-      s.hub_slots = 0;
-      return fail(GSL_ENOMEM, "hub table allocation (%lld slots) failed", (long long)words);
+      return fail(GSL_ENOMEM, "hub layout allocation failed");
     }
-    HIP_TRY(gsl::launch_fill_u64(s.hub_tab, 0xFFFFFFFF00000000ull, words, st));
-    s.hub_log2cap = lc;
-    s.hub_slots = sl;
+    s.hub_cap = H;
+  }
+  HIP_TRY(hipMemsetAsync(s.hub_best, 0, (size_t)H * sizeof(unsigned long long), st));
+  HIP_TRY(hipMemsetAsync(s.hub_rowsum, 0, (size_t)H * sizeof(unsigned long long), st));
+  HIP_TRY(gsl::launch_hub_layout(offsets, hubs, H, s.hub_chunk_start, s.hub_tab_start,
+                                 s.hub_tchunk_start, st));
+  s.h_chunk.resize((size_t)H + 1);
+  s.h_tab.resize((size_t)H + 1);
+  s.h_tchunk.resize((size_t)H + 1);
+  HIP_TRY(hipMemcpyAsync(s.h_chunk.data(), s.hub_chunk_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s.h_tab.data(), s.hub_tab_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s.h_tchunk.data(), s.hub_tchunk_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  constexpr int64_t kHubPoolBytes = (int64_t)2 << 30;
+  int64_t cap = kHubPoolBytes / 8, need = 0;
+  for (int64_t k = 0; k < H; ++k) {
+    const int64_t sz = s.h_tab[(size_t)k + 1] - s.h_tab[(size_t)k];
+    if (sz > cap) cap = sz;
+  }
+  int64_t k0 = 0;
+  for (int64_t k = 0; k < H; ++k) {
+    if (s.h_tab[(size_t)k + 1] - s.h_tab[(size_t)k0] > cap) {
+      s.hub_batches.push_back({k0, k});
+      k0 = k;
+    }
+  }
+  s.hub_batches.push_back({k0, H});
+  for (auto &bt : s.hub_batches) {
+    const int64_t sz = s.h_tab[(size_t)bt.second] - s.h_tab[(size_t)bt.first];
+    if (sz > need) need = sz;
+  }
+  if (s.hub_pool_dirty && s.hub_pool) {
+    HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_pool), 0xFFFFFFFF00000000ull,
+                                 s.hub_pool_slots, st));
+    s.hub_pool_dirty = false;
+  }
+  if (need > s.hub_pool_slots) {
+    hipFree(s.hub_pool);
+    s.hub_pool = nullptr;
+    s.hub_pool_slots = 0;
+    if (dmalloc(&s.hub_pool, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "hub table pool (%lld slots) allocation failed", (long long)need);
+    }
+    HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_pool), 0xFFFFFFFF00000000ull, need, st));
+    s.hub_pool_slots = need;
   }
   return GSL_OK;
 }
@@ -233,7 +299,8 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
   if ((rc = run_plan(s, offsets, n, st))) return rc;
   Counters plan = *s.ctr_host;
-  if ((rc = ensure_hub_table(s, plan.tier_count[gsl::kHubTier], plan.max_degree, st))) return rc;
+  const int32_t *hub_list = s.list + (plan.tier_start[gsl::kHubTier] - plan.tier_start[1]);
+  if ((rc = prepare_hubs(s, offsets, hub_list, plan.tier_count[gsl::kHubTier], st))) return rc;
   const int64_t limit = gsl_convergence_limit(n, tolerance);
   int32_t *C = labels_out;
   HIP_TRY(gsl::launch_init_labels(C, s.Cn, n, st));
@@ -249,6 +316,18 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   bool marked_prev = false;
   int64_t dn_prev = n;
   int overflow = 0;
+  // Timing events: per sweep (start, end) and per tier launch (start, end).
+  struct Launch { int tier; size_t ev; };
+  std::vector<Launch> launches;
+  std::vector<size_t> sweep_ev;
+  size_t nev = 0;
+  int64_t tier_launches[gsl::kNumTiers] = {0}, tier_sparse[gsl::kNumTiers] = {0};
+  auto rec = [&](size_t k) -> int {
+    hipEvent_t e = pool_event(s, k);
+    if (!e) return fail(GSL_EDEVICE, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(e, st));
+    return GSL_OK;
+  };
   while (it < max_iters) {
     // Pruning: sweep `it` processes only flagged vertices if the previous
     // sweep marked; this sweep marks if the previous one changed few vertices
@@ -270,19 +349,41 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
     a.processed = pr_arr + it;
     a.edges = ed_arr + it;
     a.overflow = reinterpret_cast<unsigned long long *>(&s.ctr->overflow);
+    if (o.timing) {
+      sweep_ev.push_back(nev);
+      if ((rc = rec(nev++))) return rc;
+    }
     for (int t = 1; t < gsl::kNumTiers; ++t) {
       const int64_t cnt = plan.tier_count[t];
       if (cnt <= 0) continue;
       const int32_t *l = s.list + (plan.tier_start[t] - plan.tier_start[1]);
-      HIP_TRY(gsl::launch_sweep_tier(t, a, l, cnt, s.hub_tab, s.hub_log2cap, (int)s.hub_slots, st));
+      a.tier = &s.ctr->tier_stats[t][0];
+      if (o.timing) {
+        launches.push_back({t, nev});
+        if ((rc = rec(nev++))) return rc;
+      }
+      if (t == gsl::kHubTier) {
+        s.hub_pool_dirty = true;
+        for (auto &bt : s.hub_batches)
+          HIP_TRY(gsl::launch_hub_sweep(a, l, s.hub_chunk_start, s.hub_tab_start, s.hub_tchunk_start,
+                                        s.h_chunk.data(), s.h_tchunk.data(), s.hub_pool, s.hub_best,
+                                        s.hub_rowsum, bt.first, bt.second, st));
+      } else {
+        HIP_TRY(gsl::launch_sweep_tier(t, a, l, cnt, st));
+      }
+      if (o.timing && (rc = rec(nev++))) return rc;
+      tier_launches[t] += 1;
+      tier_sparse[t] += dense ? 0 : 1;
     }
     HIP_TRY(gsl::launch_apply(C, s.Cn, s.chg, dense ? nullptr : s.act[it & 1], n, st));
+    if (o.timing && (rc = rec(nev++))) return rc;
     unsigned long long dn_host[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(&dn_host[0], dn_arr + it, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(&dn_host[1], &s.ctr->overflow, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (stats && it < GSL_STATS_MAX_ITERS) stats->marked[it] = mark ? 1 : 0;
     ++it;
+    s.hub_pool_dirty = false;  // every hub table was cleared by the sweep that just finished
     if (dn_host[1]) {
       overflow = 1;
       break;
@@ -315,11 +416,25 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
       stats->processed[k] = (int64_t)hp[k];
       stats->edges[k] = (int64_t)he[k];
     }
+    for (int t = 0; t < gsl::kNumTiers; ++t) {
+      stats->tier_vertices[t] = plan.tier_count[t];
+      stats->tier_launches[t] = tier_launches[t];
+      stats->tier_sparse[t] = tier_sparse[t];
+      stats->tier_processed[t] = (int64_t)s.ctr_host->tier_stats[t][0];
+      stats->tier_edges[t] = (int64_t)s.ctr_host->tier_stats[t][1];
+      stats->tier_changed[t] = (int64_t)s.ctr_host->tier_stats[t][2];
+      stats->tier_marked[t] = (int64_t)s.ctr_host->tier_stats[t][3];
+    }
     if (o.timing) {
       stats->ms_plan = elapsed(s.ev[0], s.ev[1]);
       stats->ms_sweeps = elapsed(s.ev[1], s.ev[2]);
       stats->ms_split = elapsed(s.ev[2], s.ev[3]);
       stats->ms_total = elapsed(s.ev[0], s.ev[3]);
+      for (const Launch &l : launches) stats->ms_tier[l.tier] += elapsed(s.pool[l.ev], s.pool[l.ev + 1]);
+      for (size_t k = 0; k < sweep_ev.size() && k < GSL_STATS_MAX_ITERS; ++k) {
+        const size_t end = k + 1 < sweep_ev.size() ? sweep_ev[k + 1] - 1 : nev - 1;
+        stats->ms_sweep[k] = elapsed(s.pool[sweep_ev[k]], s.pool[end]);
+      }
     }
   }
   return GSL_OK;

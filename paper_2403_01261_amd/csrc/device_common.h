@@ -64,6 +64,26 @@ __device__ __forceinline__ void lds_table_add(unsigned long long *tab, int log2s
   }
 }
 
+// Adds (label, w) to an LDS table with a compare-and-swap first: returns the
+// slot index if this call claimed a new slot for `label`, -1 if the label was
+// already present (its weight was added).  The table must keep a free slot
+// for every distinct label inserted.
+__device__ __forceinline__ int lds_insert(unsigned long long *tab, int log2s, uint32_t label,
+                                          uint32_t w) {
+  const uint32_t mask = (1u << log2s) - 1u;
+  uint32_t h = slot_hash(label, log2s);
+  const unsigned long long mine = ((unsigned long long)label << 32) | w;
+  for (;;) {
+    const unsigned long long prev = atomicCAS(&tab[h], kEmptySlot, mine);
+    if (prev == kEmptySlot) return (int)h;
+    if ((uint32_t)(prev >> 32) == label) {
+      atomicAdd(&tab[h], (unsigned long long)w);
+      return -1;
+    }
+    h = (h + 1u) & mask;
+  }
+}
+
 // Same on a global-memory table private to one workgroup: workgroup-scope
 // atomics (performed in the L2 of the workgroup's XCD).
 __device__ __forceinline__ void global_table_add(unsigned long long *tab, int log2s, uint32_t label,
@@ -136,7 +156,7 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long x,
 
 // Per-thread sweep counters, reduced once per block at kernel end.
 struct LocalCounts {
-  unsigned long long dn = 0, processed = 0, edges = 0, overflow = 0;
+  unsigned long long dn = 0, processed = 0, edges = 0, overflow = 0, marked = 0;
 };
 
 }  // namespace gsl

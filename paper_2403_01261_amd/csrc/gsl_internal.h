@@ -33,14 +33,9 @@ struct Counters {
   uint64_t s2_lo, s2_hi;
   double q;
   uint64_t pad[3];
+  // per tier, summed over sweeps: processed, edges, changed, marked
+  unsigned long long tier_stats[kNumTiers][4];
   // followed by per-sweep arrays dn[max_iters], processed[], edges[]
-};
-
-// Per-sweep counter triple location inside the counters block.
-struct SweepCounters {
-  unsigned long long *dn;
-  unsigned long long *processed;
-  unsigned long long *edges;
 };
 
 // Arguments common to every sweep kernel.
@@ -56,6 +51,7 @@ struct SweepArgs {
   int dense;              // process every listed vertex
   int mark;               // mark neighbours of changed vertices in nact
   unsigned long long *dn, *processed, *edges, *overflow;
+  unsigned long long *tier;  // this tier's [processed, edges, changed, marked]
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----
@@ -64,7 +60,14 @@ hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *bl
 int64_t plan_blocks(int64_t n);
 
 hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t count,
-                             uint64_t *hub_tab, int hub_log2cap, int hub_slots, hipStream_t s);
+                             hipStream_t s);
+hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, int64_t *chunk_start,
+                             int64_t *tab_start, int64_t *tchunk_start, hipStream_t s);
+hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, const int64_t *chunk_start,
+                            const int64_t *tab_start, const int64_t *tchunk_start,
+                            const int64_t *chunk_start_h, const int64_t *tchunk_start_h,
+                            unsigned long long *tab, unsigned long long *best,
+                            unsigned long long *rowsum, int64_t k0, int64_t k1, hipStream_t s);
 hipError_t launch_apply(int32_t *C, const int32_t *Cn, uint8_t *chg, uint8_t *act_clear,
                         int64_t n, hipStream_t s);
 hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s);

@@ -31,24 +31,27 @@ __device__ __forceinline__ void record_change(const SweepArgs &a, int32_t v, uin
   lc.dn += 1;
 }
 
-__device__ __forceinline__ void mark_row(const SweepArgs &a, int64_t b, int64_t e, int64_t first,
-                                         int64_t step) {
-  for (int64_t p = b + first; p < e; p += step) {
-    const int32_t j = a.cols[p];
-    if (!a.nact[j]) a.nact[j] = 1;
-  }
-}
-
 __device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCounts &lc,
                                              unsigned long long *red) {
   const unsigned long long dn = block_sum(lc.dn, red);
   const unsigned long long pr = block_sum(lc.processed, red);
   const unsigned long long ed = block_sum(lc.edges, red);
   const unsigned long long ov = block_sum(lc.overflow, red);
+  const unsigned long long mk = block_sum(lc.marked, red);
   if (threadIdx.x == 0) {
-    if (dn) atomicAdd(a.dn, dn);
-    if (pr) atomicAdd(a.processed, pr);
-    if (ed) atomicAdd(a.edges, ed);
+    if (dn) {
+      atomicAdd(a.dn, dn);
+      atomicAdd(a.tier + 2, dn);
+    }
+    if (pr) {
+      atomicAdd(a.processed, pr);
+      atomicAdd(a.tier + 0, pr);
+    }
+    if (ed) {
+      atomicAdd(a.edges, ed);
+      atomicAdd(a.tier + 1, ed);
+    }
+    if (mk) atomicAdd(a.tier + 3, mk);
     if (ov) atomicAdd(a.overflow, ov);
   }
 }
@@ -100,7 +103,10 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
         if (a.mark)
 #pragma unroll
           for (int k = 0; k < D; ++k)
-            if (k < d && !a.nact[col[k]]) a.nact[col[k]] = 1;
+            if (k < d) {
+              if (!a.nact[col[k]]) a.nact[col[k]] = 1;
+              lc.marked += 1;
+            }
       }
     }
   }
@@ -108,17 +114,24 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
 }
 
 // ---------------------------------------------------------------------------
-// Tiers 2-6: a group of G lanes (G <= 64, inside one wavefront) per vertex,
-// with a private LDS table of 2^LOG2S slots per group.  All groups of a block
-// move through insert / scan phases together, separated by block barriers.
+// Tiers 2-8: a group of G lanes per vertex -- a slice of a wavefront (G <= 64)
+// or the whole workgroup (G == BLOCK) -- with a private LDS table of up to
+// 2^LOG2S slots.  Every lane owns at most K row entries (the tier bound is
+// G * K), loads them all before inserting, and remembers the slots it
+// claimed: after the barrier the claimers read the final sums of their own
+// slots (the argmax candidates) and clear them, so no lane scans empty slots.
+// All groups of a block move through the insert / read phases together.
 // ---------------------------------------------------------------------------
-template <int G, int LOG2S, int BLOCK, int U>
-__global__ __launch_bounds__(BLOCK) void sweep_group(SweepArgs a, const int32_t *__restrict__ list,
-                                                     int64_t count) {
+template <int G, int LOG2S, int BLOCK, int K>
+__global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *__restrict__ list,
+                                                   int64_t count) {
+  static_assert(G <= 64 || G == BLOCK, "group is a wave slice or the block");
   constexpr int GPB = BLOCK / G;
   constexpr int S = 1 << LOG2S;
+  constexpr int NW = BLOCK / kWave;
   __shared__ unsigned long long tab[GPB * S];
-  __shared__ unsigned long long red[BLOCK / kWave];
+  __shared__ unsigned long long red[NW];
+  __shared__ unsigned long long red2[NW];
   for (int s = threadIdx.x; s < GPB * S; s += BLOCK) tab[s] = kEmptySlot;
   __syncthreads();
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
@@ -127,51 +140,64 @@ __global__ __launch_bounds__(BLOCK) void sweep_group(SweepArgs a, const int32_t 
   for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
     const int64_t idx = base + g;
     int32_t v = -1;
-    int64_t b = 0, e = 0;
-    int log2s = 1;
     if (idx < count) {
       v = list[idx];
       if (!a.dense && !a.act[v]) v = -1;
-      if (v >= 0) {
-        b = a.off[v];
-        e = a.off[v + 1];
-        log2s = table_log2(e - b, 1, LOG2S);
-      }
     }
-    unsigned long long rowsum = 0;
+    int64_t b = 0, e = 0;
+    int log2s = 1;
     if (v >= 0) {
-      for (int64_t p0 = b + lane; p0 < e; p0 += (int64_t)G * U) {
-        int32_t j[U];
-        uint32_t lab[U], w[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t p = p0 + (int64_t)u * G;
-          j[u] = p < e ? a.cols[p] : v;
-          w[u] = p < e ? (a.w ? a.w[p] : 1u) : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) lab[u] = j[u] != v ? (uint32_t)a.C[j[u]] : kNoLabel;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          rowsum += w[u];
-          if (lab[u] != kNoLabel) lds_table_add(T, log2s, lab[u], w[u]);
-        }
-      }
+      b = a.off[v];
+      e = a.off[v + 1];
+      log2s = table_log2(e - b, 1, LOG2S);
     }
+    int32_t j[K];
+    uint32_t wt[K], lab[K];
+    int slot[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t p = b + lane + (int64_t)k * G;
+      const bool in = p < e;
+      j[k] = in ? a.cols[p] : -1;
+      wt[k] = in ? (a.w ? a.w[p] : 1u) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) lab[k] = (j[k] >= 0 && j[k] != v) ? (uint32_t)a.C[j[k]] : kNoLabel;
+    unsigned long long rowsum = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) rowsum += wt[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) slot[k] = lab[k] != kNoLabel ? lds_insert(T, log2s, lab[k], wt[k]) : -1;
     __syncthreads();
     unsigned long long best = 0;
-    if (v >= 0) {
-      for (int s = lane; s < (1 << log2s); s += G) {
-        const unsigned long long x = T[s];
-        if (x != kEmptySlot) {
-          const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
-          best = key > best ? key : best;
-          T[s] = kEmptySlot;
-        }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (slot[k] >= 0) {
+        const unsigned long long x = T[slot[k]];
+        const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
+        best = key > best ? key : best;
+        T[slot[k]] = kEmptySlot;
       }
     }
-    best = group_max<G>(best);
-    rowsum = group_sum<G>(rowsum);
+    if constexpr (G <= 64) {
+      best = group_max<G>(best);
+      rowsum = group_sum<G>(rowsum);
+    } else {
+      best = group_max<kWave>(best);
+      rowsum = wave_sum(rowsum);
+      if (threadIdx.x % kWave == 0) {
+        red[threadIdx.x / kWave] = best;
+        red2[threadIdx.x / kWave] = rowsum;
+      }
+      __syncthreads();
+      best = 0;
+      rowsum = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        best = red[w] > best ? red[w] : best;
+        rowsum += red2[w];
+      }
+    }
     if (v >= 0) {
       if (lane == 0) {
         lc.processed += 1;
@@ -182,165 +208,15 @@ __global__ __launch_bounds__(BLOCK) void sweep_group(SweepArgs a, const int32_t 
         const uint32_t cstar = key_label(best);
         if (cstar != (uint32_t)a.C[v]) {
           if (lane == 0) record_change(a, v, cstar, lc);
-          if (a.mark) mark_row(a, b, e, lane, G);
+          if (a.mark) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+              if (j[k] >= 0) {
+                if (!a.nact[j[k]]) a.nact[j[k]] = 1;
+                lc.marked += 1;
+              }
+          }
         }
-      }
-    }
-    __syncthreads();
-  }
-  flush_counts(a, lc, red);
-}
-
-// ---------------------------------------------------------------------------
-// Tiers 7, 8: one workgroup per vertex, LDS table of up to 2^LOG2S slots.
-// ---------------------------------------------------------------------------
-template <int LOG2S, int BLOCK, int U>
-__global__ __launch_bounds__(BLOCK) void sweep_block(SweepArgs a, const int32_t *__restrict__ list,
-                                                     int64_t count) {
-  constexpr int S = 1 << LOG2S;
-  __shared__ unsigned long long tab[S];
-  __shared__ unsigned long long red[BLOCK / kWave];
-  __shared__ unsigned long long bestw[BLOCK / kWave];
-  for (int s = threadIdx.x; s < S; s += BLOCK) tab[s] = kEmptySlot;
-  __syncthreads();
-  LocalCounts lc;
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
-    const int32_t v = list[idx];
-    if (!a.dense && !a.act[v]) continue;  // uniform across the block
-    const int64_t b = a.off[v], e = a.off[v + 1];
-    const int log2s = table_log2(e - b, 1, LOG2S);
-    unsigned long long rowsum = 0;
-    for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += (int64_t)BLOCK * U) {
-      int32_t j[U];
-      uint32_t lab[U], w[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t p = p0 + (int64_t)u * BLOCK;
-        j[u] = p < e ? a.cols[p] : v;
-        w[u] = p < e ? (a.w ? a.w[p] : 1u) : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) lab[u] = j[u] != v ? (uint32_t)a.C[j[u]] : kNoLabel;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        rowsum += w[u];
-        if (lab[u] != kNoLabel) lds_table_add(tab, log2s, lab[u], w[u]);
-      }
-    }
-    __syncthreads();
-    unsigned long long best = 0;
-    for (int s = threadIdx.x; s < (1 << log2s); s += BLOCK) {
-      const unsigned long long x = tab[s];
-      if (x != kEmptySlot) {
-        const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
-        best = key > best ? key : best;
-        tab[s] = kEmptySlot;
-      }
-    }
-    best = group_max<kWave>(best);
-    rowsum = wave_sum(rowsum);
-    if (lane == 0) {
-      bestw[wid] = best;
-      red[wid] = rowsum;
-    }
-    __syncthreads();
-    best = 0;
-    rowsum = 0;
-#pragma unroll
-    for (int k = 0; k < BLOCK / kWave; ++k) {
-      best = bestw[k] > best ? bestw[k] : best;
-      rowsum += red[k];
-    }
-    if (threadIdx.x == 0) {
-      lc.processed += 1;
-      lc.edges += (unsigned long long)(e - b);
-      lc.overflow += rowsum >> 32 ? 1 : 0;
-    }
-    if (best) {
-      const uint32_t cstar = key_label(best);
-      if (cstar != (uint32_t)a.C[v]) {
-        if (threadIdx.x == 0) record_change(a, v, cstar, lc);
-        if (a.mark) mark_row(a, b, e, threadIdx.x, BLOCK);
-      }
-    }
-    __syncthreads();
-  }
-  flush_counts(a, lc, red);
-}
-
-// ---------------------------------------------------------------------------
-// Tier 9 (hubs): one workgroup per vertex; the table lives in global memory,
-// one region of 2^log2cap slots per resident workgroup, kept all-empty
-// between vertices.
-// ---------------------------------------------------------------------------
-template <int BLOCK, int U>
-__global__ __launch_bounds__(BLOCK) void sweep_hub(SweepArgs a, const int32_t *__restrict__ list,
-                                                   int64_t count, unsigned long long *hub_tab,
-                                                   int log2cap) {
-  __shared__ unsigned long long red[BLOCK / kWave];
-  __shared__ unsigned long long bestw[BLOCK / kWave];
-  unsigned long long *tab = hub_tab + ((size_t)blockIdx.x << log2cap);
-  LocalCounts lc;
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
-    const int32_t v = list[idx];
-    if (!a.dense && !a.act[v]) continue;
-    const int64_t b = a.off[v], e = a.off[v + 1];
-    const int log2s = table_log2(e - b, 1, log2cap);
-    unsigned long long rowsum = 0;
-    for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += (int64_t)BLOCK * U) {
-      int32_t j[U];
-      uint32_t lab[U], w[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t p = p0 + (int64_t)u * BLOCK;
-        j[u] = p < e ? a.cols[p] : v;
-        w[u] = p < e ? (a.w ? a.w[p] : 1u) : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) lab[u] = j[u] != v ? (uint32_t)a.C[j[u]] : kNoLabel;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        rowsum += w[u];
-        if (lab[u] != kNoLabel) global_table_add(tab, log2s, lab[u], w[u]);
-      }
-    }
-    __syncthreads();
-    unsigned long long best = 0;
-    for (int64_t s = threadIdx.x; s < ((int64_t)1 << log2s); s += BLOCK) {
-      const unsigned long long x = __hip_atomic_load(&tab[s], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-      if (x != kEmptySlot) {
-        const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
-        best = key > best ? key : best;
-        __hip_atomic_store(&tab[s], kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    }
-    best = group_max<kWave>(best);
-    rowsum = wave_sum(rowsum);
-    if (lane == 0) {
-      bestw[wid] = best;
-      red[wid] = rowsum;
-    }
-    __syncthreads();
-    best = 0;
-    rowsum = 0;
-#pragma unroll
-    for (int k = 0; k < BLOCK / kWave; ++k) {
-      best = bestw[k] > best ? bestw[k] : best;
-      rowsum += red[k];
-    }
-    if (threadIdx.x == 0) {
-      lc.processed += 1;
-      lc.edges += (unsigned long long)(e - b);
-      lc.overflow += rowsum >> 32 ? 1 : 0;
-    }
-    if (best) {
-      const uint32_t cstar = key_label(best);
-      if (cstar != (uint32_t)a.C[v]) {
-        if (threadIdx.x == 0) record_change(a, v, cstar, lc);
-        if (a.mark) mark_row(a, b, e, threadIdx.x, BLOCK);
       }
     }
     __syncthreads();
@@ -403,7 +279,7 @@ int grid_for(int64_t items, int per_block, int cap) {
 }  // namespace
 
 hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t count,
-                             uint64_t *hub_tab, int hub_log2cap, int hub_slots, hipStream_t s) {
+                             hipStream_t s) {
   if (count <= 0) return hipSuccess;
   constexpr int kCap = 256 * 16;
   switch (tier) {
@@ -411,29 +287,25 @@ hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, 
       sweep_thread<8><<<grid_for(count, 256, kCap), 256, 0, s>>>(a, list, count);
       break;
     case 2:
-      sweep_group<8, 5, 256, 2><<<grid_for(count, 256 / 8, kCap), 256, 0, s>>>(a, list, count);
+      sweep_lds<8, 5, 256, 2><<<grid_for(count, 256 / 8, kCap), 256, 0, s>>>(a, list, count);
       break;
     case 3:
-      sweep_group<16, 6, 256, 2><<<grid_for(count, 256 / 16, kCap), 256, 0, s>>>(a, list, count);
+      sweep_lds<16, 6, 256, 2><<<grid_for(count, 256 / 16, kCap), 256, 0, s>>>(a, list, count);
       break;
     case 4:
-      sweep_group<32, 7, 256, 2><<<grid_for(count, 256 / 32, kCap), 256, 0, s>>>(a, list, count);
+      sweep_lds<32, 7, 256, 2><<<grid_for(count, 256 / 32, kCap), 256, 0, s>>>(a, list, count);
       break;
     case 5:
-      sweep_group<64, 8, 256, 2><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
+      sweep_lds<64, 8, 256, 2><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
       break;
     case 6:
-      sweep_group<64, 10, 256, 4><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
+      sweep_lds<64, 10, 256, 8><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
       break;
     case 7:
-      sweep_block<12, 256, 4><<<grid_for(count, 1, kCap), 256, 0, s>>>(a, list, count);
+      sweep_lds<256, 12, 256, 8><<<grid_for(count, 1, kCap), 256, 0, s>>>(a, list, count);
       break;
     case 8:
-      sweep_block<14, 1024, 4><<<grid_for(count, 1, 256 * 2), 1024, 0, s>>>(a, list, count);
-      break;
-    case kHubTier:
-      sweep_hub<1024, 4><<<grid_for(count, 1, hub_slots), 1024, 0, s>>>(
-          a, list, count, reinterpret_cast<unsigned long long *>(hub_tab), hub_log2cap);
+      sweep_lds<1024, 14, 1024, 8><<<grid_for(count, 1, 256 * 2), 1024, 0, s>>>(a, list, count);
       break;
     default:
       return hipErrorInvalidValue;
