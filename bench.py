@@ -169,6 +169,8 @@ def main(argv=None):
               "ms_sweeps": round(sweep_ms, 3),
               "ms_split": round(sum(s["ms_split"] for s in stats) / len(stats), 3),
               "sweep_phase_GBps": round(sweep_bytes / (sweep_ms / 1000.0) / 1e9, 1) if sweep_ms else None,
+              "ms_reorder": round(sum(s["ms_reorder"] for s in stats) / len(stats), 3),
+              "renumbered": last["renumbered"],
               "iterations": last["iterations"], "changed": last["changed"]}
 
     cpu = None

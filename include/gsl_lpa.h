@@ -55,7 +55,11 @@ typedef struct gsl_options {
                      sweeps, as GSL-LPA does; 0 returns the raw LPA labels. */
   int32_t timing; /* nonzero: fill the ms_* fields of gsl_stats (records HIP
                      events between phases). */
-  int32_t reserved;
+  int32_t layout; /* 0 (default): automatic; 1: always sweep a degree-ordered
+                     renumbered copy of the graph (hubs first), which packs
+                     the labels of high-degree vertices together; 2: never.
+                     The copy costs nnz * 4 (+ nnz * 4 with weights) bytes of
+                     device memory.  Results are identical either way. */
 } gsl_options;
 
 typedef struct gsl_stats {
@@ -78,6 +82,8 @@ typedef struct gsl_stats {
   int64_t tier_changed[GSL_STATS_TIERS];    /* vertices that changed label */
   int64_t tier_marked[GSL_STATS_TIERS];     /* neighbour flags written */
   int64_t tier_sparse[GSL_STATS_TIERS];     /* launches that read the active flags */
+  int32_t renumbered;                       /* 1 if the sweeps ran on the renumbered copy */
+  float ms_reorder;                         /* time to build that copy (timing != 0) */
   float ms_tier[GSL_STATS_TIERS];           /* kernel time (timing != 0) */
 } gsl_stats;
 
@@ -106,7 +112,7 @@ int gsl_lpa(const int64_t *offsets, const int32_t *cols, const uint32_t *weights
             int32_t max_iters, double tolerance, int32_t *labels_out);
 
 /*
- * gsl_lpa_ex -- gsl_lpa with options (NULL: defaults {1, 1, 0}) and optional
+ * gsl_lpa_ex -- gsl_lpa with options (NULL: defaults {1, 1, 0, 0}) and optional
  * statistics (stats may be NULL; per-sweep arrays hold the first
  * GSL_STATS_MAX_ITERS sweeps).
  */

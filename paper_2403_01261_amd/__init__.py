@@ -32,7 +32,7 @@ class GslError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("prune", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -52,6 +52,7 @@ class _Stats(ctypes.Structure):
                 ("tier_changed", ctypes.c_int64 * STATS_TIERS),
                 ("tier_marked", ctypes.c_int64 * STATS_TIERS),
                 ("tier_sparse", ctypes.c_int64 * STATS_TIERS),
+                ("renumbered", ctypes.c_int32), ("ms_reorder", ctypes.c_float),
                 ("ms_tier", ctypes.c_float * STATS_TIERS)]
 
 
@@ -127,9 +128,13 @@ def gsl_lpa(offsets, cols, weights=None, max_iters=20, tolerance=0.05, out=None)
     return labels
 
 
+LAYOUTS = {"auto": 0, "renumbered": 1, "original": 2}
+
+
 def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=True, split=True,
-               timing=False, out=None):
-    """Returns (labels, stats dict)."""
+               timing=False, layout="auto", out=None):
+    """Returns (labels, stats dict).  layout: "auto", "renumbered" or
+    "original" (which vertex order the sweeps run in; results are identical)."""
     lib = _bind_stream()
     po, pc, pw, n = _graph_args(offsets, cols, weights)
     if out is None:
@@ -137,7 +142,7 @@ def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=
     if out.numel() != n:
         raise ValueError("out must hold n labels")
     pl = _dev(out, (torch.int32,), "out")
-    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), 0)
+    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), LAYOUTS[layout])
     st = _Stats()
     _check(lib.gsl_lpa_ex(po, pc, pw, n, int(max_iters), float(tolerance), ctypes.byref(opt),
                           ctypes.byref(st), pl))
@@ -147,6 +152,7 @@ def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=
              "edges": list(st.edges[:k]), "marked": list(st.marked[:k]), "nnz": st.nnz,
              "max_degree": st.max_degree, "ms_plan": st.ms_plan, "ms_sweeps": st.ms_sweeps,
              "ms_split": st.ms_split, "ms_total": st.ms_total, "ms_sweep": list(st.ms_sweep[:k]),
+             "renumbered": bool(st.renumbered), "ms_reorder": st.ms_reorder,
              "tiers": [{"vertices": st.tier_vertices[t], "launches": st.tier_launches[t],
                         "processed": st.tier_processed[t], "edges": st.tier_edges[t],
                         "changed": st.tier_changed[t], "marked": st.tier_marked[t],

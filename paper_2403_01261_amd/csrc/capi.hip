@@ -52,6 +52,7 @@ struct Scratch {
   unsigned long long *sigma = nullptr;
   unsigned long long *partials = nullptr;
   int partial_blocks = 0;
+  unsigned long long *tier_part = nullptr;  // per-block count records of the tier kernels
   int64_t ctr_bytes = 0;
   Counters *ctr = nullptr;
   Counters *ctr_host = nullptr;  // pinned mirror (with the per-sweep arrays)
@@ -65,7 +66,16 @@ struct Scratch {
   std::vector<int64_t> h_chunk, h_tab, h_tchunk;  // host copies
   std::vector<std::pair<int64_t, int64_t>> hub_batches;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_reorder = nullptr;
   std::vector<hipEvent_t> pool;  // per-launch timing events
+  // degree-ordered renumbered copy of the graph
+  int32_t *old2new = nullptr, *lab2 = nullptr, *minorig = nullptr;
+  unsigned long long *first_key = nullptr;
+  int64_t *off2 = nullptr;
+  int64_t copy_n_cap = -1, copy_nnz_cap = -1;
+  int32_t *cols2 = nullptr;
+  uint32_t *w2 = nullptr;
+  bool w2_ok = false;
 };
 
 // Returns event k of the pool, creating events on demand.
@@ -90,6 +100,7 @@ void free_scratch(Scratch &s) {
   hipFree(s.blk_counts);
   hipFree(s.sigma);
   hipFree(s.partials);
+  hipFree(s.tier_part);
   hipFree(s.ctr);
   hipFree(s.hub_chunk_start);
   hipFree(s.hub_tab_start);
@@ -101,6 +112,14 @@ void free_scratch(Scratch &s) {
   for (auto &e : s.ev)
     if (e) hipEventDestroy(e);
   for (auto &e : s.pool) hipEventDestroy(e);
+  if (s.ev_reorder) hipEventDestroy(s.ev_reorder);
+  hipFree(s.old2new);
+  hipFree(s.lab2);
+  hipFree(s.minorig);
+  hipFree(s.first_key);
+  hipFree(s.off2);
+  hipFree(s.cols2);
+  hipFree(s.w2);
   s = Scratch();
 }
 
@@ -138,7 +157,8 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
   }
   if (!s.partials) {
     s.partial_blocks = 4096;
-    if (dmalloc(&s.partials, 2 * (int64_t)s.partial_blocks) != hipSuccess)
+    if (dmalloc(&s.partials, 2 * (int64_t)s.partial_blocks) != hipSuccess ||
+        dmalloc(&s.tier_part, (int64_t)gsl::kNumTiers * gsl::kMaxTierGrid * gsl::kCountFields) != hipSuccess)
       return fail(GSL_ENOMEM, "device allocation failed");
   }
   const int64_t need = (int64_t)sizeof(Counters) + 3 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
@@ -160,6 +180,9 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
       if (hipEventCreate(&e) != hipSuccess) return fail(GSL_EDEVICE, "hipEventCreate failed");
   return GSL_OK;
 }
+
+// Device slot for the split's dominant-root hint (inside the counters block).
+int32_t *dominant_ptr(Scratch &s) { return reinterpret_cast<int32_t *>(&s.ctr->pad[0]); }
 
 unsigned long long *sweep_array(Counters *c, int which, int32_t max_iters) {
   auto *base = reinterpret_cast<unsigned long long *>(c + 1);
@@ -267,6 +290,46 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
   return GSL_OK;
 }
 
+// Space for the renumbered copy: n vertices, nnz entries (weights if asked).
+int ensure_copy(Scratch &s, int64_t n, int64_t nnz, bool weighted) {
+  if (n > s.copy_n_cap) {
+    hipFree(s.old2new);
+    hipFree(s.lab2);
+    hipFree(s.minorig);
+    hipFree(s.first_key);
+    hipFree(s.off2);
+    s.old2new = s.lab2 = s.minorig = nullptr;
+    s.first_key = nullptr;
+    s.off2 = nullptr;
+    s.copy_n_cap = -1;
+    if (dmalloc(&s.old2new, n) != hipSuccess || dmalloc(&s.lab2, n) != hipSuccess ||
+        dmalloc(&s.minorig, n) != hipSuccess || dmalloc(&s.off2, n + 1) != hipSuccess ||
+        dmalloc(&s.first_key, n) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "allocation of the renumbered copy (%lld vertices) failed", (long long)n);
+    }
+    s.copy_n_cap = n;
+  }
+  if (nnz > s.copy_nnz_cap || (weighted && !s.w2_ok)) {
+    hipFree(s.cols2);
+    hipFree(s.w2);
+    s.cols2 = nullptr;
+    s.w2 = nullptr;
+    s.w2_ok = false;
+    s.copy_nnz_cap = -1;
+    const int64_t cap = nnz > s.copy_nnz_cap ? nnz : s.copy_nnz_cap;
+    if (dmalloc(&s.cols2, cap) != hipSuccess || (weighted && dmalloc(&s.w2, cap) != hipSuccess)) {
+      (void)hipGetLastError();
+      hipFree(s.cols2);
+      s.cols2 = nullptr;
+      return fail(GSL_ENOMEM, "allocation of the renumbered copy (%lld entries) failed", (long long)nnz);
+    }
+    s.copy_nnz_cap = cap;
+    s.w2_ok = weighted;
+  }
+  return GSL_OK;
+}
+
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
@@ -299,11 +362,44 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
   if ((rc = run_plan(s, offsets, n, st))) return rc;
   Counters plan = *s.ctr_host;
-  const int32_t *hub_list = s.list + (plan.tier_start[gsl::kHubTier] - plan.tier_start[1]);
-  if ((rc = prepare_hubs(s, offsets, hub_list, plan.tier_count[gsl::kHubTier], st))) return rc;
-  const int64_t limit = gsl_convergence_limit(n, tolerance);
+  // Tier t is the id range [tier_start[t], +tier_count[t]) of s.list; hubs
+  // (tier 9) come first, isolated vertices (tier 0) last.
+  const int64_t H = plan.tier_count[gsl::kHubTier];
+  if ((rc = prepare_hubs(s, offsets, s.list, H, st))) return rc;
+  // Renumbered layout: chosen when vertices of degree > 64 hold most entries
+  // (their labels are the usual gather targets).
+  int64_t heavy = 0;
+  for (int t = 5; t < gsl::kNumTiers; ++t) heavy += plan.tier_edges[t];
+  const bool renumber = o.layout == 1 || (o.layout == 0 && 2 * heavy > nnz);
+  const int64_t np = n - plan.tier_count[0];  // non-isolated vertices
+  const int64_t *g_off = offsets;
+  const int32_t *g_cols = cols;
+  const uint32_t *g_w = weights;
+  const int32_t *g_list = s.list;
   int32_t *C = labels_out;
-  HIP_TRY(gsl::launch_init_labels(C, s.Cn, n, st));
+  int64_t n_sweep = n;
+  if (renumber) {
+    if ((rc = ensure_copy(s, n, nnz, weights != nullptr))) return rc;
+    if (o.timing) {
+      if (!s.ev_reorder && hipEventCreate(&s.ev_reorder) != hipSuccess)
+        return fail(GSL_EDEVICE, "hipEventCreate failed");
+      HIP_TRY(hipEventRecord(s.ev_reorder, st));
+    }
+    HIP_TRY(gsl::launch_reorder(offsets, cols, weights, n, s.list, plan.tier_count, plan.tier_start,
+                                s.hub_chunk_start, H > 0 ? s.h_chunk[(size_t)H] : 0, s.old2new, s.off2,
+                                s.cols2, weights ? s.w2 : nullptr, s.lab2, s.blk_counts, s.first_key,
+                                s.hub_rowsum, reinterpret_cast<unsigned long long *>(&s.ctr->first_flags),
+                                sweep_array(s.ctr, 0, max_iters), max_iters > 0 ? 1 : 0, st));
+    g_off = s.off2;
+    g_cols = s.cols2;
+    g_w = weights ? s.w2 : nullptr;
+    g_list = nullptr;
+    C = s.lab2;
+    n_sweep = np;
+  } else {
+    HIP_TRY(gsl::launch_init_labels(C, s.Cn, n, st));
+  }
+  const int64_t limit = gsl_convergence_limit(n, tolerance);
   const int64_t flag_bytes = (n + 3) / 4 * 4;
   HIP_TRY(gsl::launch_fill_u8(s.chg, 0, flag_bytes, st));
   HIP_TRY(gsl::launch_fill_u8(s.act[0], 0, flag_bytes, st));
@@ -328,16 +424,35 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
     HIP_TRY(hipEventRecord(e, st));
     return GSL_OK;
   };
-  while (it < max_iters) {
+  // The renumbering copy has already run the first sweep when every row was
+  // strictly increasing (see reorder.hip); pick up its result.
+  bool fused_first = false, converged = false;
+  if (renumber && max_iters > 0) {
+    unsigned long long fl[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&fl[0], &s.ctr->first_flags, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&fl[1], dn_arr, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (!(fl[0] & 1ull)) {
+      if (fl[0] & 2ull)
+        return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; weights are summed in 32 bits");
+      fused_first = true;
+      it = 1;
+      dn_prev = (int64_t)fl[1];
+      converged = dn_prev <= limit;
+    } else {
+      HIP_TRY(hipMemsetAsync(dn_arr, 0, sizeof(unsigned long long), st));
+    }
+  }
+  while (!converged && it < max_iters) {
     // Pruning: sweep `it` processes only flagged vertices if the previous
     // sweep marked; this sweep marks if the previous one changed few vertices
     // (otherwise the next sweep simply runs dense).
     const bool dense = !(o.prune && marked_prev);
     const bool mark = o.prune && it >= 1 && dn_prev * 8 <= n;
     gsl::SweepArgs a;
-    a.off = offsets;
-    a.cols = cols;
-    a.w = weights;
+    a.off = g_off;
+    a.cols = g_cols;
+    a.w = g_w;
     a.C = C;
     a.Cn = s.Cn;
     a.chg = s.chg;
@@ -353,11 +468,13 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
       sweep_ev.push_back(nev);
       if ((rc = rec(nev++))) return rc;
     }
+    gsl::TierGrids grids;
+    for (int t = 0; t < gsl::kNumTiers; ++t) grids.g[t] = 0;
     for (int t = 1; t < gsl::kNumTiers; ++t) {
       const int64_t cnt = plan.tier_count[t];
       if (cnt <= 0) continue;
-      const int32_t *l = s.list + (plan.tier_start[t] - plan.tier_start[1]);
       a.tier = &s.ctr->tier_stats[t][0];
+      a.part = s.tier_part + (size_t)t * gsl::kMaxTierGrid * gsl::kCountFields;
       if (o.timing) {
         launches.push_back({t, nev});
         if ((rc = rec(nev++))) return rc;
@@ -365,17 +482,20 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
       if (t == gsl::kHubTier) {
         s.hub_pool_dirty = true;
         for (auto &bt : s.hub_batches)
-          HIP_TRY(gsl::launch_hub_sweep(a, l, s.hub_chunk_start, s.hub_tab_start, s.hub_tchunk_start,
+          HIP_TRY(gsl::launch_hub_sweep(a, g_list, s.hub_chunk_start, s.hub_tab_start, s.hub_tchunk_start,
                                         s.h_chunk.data(), s.h_tchunk.data(), s.hub_pool, s.hub_best,
                                         s.hub_rowsum, bt.first, bt.second, st));
       } else {
-        HIP_TRY(gsl::launch_sweep_tier(t, a, l, cnt, st));
+        HIP_TRY(gsl::launch_sweep_tier(t, a, g_list, plan.tier_start[t], cnt, &grids.g[t], st));
       }
       if (o.timing && (rc = rec(nev++))) return rc;
       tier_launches[t] += 1;
       tier_sparse[t] += dense ? 0 : 1;
     }
-    HIP_TRY(gsl::launch_apply(C, s.Cn, s.chg, dense ? nullptr : s.act[it & 1], n, st));
+    HIP_TRY(gsl::launch_reduce_counts(s.tier_part, grids, s.ctr->tier_stats, dn_arr + it, pr_arr + it,
+                                      ed_arr + it, reinterpret_cast<unsigned long long *>(&s.ctr->overflow),
+                                      st));
+    HIP_TRY(gsl::launch_apply(C, s.Cn, s.chg, dense ? nullptr : s.act[it & 1], n_sweep, st));
     if (o.timing && (rc = rec(nev++))) return rc;
     unsigned long long dn_host[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(&dn_host[0], dn_arr + it, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
@@ -395,9 +515,16 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[2], st));
   if (overflow)
     return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; weights are summed in 32 bits");
-  if (o.split)
+  if (renumber) {
+    if (o.split)
+      HIP_TRY(gsl::launch_split(g_off, g_cols, np, C, s.parent, labels_out, nullptr, plan.tier_count,
+                                plan.tier_start, s.list, s.minorig, n, dominant_ptr(s), st));
+    else
+      HIP_TRY(gsl::launch_reorder_scatter(s.list, C, np, n, labels_out, st));
+  } else if (o.split) {
     HIP_TRY(gsl::launch_split(offsets, cols, n, C, s.parent, labels_out, s.list, plan.tier_count,
-                              plan.tier_start, st));
+                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), st));
+  }
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[3], st));
   if (stats) {
     HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, (size_t)s.ctr_bytes, hipMemcpyDeviceToHost, st));
@@ -416,6 +543,10 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
       stats->processed[k] = (int64_t)hp[k];
       stats->edges[k] = (int64_t)he[k];
     }
+    if (fused_first) {
+      stats->processed[0] = np;
+      stats->edges[0] = nnz;
+    }
     for (int t = 0; t < gsl::kNumTiers; ++t) {
       stats->tier_vertices[t] = plan.tier_count[t];
       stats->tier_launches[t] = tier_launches[t];
@@ -425,7 +556,9 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
       stats->tier_changed[t] = (int64_t)s.ctr_host->tier_stats[t][2];
       stats->tier_marked[t] = (int64_t)s.ctr_host->tier_stats[t][3];
     }
+    stats->renumbered = renumber ? 1 : 0;
     if (o.timing) {
+      if (renumber) stats->ms_reorder = elapsed(s.ev_reorder, s.ev[1]);
       stats->ms_plan = elapsed(s.ev[0], s.ev[1]);
       stats->ms_sweeps = elapsed(s.ev[1], s.ev[2]);
       stats->ms_split = elapsed(s.ev[2], s.ev[3]);
@@ -487,7 +620,7 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
   if ((rc = run_plan(s, offsets, n, st))) return rc;
   Counters plan = *s.ctr_host;
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list,
-                            plan.tier_count, plan.tier_start, st));
+                            plan.tier_count, plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), st));
   HIP_TRY(hipStreamSynchronize(st));
   return GSL_OK;
 }

@@ -29,10 +29,12 @@ struct Counters {
   uint64_t overflow;        // set when a row's weight sum reaches 2^32
   uint64_t split_changed;   // hook round: nonzero if any union happened
   uint64_t bad_label;       // set when an input label is outside [0, n)
+  uint64_t first_flags;     // folded first sweep: bit 0 unsorted row, bit 1 overflow
   uint64_t two_m, intra;    // modularity integer parts
   uint64_t s2_lo, s2_hi;
   double q;
   uint64_t pad[3];
+  int64_t tier_edges[16];   // row entries per tier
   // per tier, summed over sweeps: processed, edges, changed, marked
   unsigned long long tier_stats[kNumTiers][4];
   // followed by per-sweep arrays dn[max_iters], processed[], edges[]
@@ -52,6 +54,16 @@ struct SweepArgs {
   int mark;               // mark neighbours of changed vertices in nact
   unsigned long long *dn, *processed, *edges, *overflow;
   unsigned long long *tier;  // this tier's [processed, edges, changed, marked]
+  // Per-block count records of the tier kernels (kCountFields per block);
+  // summed by launch_reduce_counts instead of contended global atomics.
+  unsigned long long *part;
+};
+
+constexpr int kCountFields = 5;        // dn, processed, edges, marked, overflow
+constexpr int kMaxTierGrid = 256 * 16; // largest grid of a tier kernel
+
+struct TierGrids {
+  int g[kNumTiers];
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----
@@ -59,8 +71,14 @@ hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *bl
                        Counters *ctr, hipStream_t s);
 int64_t plan_blocks(int64_t n);
 
-hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t count,
-                             hipStream_t s);
+hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t first,
+                             int64_t count, int *grid_out, hipStream_t s);
+// Sums the per-block records of tier t (part + t * kMaxTierGrid * kCountFields,
+// g.g[t] blocks) into the tier and sweep counters.
+hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
+                                unsigned long long (*tier_stats)[4], unsigned long long *dn,
+                                unsigned long long *processed, unsigned long long *edges,
+                                unsigned long long *overflow, hipStream_t s);
 hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, int64_t *chunk_start,
                              int64_t *tab_start, int64_t *tchunk_start, hipStream_t s);
 hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, const int64_t *chunk_start,
@@ -77,7 +95,17 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
 hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
+                        const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
                         hipStream_t s);
+hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_t *w, int64_t n,
+                          const int32_t *list, const int64_t *tier_count_h, const int64_t *tier_start_h,
+                          const int64_t *hub_chunk_start, int64_t hub_chunks, int32_t *old2new,
+                          int64_t *off2, int32_t *cols2, uint32_t *w2, int32_t *lab,
+                          int64_t *scan_tmp, unsigned long long *first_key,
+                          unsigned long long *hub_rowsum, unsigned long long *flags,
+                          unsigned long long *dn0, int apply_first, hipStream_t s);
+hipError_t launch_reorder_scatter(const int32_t *list, const int32_t *val, int64_t np, int64_t n,
+                                  int32_t *out, hipStream_t s);
 hipError_t launch_check_labels(const int32_t *labels, int64_t n, unsigned long long *bad,
                                hipStream_t s);
 

@@ -40,10 +40,9 @@ __device__ __forceinline__ int64_t owner(const int64_t *start, int64_t lo, int64
   return lo;
 }
 
-__device__ __forceinline__ void global_add(unsigned long long *tab, int log2s, uint32_t label,
-                                           uint32_t w) {
-  const uint32_t mask = (1u << log2s) - 1u;
-  uint32_t h = slot_hash(label, log2s);
+// Adds (label, w) to a global table, probing linearly from slot h.
+__device__ __forceinline__ void global_add_from(unsigned long long *tab, uint32_t mask, uint32_t h,
+                                                uint32_t label, uint32_t w) {
   const unsigned long long mine = ((unsigned long long)label << 32) | w;
   for (;;) {
     unsigned long long expected = kEmptySlot;
@@ -106,7 +105,7 @@ __global__ __launch_bounds__(1024) void hub_scan_prefix(int64_t *a0, int64_t *a1
 }
 
 struct HubArgs {
-  const int32_t *hubs;        // hub vertex ids
+  const int32_t *hubs;        // hub vertex ids (NULL: hub k is vertex k)
   const int64_t *chunk_start; // [H+1]
   const int64_t *tab_start;   // [H+1]
   const int64_t *tchunk_start;// [H+1]
@@ -121,7 +120,7 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
   __shared__ unsigned long long red[kHubBlock / kWave];
   const int64_t c = h.chunk_start[h.k0] + blockIdx.x;
   const int64_t k = owner(h.chunk_start, h.k0, h.k1, c);
-  const int32_t v = h.hubs[k];
+  const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!a.dense && !a.act[v]) return;  // uniform over the block
   for (int s = threadIdx.x; s < (1 << kHubLog2S); s += kHubBlock) tab[s] = kEmptySlot;
   const int64_t rb = a.off[v], re = a.off[v + 1];
@@ -147,13 +146,34 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
   for (int q = 0; q < kHubK; ++q) slot[q] = lab[q] != kNoLabel ? lds_insert(tab, kHubLog2S, lab[q], wt[q]) : -1;
   __syncthreads();
   const int log2s = hub_log2(re - rb);
+  const uint32_t gmask = (1u << log2s) - 1u;
   unsigned long long *gt = h.tab + (h.tab_start[k] - h.tab_start[h.k0]);
+  // All first-probe compare-and-swaps of a thread are issued together; only
+  // the (rare) collisions walk on one by one.
+  unsigned long long x[kHubK], prev[kHubK];
+  uint32_t gh[kHubK];
 #pragma unroll
-  for (int q = 0; q < kHubK; ++q)
-    if (slot[q] >= 0) {
-      const unsigned long long x = tab[slot[q]];
-      global_add(gt, log2s, (uint32_t)(x >> 32), (uint32_t)x);
+  for (int q = 0; q < kHubK; ++q) {
+    x[q] = slot[q] >= 0 ? tab[slot[q]] : kEmptySlot;
+    gh[q] = slot_hash((uint32_t)(x[q] >> 32), log2s);
+  }
+#pragma unroll
+  for (int q = 0; q < kHubK; ++q) {
+    prev[q] = kEmptySlot;
+    if (slot[q] >= 0)
+      __hip_atomic_compare_exchange_strong(&gt[gh[q]], &prev[q], x[q], __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int q = 0; q < kHubK; ++q) {
+    if (slot[q] < 0 || prev[q] == kEmptySlot) continue;  // claimed on the first probe
+    const uint32_t label = (uint32_t)(x[q] >> 32), w = (uint32_t)x[q];
+    if ((uint32_t)(prev[q] >> 32) == label) {
+      __hip_atomic_fetch_add(&gt[gh[q]], (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
     }
+    global_add_from(gt, gmask, (gh[q] + 1u) & gmask, label, w);
+  }
   rs = block_sum(rs, red);
   if (threadIdx.x == 0 && rs)
     __hip_atomic_fetch_add(&h.rowsum[k], rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -163,7 +183,7 @@ __global__ __launch_bounds__(kScanBlock) void hub_scan(SweepArgs a, HubArgs h) {
   __shared__ unsigned long long red[kScanBlock / kWave];
   const int64_t tc = h.tchunk_start[h.k0] + blockIdx.x;
   const int64_t k = owner(h.tchunk_start, h.k0, h.k1, tc);
-  const int32_t v = h.hubs[k];
+  const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!a.dense && !a.act[v]) return;
   const int64_t base = h.tab_start[k] - h.tab_start[h.k0];
   const int64_t s0 = (tc - h.tchunk_start[k]) * kScanChunk;
@@ -194,7 +214,7 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
   LocalCounts lc;
   const int64_t k = h.k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < h.k1) {
-    const int32_t v = h.hubs[k];
+    const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
     if (a.dense || a.act[v]) {
       const unsigned long long best = h.best[k];
       const unsigned long long rs = h.rowsum[k];
@@ -209,6 +229,7 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
           a.Cn[v] = (int32_t)cstar;
           a.chg[v] = 1;
           lc.dn = 1;
+          if (a.mark) lc.marked = lc.edges;  // hub_mark flags the whole row
         }
       }
     }
@@ -217,7 +238,9 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
   const unsigned long long pr = block_sum(lc.processed, red);
   const unsigned long long ed = block_sum(lc.edges, red);
   const unsigned long long ov = block_sum(lc.overflow, red);
+  const unsigned long long mk = block_sum(lc.marked, red);
   if (threadIdx.x == 0) {
+    if (mk) atomicAdd(a.tier + 3, mk);
     if (dn) {
       atomicAdd(a.dn, dn);
       atomicAdd(a.tier + 2, dn);
@@ -235,22 +258,17 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
 }
 
 __global__ __launch_bounds__(kHubBlock) void hub_mark(SweepArgs a, HubArgs h) {
-  __shared__ unsigned long long red[kHubBlock / kWave];
   const int64_t c = h.chunk_start[h.k0] + blockIdx.x;
   const int64_t k = owner(h.chunk_start, h.k0, h.k1, c);
-  const int32_t v = h.hubs[k];
+  const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!a.chg[v]) return;  // uniform: only hubs changed in this sweep
   const int64_t rb = a.off[v], re = a.off[v + 1];
   const int64_t b = rb + (c - h.chunk_start[k]) * kHubChunk;
   const int64_t e = b + kHubChunk < re ? b + kHubChunk : re;
-  unsigned long long m = 0;
   for (int64_t p = b + threadIdx.x; p < e; p += kHubBlock) {
     const int32_t jj = a.cols[p];
     if (!a.nact[jj]) a.nact[jj] = 1;
-    m += 1;
   }
-  m = block_sum(m, red);
-  if (threadIdx.x == 0 && m) atomicAdd(a.tier + 3, m);
 }
 
 }  // namespace

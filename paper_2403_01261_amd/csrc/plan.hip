@@ -2,11 +2,12 @@
 //
 // The paper spreads vertices over CPU threads with per-thread hashtables
 // (Alg. 3, Sec. 5.1.2); on the GPU the work unit must match the row length
-// instead.  plan_count counts the tiers of each block of 1024 vertices,
-// plan_scan turns the counts into per-block bases and tier starts, and
-// plan_scatter writes every non-isolated vertex id into its tier's segment of
-// `list`, ascending within each tier (so consecutive lanes read neighbouring
-// CSR rows).
+// instead.  plan_count counts the vertices and row entries of each tier in
+// each block of 1024 vertices, plan_scan turns the counts into per-block bases
+// and tier starts, and plan_scatter writes every vertex id into its tier's
+// segment of `list`, ascending within each tier.  Tiers are laid out from the
+// longest rows down (hubs first, isolated vertices last), so `list` doubles as
+// a degree-ordered renumbering of the graph.
 #include "device_common.h"
 #include "gsl_internal.h"
 
@@ -28,14 +29,20 @@ __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restri
                                                          int64_t *__restrict__ blk_counts,
                                                          Counters *ctr) {
   __shared__ int cnt[kNumTiers];
+  __shared__ unsigned long long ecnt[kNumTiers];
   __shared__ unsigned long long dmax[kPlanBlock / kWave];
-  if (threadIdx.x < kNumTiers) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < kNumTiers) {
+    cnt[threadIdx.x] = 0;
+    ecnt[threadIdx.x] = 0;
+  }
   __syncthreads();
   const int64_t v = (int64_t)blockIdx.x * kPlanBlock + threadIdx.x;
   int64_t d = 0;
   if (v < n) {
     d = off[v + 1] - off[v];
-    atomicAdd(&cnt[tier_of(d)], 1);
+    const int t = tier_of(d);
+    atomicAdd(&cnt[t], 1);
+    if (d > 0) atomicAdd(&ecnt[t], (unsigned long long)d);
   }
   unsigned long long m = (unsigned long long)(d > 0 ? d : 0);
 #pragma unroll
@@ -45,7 +52,11 @@ __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restri
   }
   if (threadIdx.x % kWave == 0) dmax[threadIdx.x / kWave] = m;
   __syncthreads();
-  if (threadIdx.x < kNumTiers) blk_counts[(int64_t)blockIdx.x * kNumTiers + threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < kNumTiers) {
+    blk_counts[(int64_t)blockIdx.x * kNumTiers + threadIdx.x] = cnt[threadIdx.x];
+    if (ecnt[threadIdx.x])
+      atomicAdd(reinterpret_cast<unsigned long long *>(&ctr->tier_edges[threadIdx.x]), ecnt[threadIdx.x]);
+  }
   if (threadIdx.x == 0) {
     unsigned long long mm = 0;
     for (int k = 0; k < kPlanBlock / kWave; ++k) mm = dmax[k] > mm ? dmax[k] : mm;
@@ -54,7 +65,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restri
 }
 
 // One block: exclusive scan of blk_counts over blocks for every tier (in
-// place), tier totals and tier starts (tiers laid out in order 0..9).
+// place), tier totals and tier starts (tiers laid out in order 9..0).
 __global__ __launch_bounds__(kPlanBlock) void plan_scan(int64_t *__restrict__ blk_counts,
                                                         int64_t nblk, Counters *ctr) {
   __shared__ int64_t part[kPlanBlock];
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_scan(int64_t *__restrict__ bl
   }
   if (threadIdx.x == 0) {
     int64_t start = 0;
-    for (int t = 0; t < kNumTiers; ++t) {
+    for (int t = kNumTiers - 1; t >= 0; --t) {
       ctr->tier_count[t] = totals[t];
       ctr->tier_start[t] = start;
       start += totals[t];
@@ -111,11 +122,11 @@ __global__ __launch_bounds__(kPlanBlock) void plan_scatter(const int64_t *__rest
     if (lane == 0) wcnt[wid][k] = __popcll(m);
   }
   __syncthreads();
-  if (t > 0) {
+  if (t >= 0) {
     int before = 0;
     for (int w = 0; w < wid; ++w) before += wcnt[w][t];
     const int64_t pos = ctr->tier_start[t] + blk_base[(int64_t)blockIdx.x * kNumTiers + t] + before + rank;
-    list[pos - ctr->tier_start[1]] = (int32_t)v;
+    list[pos] = (int32_t)v;
   }
 }
 
@@ -123,8 +134,8 @@ __global__ __launch_bounds__(kPlanBlock) void plan_scatter(const int64_t *__rest
 
 int64_t plan_blocks(int64_t n) { return (n + kPlanBlock - 1) / kPlanBlock; }
 
-// list receives the non-isolated vertices grouped by tier 1..9; entry
-// tier_start[t] - tier_start[1] is the first vertex of tier t.
+// list receives every vertex grouped by tier (9 first, 0 last); entry
+// tier_start[t] is the first vertex of tier t.
 hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *blk_counts,
                        Counters *ctr, hipStream_t s) {
   const int64_t nblk = plan_blocks(n);

@@ -6,8 +6,15 @@
 // entries (u, v) with C[u] == C[v], by a lock-free union-find whose unions
 // always hang the larger root below the smaller one.  Ids therefore decrease
 // along every parent chain and the final root of each component is its
-// smallest vertex, whatever order the unions happen in.  Each undirected edge
-// is united once (from the row of its larger endpoint, v < u).
+// smallest vertex, whatever order the unions happen in.
+//
+// The edges are taken in the order of Afforest (Sutton, Ben-Nun & Barak,
+// IPDPS 2018): first the first two entries of every row, then a compression
+// and a sample of 1024 vertices that names the dominant root R, then the
+// remaining entries of every row whose vertex is not already under R.  A
+// skipped vertex u loses nothing: for an entry (u, v) with v outside R the
+// mirrored entry (v, u) is processed from v's side (the graph is symmetric),
+// either among v's first two entries or in the second pass.
 #include "device_common.h"
 #include "gsl_internal.h"
 
@@ -15,27 +22,34 @@ namespace gsl {
 
 namespace {
 
+// Parent pointers are read with cache-friendly relaxed loads that may return
+// an older value.  That is safe because a pointer only ever moves to an
+// ancestor: a stale read still names an ancestor (or the vertex itself while
+// it was a root), ids decrease along every chain, and a vertex that is not a
+// root never becomes one again.  Every hook is a device-scope compare-and-swap
+// on a root; when it fails, the value it returns is the current parent, and
+// the search resumes from there, so each retry moves to a strictly smaller id.
 __device__ __forceinline__ int32_t ld_parent(const int32_t *p, int32_t x) {
-  return __hip_atomic_load(const_cast<int32_t *>(p) + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(const_cast<int32_t *>(p) + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Root of x with path halving (a vertex's parent only ever moves to another,
-// smaller ancestor, so racing halvings are harmless).
+// Root of x (as far as this thread can see) with path halving: writing an
+// ancestor into a non-root's pointer is harmless whatever races with it.
 __device__ __forceinline__ int32_t find_root(int32_t *parent, int32_t x) {
   for (;;) {
     const int32_t p = ld_parent(parent, x);
     if (p == x) return x;
     const int32_t gp = ld_parent(parent, p);
     if (gp != p)
-      __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     x = gp;
   }
 }
 
 __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b) {
+  a = find_root(parent, a);
+  b = find_root(parent, b);
   for (;;) {
-    a = find_root(parent, a);
-    b = find_root(parent, b);
     if (a == b) return;
     if (a < b) {
       const int32_t t = a;
@@ -46,6 +60,8 @@ __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b) {
     if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return;
+    a = find_root(parent, expected);  // a was hooked meanwhile: continue above it
+    b = find_root(parent, b);
   }
 }
 
@@ -55,41 +71,102 @@ __global__ void split_init(int32_t *parent, int64_t n) {
     parent[i] = (int32_t)i;
 }
 
-// One thread per vertex (short rows).
+constexpr int kLinkFirst = 2;  // entries per row linked before the sample
+constexpr int kSamples = 1024;
+
+// First pass: the first kLinkFirst entries of every row.
+__global__ __launch_bounds__(256) void split_link_first(const int64_t *__restrict__ off,
+                                                        const int32_t *__restrict__ cols,
+                                                        const int32_t *__restrict__ C,
+                                                        int32_t *parent, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    const int64_t b = off[u], e = off[u + 1];
+    const int32_t cu = C[u];
+#pragma unroll
+    for (int q = 0; q < kLinkFirst; ++q) {
+      if (b + q >= e) break;
+      const int32_t v = cols[b + q];
+      if (v != (int32_t)u && C[v] == cu) unite(parent, (int32_t)u, v);
+    }
+  }
+}
+
+__global__ void split_flatten(int32_t *parent, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    parent[i] = find_root(parent, (int32_t)i);
+}
+
+// Most frequent root among kSamples pseudo-random vertices (ties: smaller
+// root); one block of kSamples threads.  Only a hint: any value is correct.
+__global__ __launch_bounds__(kSamples) void split_sample(const int32_t *parent, int64_t n,
+                                                         int32_t *dominant) {
+  __shared__ int32_t val[kSamples];
+  __shared__ unsigned long long best[kSamples / kWave];
+  uint64_t z = (uint64_t)threadIdx.x * 0x9e3779b97f4a7c15ull + 0x632be59bd9b4e019ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  val[threadIdx.x] = parent[(int64_t)(z % (uint64_t)n)];
+  __syncthreads();
+  const int32_t mine = val[threadIdx.x];
+  unsigned cnt = 0;
+  for (int k = 0; k < kSamples; ++k) cnt += val[k] == mine;
+  // key: count high, then the complement of the root (smaller root wins)
+  unsigned long long key = ((unsigned long long)cnt << 32) | (uint32_t)(~(uint32_t)mine);
+  key = group_max<kWave>(key);
+  if (threadIdx.x % kWave == 0) best[threadIdx.x / kWave] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    for (int w = 0; w < kSamples / kWave; ++w) m = best[w] > m ? best[w] : m;
+    *dominant = (int32_t)~(uint32_t)m;
+  }
+}
+
+// Second pass, one thread per vertex (short rows): entries from position
+// kLinkFirst on, for vertices not under the dominant root.
 __global__ __launch_bounds__(256) void split_hook_thread(const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ cols,
                                                          const int32_t *__restrict__ C,
                                                          int32_t *parent,
                                                          const int32_t *__restrict__ list,
-                                                         int64_t count) {
+                                                         int64_t first, int64_t count,
+                                                         const int32_t *__restrict__ dominant) {
+  const int32_t R = *dominant;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
-    const int32_t u = list[idx];
+    const int32_t u = list ? list[first + idx] : (int32_t)(first + idx);
+    if (ld_parent(parent, u) == R) continue;
     const int32_t cu = C[u];
-    for (int64_t p = off[u]; p < off[u + 1]; ++p) {
+    for (int64_t p = off[u] + kLinkFirst; p < off[u + 1]; ++p) {
       const int32_t v = cols[p];
-      if (v < u && C[v] == cu) unite(parent, u, v);
+      if (v != u && C[v] == cu) unite(parent, u, v);
     }
   }
 }
 
-// A group of G lanes per vertex (G <= 64) or, with G == blockDim.x, a block.
+// Same with a group of G lanes per vertex (G <= 64, or the 256-thread block).
 template <int G>
 __global__ __launch_bounds__(256) void split_hook_group(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
                                                         const int32_t *__restrict__ C,
                                                         int32_t *parent,
                                                         const int32_t *__restrict__ list,
-                                                        int64_t count) {
+                                                        int64_t first, int64_t count,
+                                                        const int32_t *__restrict__ dominant) {
   constexpr int GPB = 256 / G;
+  const int32_t R = *dominant;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   for (int64_t idx = (int64_t)blockIdx.x * GPB + g; idx < count; idx += (int64_t)gridDim.x * GPB) {
-    const int32_t u = list[idx];
+    const int32_t u = list ? list[first + idx] : (int32_t)(first + idx);
+    if (ld_parent(parent, u) == R) continue;  // uniform over the group
     const int32_t cu = C[u];
     const int64_t e = off[u + 1];
-    for (int64_t p = off[u] + lane; p < e; p += G) {
+    for (int64_t p = off[u] + kLinkFirst + lane; p < e; p += G) {
       const int32_t v = cols[p];
-      if (v < u && C[v] == cu) unite(parent, u, v);
+      if (v != u && C[v] == cu) unite(parent, u, v);
     }
   }
 }
@@ -98,6 +175,49 @@ __global__ void split_compress(int32_t *parent, int32_t *out, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     out[i] = find_root(parent, (int32_t)i);
+}
+
+// Renumbered graph: root of every vertex, and per root the smallest
+// original id of its component.  Most vertices of a block usually share one
+// root (the giant piece), so the block first folds the candidates for the
+// root of its first vertex in LDS and sends one atomic for them.
+__global__ __launch_bounds__(256) void split_root_min(int32_t *parent, const int32_t *__restrict__ orig,
+                                                      int64_t np, int32_t *minorig) {
+  __shared__ int32_t lead, lead_min;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += stride) {
+    const int64_t p = base + threadIdx.x;
+    int32_t r = -1, o = 0;
+    if (p < np) {
+      r = find_root(parent, (int32_t)p);
+      parent[p] = r;
+      o = orig[p];
+    }
+    if (threadIdx.x == 0) {
+      lead = r;
+      lead_min = 0x7fffffff;
+    }
+    __syncthreads();
+    if (r >= 0 && r == lead) atomicMin(&lead_min, o);  // LDS
+    else if (r >= 0) atomicMin(&minorig[r], o);
+    __syncthreads();
+    if (threadIdx.x == 0 && lead >= 0) atomicMin(&minorig[lead], lead_min);
+    __syncthreads();
+  }
+}
+
+__global__ void split_out(const int32_t *__restrict__ parent, const int32_t *__restrict__ orig,
+                          const int32_t *__restrict__ minorig, int64_t np, int64_t n, int32_t *out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const int32_t v = orig[p];
+    out[v] = p < np ? minorig[parent[p]] : v;
+  }
+}
+
+__global__ void fill_i32(int32_t *p, int32_t v, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 __global__ void check_labels(const int32_t *labels, int64_t n, unsigned long long *bad) {
@@ -118,29 +238,51 @@ int grid_cap(int64_t items, int per_block, int cap) {
 
 }  // namespace
 
-// tier_count_host / tier_start_host: the plan of the graph (tier t occupies
-// list[tier_start[t] - tier_start[1] ...]).
+// Split on a graph whose vertices are grouped by tier (tier t occupies
+// [tier_start[t], tier_start[t] + tier_count[t]) of `list`, or of the ids
+// themselves when list is NULL).
+//  orig == NULL : the graph is in caller ids; out[i] = smallest id of i's piece.
+//  orig != NULL : the graph is the renumbered copy of its n non-isolated
+//                 vertices, orig[p] the caller id of vertex p (orig holds
+//                 n_total entries, isolated vertices last); out is written in
+//                 caller ids with the smallest caller id of each piece.
 hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
+                        const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
                         hipStream_t s) {
-  if (n <= 0) return hipSuccess;
   constexpr int kCap = 256 * 16;
-  split_init<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
-  for (int t = 1; t < kNumTiers; ++t) {
-    const int64_t cnt = tier_count_host[t];
-    if (cnt <= 0) continue;
-    const int32_t *l = list + (tier_start_host[t] - tier_start_host[1]);
-    if (t == 1)
-      split_hook_thread<<<grid_cap(cnt, 256, kCap), 256, 0, s>>>(off, cols, C, parent, l, cnt);
-    else if (t <= 3)
-      split_hook_group<8><<<grid_cap(cnt, 32, kCap), 256, 0, s>>>(off, cols, C, parent, l, cnt);
-    else if (t <= 6)
-      split_hook_group<64><<<grid_cap(cnt, 4, kCap), 256, 0, s>>>(off, cols, C, parent, l, cnt);
-    else
-      split_hook_group<256><<<grid_cap(cnt, 1, kCap), 256, 0, s>>>(off, cols, C, parent, l, cnt);
+  if (n > 0) {
+    split_init<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
+    split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n);
+    split_flatten<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
+    split_sample<<<1, kSamples, 0, s>>>(parent, n, dominant);
   }
-  split_compress<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, out, n);
+  for (int t = 1; t < kNumTiers; ++t) {
+    const int64_t cnt = tier_count_host[t], first = tier_start_host[t];
+    if (cnt <= 0) continue;
+    if (t == 1)
+      split_hook_thread<<<grid_cap(cnt, 256, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+                                                                  dominant);
+    else if (t <= 3)
+      split_hook_group<8><<<grid_cap(cnt, 32, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+                                                                   dominant);
+    else if (t <= 6)
+      split_hook_group<64><<<grid_cap(cnt, 4, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+                                                                   dominant);
+    else
+      split_hook_group<256><<<grid_cap(cnt, 1, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+                                                                    dominant);
+  }
+  if (!orig) {
+    if (n > 0) split_compress<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, out, n);
+  } else {
+    if (n > 0) {
+      fill_i32<<<grid_cap(n, 256, kCap), 256, 0, s>>>(minorig, 0x7fffffff, n);
+      split_root_min<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, orig, n, minorig);
+    }
+    if (n_total > 0) split_out<<<grid_cap(n_total, 256, kCap), 256, 0, s>>>(parent, orig, minorig, n, n_total, out);
+  }
   return hipGetLastError();
 }
 

@@ -31,28 +31,21 @@ __device__ __forceinline__ void record_change(const SweepArgs &a, int32_t v, uin
   lc.dn += 1;
 }
 
+// Block totals of the per-thread counts, stored as this block's record.
 __device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCounts &lc,
                                              unsigned long long *red) {
   const unsigned long long dn = block_sum(lc.dn, red);
   const unsigned long long pr = block_sum(lc.processed, red);
   const unsigned long long ed = block_sum(lc.edges, red);
-  const unsigned long long ov = block_sum(lc.overflow, red);
   const unsigned long long mk = block_sum(lc.marked, red);
+  const unsigned long long ov = block_sum(lc.overflow, red);
   if (threadIdx.x == 0) {
-    if (dn) {
-      atomicAdd(a.dn, dn);
-      atomicAdd(a.tier + 2, dn);
-    }
-    if (pr) {
-      atomicAdd(a.processed, pr);
-      atomicAdd(a.tier + 0, pr);
-    }
-    if (ed) {
-      atomicAdd(a.edges, ed);
-      atomicAdd(a.tier + 1, ed);
-    }
-    if (mk) atomicAdd(a.tier + 3, mk);
-    if (ov) atomicAdd(a.overflow, ov);
+    unsigned long long *r = a.part + (size_t)blockIdx.x * kCountFields;
+    r[0] = dn;
+    r[1] = pr;
+    r[2] = ed;
+    r[3] = mk;
+    r[4] = ov;
   }
 }
 
@@ -62,12 +55,12 @@ __device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCoun
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *__restrict__ list,
-                                                    int64_t count) {
+                                                    int64_t first, int64_t count) {
   __shared__ unsigned long long red[256 / kWave];
   LocalCounts lc;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
-    const int32_t v = list[idx];
+    const int32_t v = list ? list[first + idx] : (int32_t)(first + idx);
     if (!a.dense && !a.act[v]) continue;
     const int64_t b = a.off[v];
     const int d = (int)(a.off[v + 1] - b);
@@ -124,7 +117,7 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
 // ---------------------------------------------------------------------------
 template <int G, int LOG2S, int BLOCK, int K>
 __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *__restrict__ list,
-                                                   int64_t count) {
+                                                   int64_t first, int64_t count) {
   static_assert(G <= 64 || G == BLOCK, "group is a wave slice or the block");
   constexpr int GPB = BLOCK / G;
   constexpr int S = 1 << LOG2S;
@@ -141,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
     const int64_t idx = base + g;
     int32_t v = -1;
     if (idx < count) {
-      v = list[idx];
+      v = list ? list[first + idx] : (int32_t)(first + idx);
       if (!a.dense && !a.act[v]) v = -1;
     }
     int64_t b = 0, e = 0;
@@ -278,38 +271,86 @@ int grid_for(int64_t items, int per_block, int cap) {
 
 }  // namespace
 
-hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t count,
-                             hipStream_t s) {
+hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t first,
+                             int64_t count, int *grid_out, hipStream_t s) {
+  *grid_out = 0;
   if (count <= 0) return hipSuccess;
-  constexpr int kCap = 256 * 16;
+  constexpr int kCap = kMaxTierGrid;
+  int grid = 0;
   switch (tier) {
     case 1:
-      sweep_thread<8><<<grid_for(count, 256, kCap), 256, 0, s>>>(a, list, count);
+      grid = grid_for(count, 256, kCap);
+      sweep_thread<8><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
     case 2:
-      sweep_lds<8, 5, 256, 2><<<grid_for(count, 256 / 8, kCap), 256, 0, s>>>(a, list, count);
+      grid = grid_for(count, 256 / 8, kCap);
+      sweep_lds<8, 5, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
     case 3:
-      sweep_lds<16, 6, 256, 2><<<grid_for(count, 256 / 16, kCap), 256, 0, s>>>(a, list, count);
+      grid = grid_for(count, 256 / 16, kCap);
+      sweep_lds<16, 6, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
     case 4:
-      sweep_lds<32, 7, 256, 2><<<grid_for(count, 256 / 32, kCap), 256, 0, s>>>(a, list, count);
+      grid = grid_for(count, 256 / 32, kCap);
+      sweep_lds<32, 7, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
     case 5:
-      sweep_lds<64, 8, 256, 2><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
+      grid = grid_for(count, 256 / 64, kCap);
+      sweep_lds<64, 8, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
     case 6:
-      sweep_lds<64, 10, 256, 8><<<grid_for(count, 256 / 64, kCap), 256, 0, s>>>(a, list, count);
+      grid = grid_for(count, 256 / 64, kCap);
+      sweep_lds<64, 10, 256, 8><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
     case 7:
-      sweep_lds<256, 12, 256, 8><<<grid_for(count, 1, kCap), 256, 0, s>>>(a, list, count);
+      grid = grid_for(count, 1, kCap);
+      sweep_lds<256, 12, 256, 8><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
     case 8:
-      sweep_lds<1024, 14, 1024, 8><<<grid_for(count, 1, 256 * 2), 1024, 0, s>>>(a, list, count);
+      grid = grid_for(count, 1, 256 * 2);
+      sweep_lds<1024, 14, 1024, 8><<<grid, 1024, 0, s>>>(a, list, first, count);
       break;
     default:
       return hipErrorInvalidValue;
   }
+  *grid_out = grid;
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void reduce_counts(const unsigned long long *__restrict__ part, TierGrids g,
+                              unsigned long long (*tier_stats)[4], unsigned long long *dn,
+                              unsigned long long *processed, unsigned long long *edges,
+                              unsigned long long *overflow) {
+  __shared__ unsigned long long red[256 / kWave];
+  const int t = blockIdx.x;
+  const int nb = g.g[t];
+  if (nb <= 0) return;
+  const unsigned long long *r = part + (size_t)t * kMaxTierGrid * kCountFields;
+  unsigned long long v[kCountFields] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int f = 0; f < kCountFields; ++f) v[f] += r[(size_t)b * kCountFields + f];
+#pragma unroll
+  for (int f = 0; f < kCountFields; ++f) v[f] = block_sum(v[f], red);
+  if (threadIdx.x == 0) {
+    atomicAdd(&tier_stats[t][2], v[0]);
+    atomicAdd(&tier_stats[t][0], v[1]);
+    atomicAdd(&tier_stats[t][1], v[2]);
+    atomicAdd(&tier_stats[t][3], v[3]);
+    atomicAdd(dn, v[0]);
+    atomicAdd(processed, v[1]);
+    atomicAdd(edges, v[2]);
+    if (v[4]) atomicAdd(overflow, v[4]);
+  }
+}
+}  // namespace
+
+hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
+                                unsigned long long (*tier_stats)[4], unsigned long long *dn,
+                                unsigned long long *processed, unsigned long long *edges,
+                                unsigned long long *overflow, hipStream_t s) {
+  reduce_counts<<<kNumTiers, 256, 0, s>>>(part, g, tier_stats, dn, processed, edges, overflow);
   return hipGetLastError();
 }
 

@@ -35,20 +35,21 @@ def gsl():
     return m
 
 
-def run_gpu(gsl, g, max_iters=20, tol=0.05, prune=True, split=True, weights="as-is"):
+def run_gpu(gsl, g, max_iters=20, tol=0.05, prune=True, split=True, weights="as-is", layout="auto"):
     off, cols, w = to_device(g, weights=weights)
-    lab, st = gsl.gsl_lpa_ex(off, cols, w, max_iters, tol, prune=prune, split=split)
+    lab, st = gsl.gsl_lpa_ex(off, cols, w, max_iters, tol, prune=prune, split=split, layout=layout)
     return lab.cpu().numpy(), st
 
 
-def assert_same(gsl, g, max_iters=20, tol=0.05, tag=""):
+def assert_same(gsl, g, max_iters=20, tol=0.05, tag="", layouts=("original", "renumbered")):
     for split in (False, True):
         r = oracle.lpa(g, max_iters, tol, split=split)
-        lab, st = run_gpu(gsl, g, max_iters, tol, split=split)
-        assert st["iterations"] == r.iterations, (tag, split)
-        k = min(r.iterations, 64)
-        assert list(st["changed"][:k]) == list(r.dn[:k]), (tag, split)
-        np.testing.assert_array_equal(lab, r.labels, err_msg="%s split=%s" % (tag, split))
+        for layout in layouts:
+            lab, st = run_gpu(gsl, g, max_iters, tol, split=split, layout=layout)
+            assert st["iterations"] == r.iterations, (tag, split, layout)
+            k = min(r.iterations, 64)
+            assert list(st["changed"][:k]) == list(r.dn[:k]), (tag, split, layout)
+            np.testing.assert_array_equal(lab, r.labels, err_msg="%s split=%s %s" % (tag, split, layout))
 
 
 def test_every_graph_up_to_5_vertices(gsl):
@@ -115,6 +116,14 @@ def test_batch_members(gsl):
     b = workloads.make(5, small=True)
     for k in range(0, b.num_graphs, 7):
         assert_same(gsl, b.subgraph(k), tag="batch member %d" % k)
+
+
+def test_layout_auto_choice(gsl):
+    # Power-law graph: most entries sit in rows of degree > 64 -> renumbered.
+    _, st = run_gpu(gsl, workloads.make(2, small=True))
+    assert st["renumbered"]
+    _, st = run_gpu(gsl, workloads.make(3, small=True))
+    assert not st["renumbered"]
 
 
 def test_pruning_does_not_change_results(gsl):
@@ -216,10 +225,11 @@ def test_full_workload_matches_oracle_hash(gsl, idx):
     assert g.n == gold["n"] and g.nnz == gold["nnz"]
     assert graph_hash(g) == gold["graph_xxh128"], "generator output differs from the golden graph"
     say("workload %d: n=%d nnz=%d" % (idx, g.n, g.nnz))
-    lab, st = run_gpu(gsl, g, gold["max_iters"], gold["tolerance"])
-    assert st["iterations"] == gold["iterations"]
-    assert list(st["changed"][:st["iterations"]]) == gold["dn"]
-    assert labels_hash(lab) == gold["labels_xxh128"]
+    for layout in ("auto", "original", "renumbered"):
+        lab, st = run_gpu(gsl, g, gold["max_iters"], gold["tolerance"], layout=layout)
+        assert st["iterations"] == gold["iterations"], layout
+        assert list(st["changed"][:st["iterations"]]) == gold["dn"], layout
+        assert labels_hash(lab) == gold["labels_xxh128"], layout
     off, cols, w = to_device(g)
     q = gsl.gsl_modularity(off, cols, w, torch.from_numpy(lab).cuda())
     assert abs(q - gold["modularity"]) <= 1e-12 * max(1.0, abs(gold["modularity"]))
