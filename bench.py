@@ -38,10 +38,12 @@ WORKLOAD_TEXT = {
     4: "web-scale R-MAT scale 26 (67,108,864 vertices), edge factor 32, a/b/c/d "
        "0.57/0.19/0.19/0.05, symmetrised, unit weights",
 }
-TIER_KERNEL = {1: "sweep_thread<8>", 2: "sweep_group<8,5,256,2>", 3: "sweep_group<16,6,256,2>",
-               4: "sweep_group<32,7,256,2>", 5: "sweep_group<64,8,256,2>",
-               6: "sweep_group<64,10,256,4>", 7: "sweep_block<12,256,4>",
-               8: "sweep_block<14,1024,4>", 9: "sweep_hub<1024,4>"}
+# Kernel launched for each degree tier (as rocprofv3 names it, template
+# arguments in order).
+TIER_KERNEL = {1: "sweep_thread<8>", 2: "sweep_lds<8, 5, 256, 2>", 3: "sweep_lds<16, 6, 256, 2>",
+               4: "sweep_lds<32, 7, 256, 2>", 5: "sweep_lds<64, 8, 256, 2>",
+               6: "sweep_lds<64, 10, 256, 8>", 7: "sweep_lds<256, 12, 256, 8>",
+               8: "sweep_lds<1024, 14, 1024, 8>", 9: "hub_insert"}
 
 
 def log(*a):
@@ -83,6 +85,96 @@ def measured_traffic(workload: str, kernel: str):
     return entry.get("bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30  # plain device-to-device copy used to calibrate the PMC counters
+
+
+def _read_counter_csv(d: str, counter: str):
+    """{dispatch_id: (kernel_name, value)} from a rocprofv3 --pmc csv directory."""
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") != counter:
+                    continue
+                did = int(r["Dispatch_Id"])
+                name, val = r["Kernel_Name"], float(r["Counter_Value"])
+                prev = out.get(did)
+                out[did] = (name, val + (prev[1] if prev else 0.0))
+    return out
+
+
+def _kernel_stats(d: str):
+    import csv
+    import glob
+    paths = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not paths:
+        return []
+    with open(paths[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    return name.replace("gsl::(anonymous namespace)::", "").replace("void ", "")
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int, kernel: str,
+                  commands: list) -> dict:
+    """Traffic of `kernel` per launch from FETCH_SIZE / WRITE_SIZE runs, each
+    scaled by the counter's reading for the plain COPY_BYTES copy."""
+    from graphgen import workloads
+    fetch = _read_counter_csv(fetch_dir, "FETCH_SIZE")
+    write = _read_counter_csv(write_dir, "WRITE_SIZE")
+
+    def calib(rec):
+        copies = [v for n, v in rec.values() if "copyBuffer" in n]
+        return max(copies) if copies else None
+
+    cf, cw = calib(fetch), calib(write)
+    kf = [v for n, v in fetch.values() if kernel in _short(n)]
+    kw = [v for n, v in write.values() if kernel in _short(n)]
+    if not kf or not kw or not cf or not cw:
+        raise SystemExit("counter runs lack the kernel %r or the calibration copy" % kernel)
+    sf = COPY_BYTES / (cf * 1024.0)
+    sw = COPY_BYTES / (cw * 1024.0)
+    fetch_b = sum(kf) / len(kf) * 1024.0 * sf
+    write_b = sum(kw) / len(kw) * 1024.0 * sw
+    wname = workloads.NAMES[workload]
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+    rec.setdefault(wname, {})[kernel] = {
+        "bytes_per_launch": int(round(fetch_b + write_b)), "fetch_bytes_per_launch": int(round(fetch_b)),
+        "write_bytes_per_launch": int(round(write_b)), "launches_counted": len(kf),
+        "copy_fetch_kib": cf, "copy_write_kib": cw, "scale_fetch": sf, "scale_write": sw,
+        "source_hash": source_hash(), "commands": commands}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    # Short text summary of the kernel trace next to it.
+    stats = _kernel_stats(trace_dir)
+    md = os.path.join(ROOT, "profiles", "%s_%s.md" % (wname, kernel.split("<")[0]))
+    with open(md, "w") as f:
+        f.write("# %s on %s\n\n" % (kernel, wname))
+        f.write("Commands (repository root, MI355X):\n\n")
+        for c in commands:
+            f.write("    %s\n" % c)
+        f.write("\nHBM traffic of `%s` per launch (%d launches): fetch %.3f GB, write %.3f GB "
+                "(FETCH_SIZE / WRITE_SIZE scaled by a %d MiB copy: x%.4f / x%.4f).\n\n"
+                % (kernel, len(kf), fetch_b / 1e9, write_b / 1e9, COPY_BYTES >> 20, sf, sw))
+        if stats:
+            f.write("| kernel | calls | avg us | total ms | % |\n|---|---|---|---|---|\n")
+            for r in stats[:20]:
+                f.write("| %s | %s | %.1f | %.2f | %.1f |\n" % (
+                    _short(r["Name"])[:70], r["Calls"], float(r["AverageNs"]) / 1e3,
+                    float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    return rec[wname][kernel]
+
+
 def cpu_baseline(g, max_iters, tol):
     import oracle
     t0 = time.perf_counter()
@@ -101,7 +193,17 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"),
+                    help="write profiles/traffic.json from rocprofv3 counter runs and exit")
+    ap.add_argument("--kernel", default=None, help="kernel for --summarize-pmc")
+    ap.add_argument("--commands", nargs="*", default=[], help="commands recorded by --summarize-pmc")
     args = ap.parse_args(argv)
+    if args.summarize_pmc:
+        r = summarize_pmc(*args.summarize_pmc, args.workload, args.kernel, args.commands)
+        print(json.dumps(r))
+        return 0
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -115,6 +217,12 @@ def main(argv=None):
 
     gsl.load()
     dev = torch.device("cuda:0")
+    if args.pmc_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     g = workloads.make(args.workload)
     log("generated %s: n=%d nnz=%d in %.1fs" % (workloads.NAMES[args.workload], g.n, g.nnz,

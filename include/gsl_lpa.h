@@ -84,6 +84,7 @@ typedef struct gsl_stats {
   int64_t tier_sparse[GSL_STATS_TIERS];     /* launches that read the active flags */
   int32_t renumbered;                       /* 1 if the sweeps ran on the renumbered copy */
   float ms_reorder;                         /* time to build that copy (timing != 0) */
+  float ms_hub_finish;                      /* hub table scan, decision, marking */
   float ms_tier[GSL_STATS_TIERS];           /* kernel time (timing != 0) */
 } gsl_stats;
 

@@ -53,6 +53,7 @@ class _Stats(ctypes.Structure):
                 ("tier_marked", ctypes.c_int64 * STATS_TIERS),
                 ("tier_sparse", ctypes.c_int64 * STATS_TIERS),
                 ("renumbered", ctypes.c_int32), ("ms_reorder", ctypes.c_float),
+                ("ms_hub_finish", ctypes.c_float),
                 ("ms_tier", ctypes.c_float * STATS_TIERS)]
 
 
@@ -153,6 +154,7 @@ def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=
              "max_degree": st.max_degree, "ms_plan": st.ms_plan, "ms_sweeps": st.ms_sweeps,
              "ms_split": st.ms_split, "ms_total": st.ms_total, "ms_sweep": list(st.ms_sweep[:k]),
              "renumbered": bool(st.renumbered), "ms_reorder": st.ms_reorder,
+             "ms_hub_finish": st.ms_hub_finish,
              "tiers": [{"vertices": st.tier_vertices[t], "launches": st.tier_launches[t],
                         "processed": st.tier_processed[t], "edges": st.tier_edges[t],
                         "changed": st.tier_changed[t], "marked": st.tier_marked[t],

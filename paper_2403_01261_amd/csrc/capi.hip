@@ -415,6 +415,9 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   // Timing events: per sweep (start, end) and per tier launch (start, end).
   struct Launch { int tier; size_t ev; };
   std::vector<Launch> launches;
+  // Hub tier segments after the first hub_insert: (kind, event index); kind
+  // 0 = a hub_insert of a later batch, 1 = the finishing kernels.
+  std::vector<Launch> hub_finish_ev;
   std::vector<size_t> sweep_ev;
   size_t nev = 0;
   int64_t tier_launches[gsl::kNumTiers] = {0}, tier_sparse[gsl::kNumTiers] = {0};
@@ -480,11 +483,22 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
         if ((rc = rec(nev++))) return rc;
       }
       if (t == gsl::kHubTier) {
+        // Tier-9 timing covers hub_insert only; the scan / decide / mark
+        // kernels are timed as ms_hub_finish.
         s.hub_pool_dirty = true;
-        for (auto &bt : s.hub_batches)
-          HIP_TRY(gsl::launch_hub_sweep(a, g_list, s.hub_chunk_start, s.hub_tab_start, s.hub_tchunk_start,
-                                        s.h_chunk.data(), s.h_tchunk.data(), s.hub_pool, s.hub_best,
-                                        s.hub_rowsum, bt.first, bt.second, st));
+        for (size_t bi = 0; bi < s.hub_batches.size(); ++bi) {
+          const auto &bt = s.hub_batches[bi];
+          for (int stage = 0; stage < 2; ++stage) {
+            if (o.timing && (bi > 0 || stage > 0)) {
+              hub_finish_ev.push_back({stage == 0 ? 0 : 1, nev});
+              if ((rc = rec(nev++))) return rc;
+            }
+            HIP_TRY(gsl::launch_hub_sweep(a, g_list, s.hub_chunk_start, s.hub_tab_start,
+                                          s.hub_tchunk_start, s.h_chunk.data(), s.h_tchunk.data(),
+                                          s.hub_pool, s.hub_best, s.hub_rowsum, bt.first, bt.second,
+                                          stage, st));
+          }
+        }
       } else {
         HIP_TRY(gsl::launch_sweep_tier(t, a, g_list, plan.tier_start[t], cnt, &grids.g[t], st));
       }
@@ -563,7 +577,16 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
       stats->ms_sweeps = elapsed(s.ev[1], s.ev[2]);
       stats->ms_split = elapsed(s.ev[2], s.ev[3]);
       stats->ms_total = elapsed(s.ev[0], s.ev[3]);
+      // Each recorded launch spans its start event to the next event; a hub
+      // segment of kind 1 (finish) counts towards ms_hub_finish instead.
       for (const Launch &l : launches) stats->ms_tier[l.tier] += elapsed(s.pool[l.ev], s.pool[l.ev + 1]);
+      for (const Launch &l : hub_finish_ev) {
+        const float ms = elapsed(s.pool[l.ev], s.pool[l.ev + 1]);
+        if (l.tier == 1)
+          stats->ms_hub_finish += ms;
+        else
+          stats->ms_tier[gsl::kHubTier] += ms;
+      }
       for (size_t k = 0; k < sweep_ev.size() && k < GSL_STATS_MAX_ITERS; ++k) {
         const size_t end = k + 1 < sweep_ev.size() ? sweep_ev[k + 1] - 1 : nev - 1;
         stats->ms_sweep[k] = elapsed(s.pool[sweep_ev[k]], s.pool[end]);

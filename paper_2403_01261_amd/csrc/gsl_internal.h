@@ -85,7 +85,8 @@ hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, const int64
                             const int64_t *tab_start, const int64_t *tchunk_start,
                             const int64_t *chunk_start_h, const int64_t *tchunk_start_h,
                             unsigned long long *tab, unsigned long long *best,
-                            unsigned long long *rowsum, int64_t k0, int64_t k1, hipStream_t s);
+                            unsigned long long *rowsum, int64_t k0, int64_t k1, int stage,
+                            hipStream_t s);
 hipError_t launch_apply(int32_t *C, const int32_t *Cn, uint8_t *chg, uint8_t *act_clear,
                         int64_t n, hipStream_t s);
 hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s);

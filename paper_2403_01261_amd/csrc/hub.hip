@@ -281,18 +281,23 @@ hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H,
   return hipGetLastError();
 }
 
-// Runs the four hub kernels for hubs [k0, k1).  Host arrays give the prefix
-// sums so grid sizes are known without a device round trip.
+// The hub kernels for hubs [k0, k1): stage 0 is hub_insert, stage 1 the
+// scan, decision and marking.  Host arrays give the prefix sums so grid sizes
+// are known without a device round trip.
 hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, const int64_t *chunk_start,
                             const int64_t *tab_start, const int64_t *tchunk_start,
                             const int64_t *chunk_start_h, const int64_t *tchunk_start_h,
                             unsigned long long *tab, unsigned long long *best,
-                            unsigned long long *rowsum, int64_t k0, int64_t k1, hipStream_t s) {
+                            unsigned long long *rowsum, int64_t k0, int64_t k1, int stage,
+                            hipStream_t s) {
   if (k1 <= k0) return hipSuccess;
   HubArgs h{hubs, chunk_start, tab_start, tchunk_start, tab, best, rowsum, k0, k1};
   const int64_t chunks = chunk_start_h[k1] - chunk_start_h[k0];
   const int64_t tchunks = tchunk_start_h[k1] - tchunk_start_h[k0];
-  hub_insert<<<(unsigned)chunks, kHubBlock, 0, s>>>(a, h);
+  if (stage == 0) {
+    hub_insert<<<(unsigned)chunks, kHubBlock, 0, s>>>(a, h);
+    return hipGetLastError();
+  }
   hub_scan<<<(unsigned)tchunks, kScanBlock, 0, s>>>(a, h);
   hub_decide<<<(unsigned)((k1 - k0 + 255) / 256), 256, 0, s>>>(a, h);
   if (a.mark) hub_mark<<<(unsigned)chunks, kHubBlock, 0, s>>>(a, h);

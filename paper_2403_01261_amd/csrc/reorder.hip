@@ -111,8 +111,9 @@ __device__ __forceinline__ void first_entry(const CopyArgs &c, int32_t v, int64_
 }
 
 // Rows [first, first + count) of the new numbering, G lanes per row (G <= 64
-// or the whole block).
-template <int G, int BLOCK>
+// or the whole block), each lane owning at most K entries of the row (the
+// tier bound is G * K) with all its loads issued before any use.
+template <int G, int BLOCK, int K>
 __global__ __launch_bounds__(BLOCK) void reorder_rows(CopyArgs c, int64_t first, int64_t count) {
   constexpr int GPB = BLOCK / G;
   __shared__ unsigned long long red[BLOCK / kWave], red2[BLOCK / kWave];
@@ -121,15 +122,36 @@ __global__ __launch_bounds__(BLOCK) void reorder_rows(CopyArgs c, int64_t first,
   for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
     const int64_t idx = base + g;
     unsigned long long best = 0, rowsum = 0;
-    int64_t p = -1;
+    int64_t p = -1, b = 0, e = 0, b2 = 0;
+    int32_t v = -1;
     if (idx < count) {
       p = first + idx;
-      const int32_t v = c.list[p];
-      const int64_t b = c.off[v], e = c.off[v + 1], b2 = c.off2[p];
-      for (int64_t q = b + lane; q < e; q += G) {
-        c.cols2[b2 + (q - b)] = c.old2new[c.cols[q]];
-        if (c.w) c.w2[b2 + (q - b)] = c.w[q];
-        first_entry(c, v, q, e, best, rowsum, unsorted);
+      v = c.list[p];
+      b = c.off[v];
+      e = c.off[v + 1];
+      b2 = c.off2[p];
+    }
+    int32_t j[K], jn[K];
+    uint32_t w[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t q = b + lane + (int64_t)k * G;
+      const bool in = q < e;
+      j[k] = in ? c.cols[q] : -1;
+      jn[k] = in && q + 1 < e ? c.cols[q + 1] : 0x7fffffff;
+      w[k] = in ? (c.w ? c.w[q] : 1u) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (j[k] < 0) continue;
+      const int64_t q = b + lane + (int64_t)k * G;
+      c.cols2[b2 + (q - b)] = c.old2new[j[k]];
+      if (c.w) c.w2[b2 + (q - b)] = w[k];
+      unsorted |= jn[k] <= j[k];
+      rowsum += w[k];
+      if (j[k] != v) {
+        const unsigned long long key = argmax_key((uint32_t)j[k], w[k]);
+        best = key > best ? key : best;
       }
     }
     if constexpr (G <= 64) {
@@ -145,9 +167,9 @@ __global__ __launch_bounds__(BLOCK) void reorder_rows(CopyArgs c, int64_t first,
       __syncthreads();
       best = 0;
       rowsum = 0;
-      for (int w = 0; w < BLOCK / kWave; ++w) {
-        best = red[w] > best ? red[w] : best;
-        rowsum += red2[w];
+      for (int ww = 0; ww < BLOCK / kWave; ++ww) {
+        best = red[ww] > best ? red[ww] : best;
+        rowsum += red2[ww];
       }
       __syncthreads();
     }
@@ -288,13 +310,21 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
     const int64_t cnt = tier_count_h[t], first = tier_start_h[t];
     if (cnt <= 0) continue;
     if (t == 1)
-      reorder_rows<1, 256><<<grid_of(cnt, 256, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t <= 3)
-      reorder_rows<16, 256><<<grid_of(cnt, 16, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t <= 6)
-      reorder_rows<64, 256><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t <= 8)
-      reorder_rows<1024, 1024><<<grid_of(cnt, 1, kCap), 1024, 0, s>>>(c, first, cnt);
+      reorder_rows<1, 256, 8><<<grid_of(cnt, 256, kCap), 256, 0, s>>>(c, first, cnt);
+    else if (t == 2)
+      reorder_rows<8, 256, 2><<<grid_of(cnt, 32, kCap), 256, 0, s>>>(c, first, cnt);
+    else if (t == 3)
+      reorder_rows<16, 256, 2><<<grid_of(cnt, 16, kCap), 256, 0, s>>>(c, first, cnt);
+    else if (t == 4)
+      reorder_rows<32, 256, 2><<<grid_of(cnt, 8, kCap), 256, 0, s>>>(c, first, cnt);
+    else if (t == 5)
+      reorder_rows<64, 256, 2><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
+    else if (t == 6)
+      reorder_rows<64, 256, 8><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
+    else if (t == 7)
+      reorder_rows<256, 256, 8><<<grid_of(cnt, 1, kCap), 256, 0, s>>>(c, first, cnt);
+    else if (t == 8)
+      reorder_rows<1024, 1024, 8><<<grid_of(cnt, 1, kCap), 1024, 0, s>>>(c, first, cnt);
     else if (hub_chunks > 0)
       reorder_hub_rows<<<(unsigned)hub_chunks, 1024, 0, s>>>(c, hub_chunk_start, cnt);
   }
