@@ -42,8 +42,8 @@ WORKLOAD_TEXT = {
 # arguments in order).
 TIER_KERNEL = {1: "sweep_thread<8>", 2: "sweep_lds<8, 5, 256, 2>", 3: "sweep_lds<16, 6, 256, 2>",
                4: "sweep_lds<32, 7, 256, 2>", 5: "sweep_lds<64, 8, 256, 2>",
-               6: "sweep_lds<64, 10, 256, 8>", 7: "sweep_lds<256, 12, 256, 8>",
-               8: "sweep_lds<1024, 14, 1024, 8>", 9: "hub_insert"}
+               6: "sweep_lds<64, 10, 256, 8>", 7: "sweep_lds<256, 12, 256, 8>", 8: "hub_insert"}
+NUM_TIERS = 9
 
 
 def log(*a):
@@ -251,8 +251,8 @@ def main(argv=None):
     log("timed %d steps: %.3f ms/step, %.3g edges/s" % (args.steps, ms_per_step, value))
 
     # Dominant sweep kernel over the timed steps.
-    ms_tier = [sum(st["tiers"][t]["ms"] for st in stats) for t in range(10)]
-    dom = max(range(1, 10), key=lambda t: ms_tier[t])
+    ms_tier = [sum(st["tiers"][t]["ms"] for st in stats) for t in range(NUM_TIERS)]
+    dom = max(range(1, NUM_TIERS), key=lambda t: ms_tier[t])
     agg = {key: sum(st["tiers"][dom][key] for st in stats)
            for key in ("vertices", "launches", "processed", "edges", "changed", "marked",
                        "sparse_launches")}
@@ -271,7 +271,7 @@ def main(argv=None):
     # Whole sweep phase (all tier kernels + apply) for context.
     sweep_ms = sum(st["ms_sweeps"] for st in stats) / len(stats)
     sweep_bytes = sum(tier_bytes(dict(st["tiers"][t], vertices=st["tiers"][t]["vertices"]), weighted)
-                      for st in stats for t in range(1, 10)) / len(stats)
+                      for st in stats for t in range(1, NUM_TIERS)) / len(stats)
     last = stats[-1]
     phases = {"ms_plan": round(sum(s["ms_plan"] for s in stats) / len(stats), 3),
               "ms_sweeps": round(sweep_ms, 3),

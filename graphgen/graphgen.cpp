@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <utility>
 #include <vector>
@@ -79,6 +80,20 @@ inline uint32_t pair_weight(uint64_t seed, int64_t u, int64_t v, uint32_t wmin, 
   return (uint32_t)((uint64_t)wmin + h % span);
 }
 
+// Progress lines on stderr (GRAPHGEN_VERBOSE=1): long generations print each
+// phase as it ends so a supervising process sees activity.
+inline bool verbose() {
+  static const bool v = getenv("GRAPHGEN_VERBOSE") && getenv("GRAPHGEN_VERBOSE")[0] == '1';
+  return v;
+}
+inline double now_s() { return omp_get_wtime(); }
+inline void progress(const char *what, double t0) {
+  if (verbose()) {
+    fprintf(stderr, "graphgen: %s done at %.1f s\n", what, now_s() - t0);
+    fflush(stderr);
+  }
+}
+
 inline void atomic_inc(int64_t *p) { __atomic_fetch_add(p, (int64_t)1, __ATOMIC_RELAXED); }
 inline int64_t atomic_fetch_inc(int64_t *p) { return __atomic_fetch_add(p, (int64_t)1, __ATOMIC_RELAXED); }
 
@@ -121,6 +136,7 @@ int build_sym_csr(int64_t n, int64_t nchunks, Src src, uint64_t wseed, uint32_t 
   memset(out, 0, sizeof(*out));
   out->n = n;
   out->num_graphs = 1;
+  const double t0 = now_s();
   int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
   if (!cnt) return -2;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -131,6 +147,7 @@ int build_sym_csr(int64_t n, int64_t nchunks, Src src, uint64_t wseed, uint32_t 
       atomic_inc(&cnt[v]);
     });
   }
+  progress("degree count", t0);
   // Exclusive prefix sum -> row starts (pre-dedup).
   int64_t *start = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
   if (!start) { free(cnt); return -2; }
@@ -151,6 +168,7 @@ int build_sym_csr(int64_t n, int64_t nchunks, Src src, uint64_t wseed, uint32_t 
       tmp[atomic_fetch_inc(&cnt[v])] = (int32_t)u;
     });
   }
+  progress("scatter", t0);
   // Sort and deduplicate each row; cnt[i] := new degree.
 #pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t i = 0; i < n; ++i) {
@@ -158,6 +176,7 @@ int build_sym_csr(int64_t n, int64_t nchunks, Src src, uint64_t wseed, uint32_t 
     std::sort(b, e);
     cnt[i] = std::unique(b, e) - b;
   }
+  progress("row sort", t0);
   int64_t *off = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
   if (!off) { free(cnt); free(start); free(tmp); return -2; }
   acc = 0;
@@ -181,6 +200,7 @@ int build_sym_csr(int64_t n, int64_t nchunks, Src src, uint64_t wseed, uint32_t 
   free(cnt);
   free(start);
   free(tmp);
+  progress("compaction", t0);
   out->nnz = nnz;
   out->offsets = off;
   out->cols = cols;

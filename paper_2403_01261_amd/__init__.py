@@ -61,11 +61,13 @@ _lib = None
 _VP = ctypes.c_void_p
 
 
-def load(path: str = LIB_PATH):
-    """Loads the native library (raises if it was not built)."""
+def load(path: str = None):
+    """Loads the native library (raises if it was not built).  The path
+    defaults to the in-tree build; GSL_LPA_LIB may name another build."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("GSL_LPA_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError("libgsl_lpa.so not found at %s: build it with "
                           "`python -c 'import __graft_entry__ as g; g.build()'`" % path)

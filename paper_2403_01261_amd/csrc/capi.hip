@@ -58,12 +58,13 @@ struct Scratch {
   Counters *ctr_host = nullptr;  // pinned mirror (with the per-sweep arrays)
   // hub tier layout (prefix sums over the hubs of the current graph)
   int64_t hub_cap = 0;
-  int64_t *hub_chunk_start = nullptr, *hub_tab_start = nullptr, *hub_tchunk_start = nullptr;
+  int64_t *hub_chunk_start = nullptr, *hub_part_start = nullptr, *hub_hist_start = nullptr;
   unsigned long long *hub_best = nullptr, *hub_rowsum = nullptr;
-  unsigned long long *hub_pool = nullptr;
-  int64_t hub_pool_slots = 0;
-  bool hub_pool_dirty = false;  // a call stopped while hub tables may hold entries
-  std::vector<int64_t> h_chunk, h_tab, h_tchunk;  // host copies
+  unsigned long long *hub_staging = nullptr;  // (label, sum) pairs of one batch
+  int32_t *hub_hist = nullptr;                // partition bounds of one batch
+  int64_t hub_staging_cap = 0, hub_hist_cap = 0;
+  std::vector<int64_t> h_chunk, h_part, h_hist;  // host copies of the prefix sums
+  std::vector<int> hub_max_parts;                // largest partition count per batch
   std::vector<std::pair<int64_t, int64_t>> hub_batches;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_reorder = nullptr;
@@ -103,11 +104,12 @@ void free_scratch(Scratch &s) {
   hipFree(s.tier_part);
   hipFree(s.ctr);
   hipFree(s.hub_chunk_start);
-  hipFree(s.hub_tab_start);
-  hipFree(s.hub_tchunk_start);
+  hipFree(s.hub_part_start);
+  hipFree(s.hub_hist_start);
   hipFree(s.hub_best);
   hipFree(s.hub_rowsum);
-  hipFree(s.hub_pool);
+  hipFree(s.hub_staging);
+  hipFree(s.hub_hist);
   if (s.ctr_host) hipHostFree(s.ctr_host);
   for (auto &e : s.ev)
     if (e) hipEventDestroy(e);
@@ -220,22 +222,21 @@ int run_plan(Scratch &s, const int64_t *offsets, int64_t n, hipStream_t st) {
 }
 
 // Builds the hub layout of the current graph and splits the hubs into
-// batches whose global tables fit in the pool (kHubPoolBytes, or the largest
-// single table if that is bigger).
+// batches whose staging area fits kHubStagingBytes (at least one hub each).
 int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_t H, hipStream_t st) {
   s.hub_batches.clear();
   if (H <= 0) return GSL_OK;
   if (H > s.hub_cap) {
     hipFree(s.hub_chunk_start);
-    hipFree(s.hub_tab_start);
-    hipFree(s.hub_tchunk_start);
+    hipFree(s.hub_part_start);
+    hipFree(s.hub_hist_start);
     hipFree(s.hub_best);
     hipFree(s.hub_rowsum);
-    s.hub_chunk_start = s.hub_tab_start = s.hub_tchunk_start = nullptr;
+    s.hub_chunk_start = s.hub_part_start = s.hub_hist_start = nullptr;
     s.hub_best = s.hub_rowsum = nullptr;
     s.hub_cap = 0;
-    if (dmalloc(&s.hub_chunk_start, H + 1) != hipSuccess || dmalloc(&s.hub_tab_start, H + 1) != hipSuccess ||
-        dmalloc(&s.hub_tchunk_start, H + 1) != hipSuccess || dmalloc(&s.hub_best, H) != hipSuccess ||
+    if (dmalloc(&s.hub_chunk_start, H + 1) != hipSuccess || dmalloc(&s.hub_part_start, H + 1) != hipSuccess ||
+        dmalloc(&s.hub_hist_start, H + 1) != hipSuccess || dmalloc(&s.hub_best, H) != hipSuccess ||
         dmalloc(&s.hub_rowsum, H) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSL_ENOMEM, "hub layout allocation failed");
@@ -244,48 +245,61 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
   }
   HIP_TRY(hipMemsetAsync(s.hub_best, 0, (size_t)H * sizeof(unsigned long long), st));
   HIP_TRY(hipMemsetAsync(s.hub_rowsum, 0, (size_t)H * sizeof(unsigned long long), st));
-  HIP_TRY(gsl::launch_hub_layout(offsets, hubs, H, s.hub_chunk_start, s.hub_tab_start,
-                                 s.hub_tchunk_start, st));
+  gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
+  HIP_TRY(gsl::launch_hub_layout(offsets, hubs, H, L, st));
   s.h_chunk.resize((size_t)H + 1);
-  s.h_tab.resize((size_t)H + 1);
-  s.h_tchunk.resize((size_t)H + 1);
+  s.h_part.resize((size_t)H + 1);
+  s.h_hist.resize((size_t)H + 1);
   HIP_TRY(hipMemcpyAsync(s.h_chunk.data(), s.hub_chunk_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(s.h_tab.data(), s.hub_tab_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(s.h_tchunk.data(), s.hub_tchunk_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s.h_part.data(), s.hub_part_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s.h_hist.data(), s.hub_hist_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  constexpr int64_t kHubPoolBytes = (int64_t)2 << 30;
-  int64_t cap = kHubPoolBytes / 8, need = 0;
-  for (int64_t k = 0; k < H; ++k) {
-    const int64_t sz = s.h_tab[(size_t)k + 1] - s.h_tab[(size_t)k];
-    if (sz > cap) cap = sz;
-  }
+  constexpr int64_t kHubStagingBytes = (int64_t)4 << 30;
+  const int64_t chunk_cap = kHubStagingBytes / ((int64_t)gsl::kHubChunk * 8);
   int64_t k0 = 0;
   for (int64_t k = 0; k < H; ++k) {
-    if (s.h_tab[(size_t)k + 1] - s.h_tab[(size_t)k0] > cap) {
+    if (k > k0 && s.h_chunk[(size_t)k + 1] - s.h_chunk[(size_t)k0] > chunk_cap) {
       s.hub_batches.push_back({k0, k});
       k0 = k;
     }
   }
   s.hub_batches.push_back({k0, H});
+  s.hub_max_parts.clear();
   for (auto &bt : s.hub_batches) {
-    const int64_t sz = s.h_tab[(size_t)bt.second] - s.h_tab[(size_t)bt.first];
-    if (sz > need) need = sz;
-  }
-  if (s.hub_pool_dirty && s.hub_pool) {
-    HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_pool), 0xFFFFFFFF00000000ull,
-                                 s.hub_pool_slots, st));
-    s.hub_pool_dirty = false;
-  }
-  if (need > s.hub_pool_slots) {
-    hipFree(s.hub_pool);
-    s.hub_pool = nullptr;
-    s.hub_pool_slots = 0;
-    if (dmalloc(&s.hub_pool, need) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(GSL_ENOMEM, "hub table pool (%lld slots) allocation failed", (long long)need);
+    int64_t m = 1;
+    for (int64_t k = bt.first; k < bt.second; ++k) {
+      const int64_t P = s.h_part[(size_t)k + 1] - s.h_part[(size_t)k];
+      m = P > m ? P : m;
     }
-    HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_pool), 0xFFFFFFFF00000000ull, need, st));
-    s.hub_pool_slots = need;
+    s.hub_max_parts.push_back((int)m);
+  }
+  int64_t need_chunks = 0, need_hist = 0;
+  for (auto &bt : s.hub_batches) {
+    const int64_t c = s.h_chunk[(size_t)bt.second] - s.h_chunk[(size_t)bt.first];
+    const int64_t h = s.h_hist[(size_t)bt.second] - s.h_hist[(size_t)bt.first];
+    need_chunks = c > need_chunks ? c : need_chunks;
+    need_hist = h > need_hist ? h : need_hist;
+  }
+  const int64_t need_staging = need_chunks * gsl::kHubChunk;
+  if (need_staging > s.hub_staging_cap) {
+    hipFree(s.hub_staging);
+    s.hub_staging = nullptr;
+    s.hub_staging_cap = 0;
+    if (dmalloc(&s.hub_staging, need_staging) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "hub staging allocation (%lld pairs) failed", (long long)need_staging);
+    }
+    s.hub_staging_cap = need_staging;
+  }
+  if (need_hist > s.hub_hist_cap) {
+    hipFree(s.hub_hist);
+    s.hub_hist = nullptr;
+    s.hub_hist_cap = 0;
+    if (dmalloc(&s.hub_hist, need_hist) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "hub partition records allocation failed");
+    }
+    s.hub_hist_cap = need_hist;
   }
   return GSL_OK;
 }
@@ -363,7 +377,7 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   if ((rc = run_plan(s, offsets, n, st))) return rc;
   Counters plan = *s.ctr_host;
   // Tier t is the id range [tier_start[t], +tier_count[t]) of s.list; hubs
-  // (tier 9) come first, isolated vertices (tier 0) last.
+  // (tier 8) come first, isolated vertices (tier 0) last.
   const int64_t H = plan.tier_count[gsl::kHubTier];
   if ((rc = prepare_hubs(s, offsets, s.list, H, st))) return rc;
   // Renumbered layout: chosen when vertices of degree > 64 hold most entries
@@ -483,9 +497,9 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
         if ((rc = rec(nev++))) return rc;
       }
       if (t == gsl::kHubTier) {
-        // Tier-9 timing covers hub_insert only; the scan / decide / mark
+        // Tier-9 timing covers hub_insert only; the merge / decide / mark
         // kernels are timed as ms_hub_finish.
-        s.hub_pool_dirty = true;
+        const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
         for (size_t bi = 0; bi < s.hub_batches.size(); ++bi) {
           const auto &bt = s.hub_batches[bi];
           for (int stage = 0; stage < 2; ++stage) {
@@ -493,10 +507,9 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
               hub_finish_ev.push_back({stage == 0 ? 0 : 1, nev});
               if ((rc = rec(nev++))) return rc;
             }
-            HIP_TRY(gsl::launch_hub_sweep(a, g_list, s.hub_chunk_start, s.hub_tab_start,
-                                          s.hub_tchunk_start, s.h_chunk.data(), s.h_tchunk.data(),
-                                          s.hub_pool, s.hub_best, s.hub_rowsum, bt.first, bt.second,
-                                          stage, st));
+            HIP_TRY(gsl::launch_hub_sweep(a, g_list, L, s.h_chunk.data(), s.h_part.data(),
+                                          s.hub_staging, s.hub_hist, s.hub_best, s.hub_rowsum,
+                                          bt.first, bt.second, s.hub_max_parts[bi], stage, st));
           }
         }
       } else {
@@ -517,7 +530,6 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
     HIP_TRY(hipStreamSynchronize(st));
     if (stats && it < GSL_STATS_MAX_ITERS) stats->marked[it] = mark ? 1 : 0;
     ++it;
-    s.hub_pool_dirty = false;  // every hub table was cleared by the sweep that just finished
     if (dn_host[1]) {
       overflow = 1;
       break;

@@ -10,15 +10,16 @@ namespace gsl {
 // ----------------------------------------------------------------------------
 // Degree tiers.  Every vertex with degree d > 0 is processed by the kernel of
 // the smallest tier whose bound is >= d; tier 0 holds isolated vertices, which
-// never change label and are not listed.
+// never change label.
 //   tier 1        : one thread per vertex, labels held in registers
 //   tiers 2 - 6   : a group of G lanes per vertex, LDS hash table per group
-//   tiers 7, 8    : one workgroup per vertex, LDS hash table per workgroup
-//   tier 9 (hub)  : one workgroup per vertex, hash table in global memory
+//   tier 7        : one workgroup per vertex, LDS hash table per workgroup
+//   tier 8 (hub)  : rows cut into chunks, one workgroup per chunk, partial
+//                   sums merged per hash partition (hub.hip)
 // ----------------------------------------------------------------------------
-constexpr int kNumTiers = 10;
-constexpr int kHubTier = 9;
-constexpr int64_t kTierMaxDeg[kNumTiers] = {0, 8, 16, 32, 64, 128, 512, 2048, 8192,
+constexpr int kNumTiers = 9;
+constexpr int kHubTier = 8;
+constexpr int64_t kTierMaxDeg[kNumTiers] = {0, 8, 16, 32, 64, 128, 512, 2048,
                                             (int64_t)0x7fffffffffffffffLL};
 
 // Device-side counters; one block of memory zeroed at the start of every call.
@@ -79,14 +80,22 @@ hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
                                 unsigned long long (*tier_stats)[4], unsigned long long *dn,
                                 unsigned long long *processed, unsigned long long *edges,
                                 unsigned long long *overflow, hipStream_t s);
-hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, int64_t *chunk_start,
-                             int64_t *tab_start, int64_t *tchunk_start, hipStream_t s);
-hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, const int64_t *chunk_start,
-                            const int64_t *tab_start, const int64_t *tchunk_start,
-                            const int64_t *chunk_start_h, const int64_t *tchunk_start_h,
-                            unsigned long long *tab, unsigned long long *best,
-                            unsigned long long *rowsum, int64_t k0, int64_t k1, int stage,
-                            hipStream_t s);
+// Hub tier layout: rows cut into chunks of kHubChunk entries; prefix sums
+// over the hubs (H + 1 entries each) of their chunks, hash partitions and
+// partition-boundary records (chunks * (partitions + 1)).
+constexpr int kHubChunk = 2048;
+struct HubLayout {
+  int64_t *chunk_start;
+  int64_t *part_start;
+  int64_t *hist_start;
+};
+hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, HubLayout L,
+                             hipStream_t s);
+hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L,
+                            const int64_t *chunk_start_h, const int64_t *part_start_h,
+                            unsigned long long *staging, int32_t *hist, unsigned long long *best,
+                            unsigned long long *rowsum, int64_t k0, int64_t k1, int max_parts,
+                            int stage, hipStream_t s);
 hipError_t launch_apply(int32_t *C, const int32_t *Cn, uint8_t *chg, uint8_t *act_clear,
                         int64_t n, hipStream_t s);
 hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s);

@@ -1,19 +1,24 @@
-// Hub tier of the sweep: vertices whose row is longer than one workgroup's LDS
-// table can take (degree > 8192).
+// Hub tier of the sweep: vertices of degree > 2048, too long for one
+// workgroup's LDS table at good occupancy.
 //
 // A hub row is cut into chunks of kHubChunk entries and every chunk gets its
-// own workgroup, so one hub keeps many compute units busy:
-//   hub_insert : sums the chunk's labels in an LDS table, then adds each
-//                distinct (label, sum) into the hub's table in global memory
-//                (agent-scope atomics; the LDS pass removes repeated labels
-//                before they reach global memory);
-//   hub_scan   : reads every hub table in chunks of kScanChunk slots, clears
-//                them and folds the packed argmax keys into hub_best[k];
-//   hub_decide : one thread per hub compares the winning label with C[v] and
-//                records the change;
+// own workgroup, so one hub keeps many compute units busy.  Partial sums meet
+// in a staging area instead of a shared hash table, so no global atomics are
+// spent per label:
+//   hub_insert : sums the chunk's labels in an LDS table, sorts the distinct
+//                (label, sum) pairs by a hash partition of the label (P_k
+//                partitions per hub) and stores them, with the partition
+//                boundaries, in the chunk's own staging segment;
+//   hub_merge  : one workgroup per (hub, partition) sums that partition's pairs
+//                from every chunk of the hub in an LDS table and folds the
+//                packed argmax key into hub_best[k];
+//   hub_decide : one thread per hub compares the winner with C[v];
 //   hub_mark   : marks the neighbours of changed hubs, chunk by chunk.
-// The per-hub layout (chunk, table and scan-chunk prefix sums) is built once
-// per call by hub_sizes + hub_scan_prefix.
+// P_k = ceil(d_k / 2048) (at most kMaxParts), so a partition expects at most
+// 2048 distinct labels; a merge table holds 4096 slots and a partition that
+// still overflows is redone in 2, 4, ... sub-passes that each keep a hashed
+// share of the labels, so every input is handled exactly.  Tables stay at
+// 32 KB so several workgroups share a compute unit.
 #include "device_common.h"
 #include "gsl_internal.h"
 
@@ -21,12 +26,25 @@ namespace gsl {
 
 namespace {
 
-constexpr int kHubBlock = 1024;
-constexpr int kHubK = 8;
-constexpr int kHubChunk = kHubBlock * kHubK;  // row entries per insert workgroup
-constexpr int kHubLog2S = 14;                 // LDS slots: 2 per chunk entry
-constexpr int kScanBlock = 256;
-constexpr int kScanChunk = kScanBlock * 16;   // table slots per scan workgroup
+constexpr int kHubBlock = 256;
+constexpr int kHubK = kHubChunk / kHubBlock;  // row entries per lane
+constexpr int kTabLog2 = 12;                  // 4096 LDS slots (2 per chunk entry)
+constexpr int kTabSlots = 1 << kTabLog2;
+constexpr int kMaxParts = 8192;
+constexpr int kPartSize = 2048;               // expected distinct labels per partition
+constexpr int kMergeBlock = 256;
+// Claims before a merge pass gives up and the partition is split into
+// sub-passes (a build may lower it with -DGSL_HUB_MERGE_CAP=... to exercise
+// that path).
+#ifndef GSL_HUB_MERGE_CAP
+#define GSL_HUB_MERGE_CAP (4096 - 256 - 1)
+#endif
+constexpr int kMergeCap = GSL_HUB_MERGE_CAP;
+static_assert(kMergeCap > 0 && kMergeCap + kMergeBlock < kTabSlots, "a free slot must always remain");
+constexpr int kChunkGroup = 1024;                       // chunks whose slices one merge step indexes
+
+static_assert(kHubChunk % kHubBlock == 0, "chunk must split evenly over the block");
+static_assert(2 * kHubChunk <= kTabSlots, "insert table must hold every chunk entry");
 
 // Largest k with start[k] <= x, for k in [lo, hi).
 __device__ __forceinline__ int64_t owner(const int64_t *start, int64_t lo, int64_t hi, int64_t x) {
@@ -40,38 +58,38 @@ __device__ __forceinline__ int64_t owner(const int64_t *start, int64_t lo, int64
   return lo;
 }
 
-// Adds (label, w) to a global table, probing linearly from slot h.
-__device__ __forceinline__ void global_add_from(unsigned long long *tab, uint32_t mask, uint32_t h,
-                                                uint32_t label, uint32_t w) {
-  const unsigned long long mine = ((unsigned long long)label << 32) | w;
-  for (;;) {
-    unsigned long long expected = kEmptySlot;
-    if (__hip_atomic_compare_exchange_strong(&tab[h], &expected, mine, __ATOMIC_RELAXED,
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      return;
-    if ((uint32_t)(expected >> 32) == label) {
-      __hip_atomic_fetch_add(&tab[h], (unsigned long long)w, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      return;
-    }
-    h = (h + 1u) & mask;
-  }
+__device__ __forceinline__ int hub_parts(int64_t d) {
+  int64_t p = (d + kPartSize - 1) / kPartSize;
+  return (int)(p < 1 ? 1 : (p > kMaxParts ? kMaxParts : p));
 }
 
-__device__ __forceinline__ int hub_log2(int64_t d) { return ceil_log2((uint64_t)(2 * (d > 0 ? d : 1))); }
+// Label mixers independent of the Fibonacci slot hash (murmur3 finalizer).
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+__device__ __forceinline__ int part_of(uint32_t label, int P) {
+  return (int)(((uint64_t)mix32(label) * (uint64_t)P) >> 32);
+}
+__device__ __forceinline__ uint32_t sub_of(uint32_t label) { return mix32(label ^ 0x9e3779b9u); }
 
-// Per hub: insert chunks, table slots, scan chunks.
+// Per hub: insert chunks, partitions, histogram entries (chunks * (P + 1)).
 __global__ void hub_sizes(const int64_t *__restrict__ off, const int32_t *__restrict__ hubs, int64_t H,
-                          int64_t *__restrict__ chunks, int64_t *__restrict__ slots,
-                          int64_t *__restrict__ tchunks) {
+                          int64_t *__restrict__ chunks, int64_t *__restrict__ parts,
+                          int64_t *__restrict__ hist) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= H) return;
   const int32_t v = hubs[k];
   const int64_t d = off[v + 1] - off[v];
-  const int64_t s = (int64_t)1 << hub_log2(d);
-  chunks[k] = (d + kHubChunk - 1) / kHubChunk;
-  slots[k] = s;
-  tchunks[k] = (s + kScanChunk - 1) / kScanChunk;
+  const int64_t nc = (d + kHubChunk - 1) / kHubChunk;
+  const int P = hub_parts(d);
+  chunks[k] = nc;
+  parts[k] = P;
+  hist[k] = nc * (P + 1);
 }
 
 // Exclusive prefix sums of three arrays of H entries (in place, entry H gets
@@ -105,30 +123,61 @@ __global__ __launch_bounds__(1024) void hub_scan_prefix(int64_t *a0, int64_t *a1
 }
 
 struct HubArgs {
-  const int32_t *hubs;        // hub vertex ids (NULL: hub k is vertex k)
-  const int64_t *chunk_start; // [H+1]
-  const int64_t *tab_start;   // [H+1]
-  const int64_t *tchunk_start;// [H+1]
-  unsigned long long *tab;    // table pool; hub k of the batch at tab_start[k] - tab_start[k0]
-  unsigned long long *best;   // [H] packed argmax keys
-  unsigned long long *rowsum; // [H] summed row weights
-  int64_t k0, k1;             // hubs of this batch
+  const int32_t *hubs;           // hub vertex ids (NULL: hub k is vertex k)
+  HubLayout L;                   // [H+1] prefix arrays
+  unsigned long long *staging;   // chunk c of the batch at (c - chunk_start[k0]) * kHubChunk
+  int32_t *hist;                 // partition bounds, relative to hist_start[k0]
+  unsigned long long *best;      // [H] packed argmax keys
+  unsigned long long *rowsum;    // [H] summed row weights
+  int64_t k0, k1;                // hubs of this batch
 };
 
+// Exclusive scan of a[0..n) (n <= kMaxParts) in LDS by the whole block;
+// a[n] receives the total.  `part` needs blockDim.x entries.  Ends with a
+// barrier.
+template <int BLOCK>
+__device__ void block_exclusive_scan(int *a, int n, int *part) {
+  const int per = (n + BLOCK - 1) / BLOCK;
+  const int lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += a[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < BLOCK; o <<= 1) {
+    const int y = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  int run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+  for (int i = lo; i < hi; ++i) {
+    const int c = a[i];
+    a[i] = run;
+    run += c;
+  }
+  if (threadIdx.x == BLOCK - 1) a[n] = part[BLOCK - 1];
+  __syncthreads();
+}
+
+// Dynamic LDS: the partition histogram, (largest P of the batch + 1) ints.
 __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) {
-  __shared__ unsigned long long tab[1 << kHubLog2S];
+  __shared__ unsigned long long tab[kTabSlots];
+  extern __shared__ int hist[];
+  __shared__ int scan_part[kHubBlock];
   __shared__ unsigned long long red[kHubBlock / kWave];
-  const int64_t c = h.chunk_start[h.k0] + blockIdx.x;
-  const int64_t k = owner(h.chunk_start, h.k0, h.k1, c);
+  const int64_t c = h.L.chunk_start[h.k0] + blockIdx.x;
+  const int64_t k = owner(h.L.chunk_start, h.k0, h.k1, c);
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!a.dense && !a.act[v]) return;  // uniform over the block
-  for (int s = threadIdx.x; s < (1 << kHubLog2S); s += kHubBlock) tab[s] = kEmptySlot;
   const int64_t rb = a.off[v], re = a.off[v + 1];
-  const int64_t b = rb + (c - h.chunk_start[k]) * kHubChunk;
+  const int P = hub_parts(re - rb);
+  const int64_t cl = c - h.L.chunk_start[k];
+  const int64_t b = rb + cl * kHubChunk;
   const int64_t e = b + kHubChunk < re ? b + kHubChunk : re;
+  for (int s = threadIdx.x; s < kTabSlots; s += kHubBlock) tab[s] = kEmptySlot;
+  for (int i = threadIdx.x; i <= P; i += kHubBlock) hist[i] = 0;
   int32_t j[kHubK];
   uint32_t wt[kHubK], lab[kHubK];
-  int slot[kHubK];
 #pragma unroll
   for (int q = 0; q < kHubK; ++q) {
     const int64_t p = b + threadIdx.x + (int64_t)q * kHubBlock;
@@ -141,62 +190,110 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
   unsigned long long rs = 0;
 #pragma unroll
   for (int q = 0; q < kHubK; ++q) rs += wt[q];
-  __syncthreads();  // table initialised
+  __syncthreads();  // table and histogram initialised
+  int slot[kHubK];
 #pragma unroll
-  for (int q = 0; q < kHubK; ++q) slot[q] = lab[q] != kNoLabel ? lds_insert(tab, kHubLog2S, lab[q], wt[q]) : -1;
+  for (int q = 0; q < kHubK; ++q) slot[q] = lab[q] != kNoLabel ? lds_insert(tab, kTabLog2, lab[q], wt[q]) : -1;
   __syncthreads();
-  const int log2s = hub_log2(re - rb);
-  const uint32_t gmask = (1u << log2s) - 1u;
-  unsigned long long *gt = h.tab + (h.tab_start[k] - h.tab_start[h.k0]);
-  // All first-probe compare-and-swaps of a thread are issued together; only
-  // the (rare) collisions walk on one by one.
-  unsigned long long x[kHubK], prev[kHubK];
-  uint32_t gh[kHubK];
+  unsigned long long x[kHubK];
+  int pp[kHubK], rank[kHubK];
 #pragma unroll
   for (int q = 0; q < kHubK; ++q) {
-    x[q] = slot[q] >= 0 ? tab[slot[q]] : kEmptySlot;
-    gh[q] = slot_hash((uint32_t)(x[q] >> 32), log2s);
-  }
-#pragma unroll
-  for (int q = 0; q < kHubK; ++q) {
-    prev[q] = kEmptySlot;
-    if (slot[q] >= 0)
-      __hip_atomic_compare_exchange_strong(&gt[gh[q]], &prev[q], x[q], __ATOMIC_RELAXED,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-#pragma unroll
-  for (int q = 0; q < kHubK; ++q) {
-    if (slot[q] < 0 || prev[q] == kEmptySlot) continue;  // claimed on the first probe
-    const uint32_t label = (uint32_t)(x[q] >> 32), w = (uint32_t)x[q];
-    if ((uint32_t)(prev[q] >> 32) == label) {
-      __hip_atomic_fetch_add(&gt[gh[q]], (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      continue;
+    x[q] = 0;
+    pp[q] = 0;
+    rank[q] = 0;
+    if (slot[q] >= 0) {
+      x[q] = tab[slot[q]];
+      pp[q] = part_of((uint32_t)(x[q] >> 32), P);
+      rank[q] = atomicAdd(&hist[pp[q]], 1);
     }
-    global_add_from(gt, gmask, (gh[q] + 1u) & gmask, label, w);
   }
+  __syncthreads();
+  block_exclusive_scan<kHubBlock>(hist, P, scan_part);
+  unsigned long long *stage = h.staging + (c - h.L.chunk_start[h.k0]) * kHubChunk;
+#pragma unroll
+  for (int q = 0; q < kHubK; ++q)
+    if (slot[q] >= 0) stage[hist[pp[q]] + rank[q]] = x[q];
+  int32_t *gh = h.hist + (h.L.hist_start[k] - h.L.hist_start[h.k0]) + cl * (P + 1);
+  for (int i = threadIdx.x; i <= P; i += kHubBlock) gh[i] = hist[i];
   rs = block_sum(rs, red);
   if (threadIdx.x == 0 && rs)
     __hip_atomic_fetch_add(&h.rowsum[k], rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kScanBlock) void hub_scan(SweepArgs a, HubArgs h) {
-  __shared__ unsigned long long red[kScanBlock / kWave];
-  const int64_t tc = h.tchunk_start[h.k0] + blockIdx.x;
-  const int64_t k = owner(h.tchunk_start, h.k0, h.k1, tc);
+__global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h) {
+  __shared__ unsigned long long tab[kTabSlots];
+  __shared__ int pre[kChunkGroup + 1];
+  __shared__ int scan_part[kMergeBlock];
+  __shared__ int claimed, overflow;
+  __shared__ unsigned long long red[kMergeBlock / kWave];
+  const int64_t gp = h.L.part_start[h.k0] + blockIdx.x;
+  const int64_t k = owner(h.L.part_start, h.k0, h.k1, gp);
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!a.dense && !a.act[v]) return;
-  const int64_t base = h.tab_start[k] - h.tab_start[h.k0];
-  const int64_t s0 = (tc - h.tchunk_start[k]) * kScanChunk;
-  const int64_t size = h.tab_start[k + 1] - h.tab_start[k];
-  const int64_t s1 = s0 + kScanChunk < size ? s0 + kScanChunk : size;
+  const int p = (int)(gp - h.L.part_start[k]);
+  const int P = hub_parts(a.off[v + 1] - a.off[v]);
+  const int64_t c0 = h.L.chunk_start[k], nc = h.L.chunk_start[k + 1] - c0;
+  const int32_t *gh = h.hist + (h.L.hist_start[k] - h.L.hist_start[h.k0]);
+  const unsigned long long *stage = h.staging + (c0 - h.L.chunk_start[h.k0]) * kHubChunk;
   unsigned long long best = 0;
-  for (int64_t s = s0 + threadIdx.x; s < s1; s += kScanBlock) {
-    unsigned long long *slot = h.tab + base + s;
-    const unsigned long long x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (x != kEmptySlot) {
-      const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
-      best = key > best ? key : best;
-      __hip_atomic_store(slot, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t R = 1;; R <<= 1) {
+    bool ok = true;
+    unsigned long long pass_best = 0;
+    for (uint32_t r = 0; r < R && ok; ++r) {
+      for (int s = threadIdx.x; s < kTabSlots; s += kMergeBlock) tab[s] = kEmptySlot;
+      if (threadIdx.x == 0) {
+        claimed = 0;
+        overflow = 0;
+      }
+      __syncthreads();
+      for (int64_t g0 = 0; g0 < nc; g0 += kChunkGroup) {
+        const int gn = (int)(nc - g0 < kChunkGroup ? nc - g0 : kChunkGroup);
+        for (int i = threadIdx.x; i < gn; i += kMergeBlock) {
+          const int32_t *hc = gh + (g0 + i) * (P + 1);
+          pre[i] = hc[p + 1] - hc[p];
+        }
+        __syncthreads();
+        block_exclusive_scan<kMergeBlock>(pre, gn, scan_part);
+        const int total = pre[gn];
+        for (int t = threadIdx.x; t < total; t += kMergeBlock) {
+          int lo = 0, hi = gn;  // chunk i with pre[i] <= t < pre[i + 1]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (pre[mid] <= t)
+              lo = mid;
+            else
+              hi = mid;
+          }
+          const int32_t *hc = gh + (g0 + lo) * (P + 1);
+          const unsigned long long xv = stage[(g0 + lo) * kHubChunk + hc[p] + (t - pre[lo])];
+          const uint32_t label = (uint32_t)(xv >> 32);
+          if (R > 1 && (sub_of(label) & (R - 1)) != r) continue;
+          if (__hip_atomic_load(&overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) continue;
+          if (__hip_atomic_load(&claimed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= kMergeCap) {
+            overflow = 1;
+            continue;
+          }
+          if (lds_insert(tab, kTabLog2, label, (uint32_t)xv) >= 0) atomicAdd(&claimed, 1);
+        }
+        __syncthreads();
+      }
+      if (overflow) {
+        ok = false;  // uniform: read after the barrier
+      } else {
+        for (int s = threadIdx.x; s < kTabSlots; s += kMergeBlock) {
+          const unsigned long long xv = tab[s];
+          if (xv != kEmptySlot) {
+            const unsigned long long key = argmax_key((uint32_t)(xv >> 32), (uint32_t)xv);
+            pass_best = key > pass_best ? key : pass_best;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (ok) {
+      best = pass_best;
+      break;
     }
   }
   best = group_max<kWave>(best);
@@ -204,7 +301,7 @@ __global__ __launch_bounds__(kScanBlock) void hub_scan(SweepArgs a, HubArgs h) {
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long m = 0;
-    for (int w = 0; w < kScanBlock / kWave; ++w) m = red[w] > m ? red[w] : m;
+    for (int w = 0; w < kMergeBlock / kWave; ++w) m = red[w] > m ? red[w] : m;
     if (m) __hip_atomic_fetch_max(&h.best[k], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -258,12 +355,12 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
 }
 
 __global__ __launch_bounds__(kHubBlock) void hub_mark(SweepArgs a, HubArgs h) {
-  const int64_t c = h.chunk_start[h.k0] + blockIdx.x;
-  const int64_t k = owner(h.chunk_start, h.k0, h.k1, c);
+  const int64_t c = h.L.chunk_start[h.k0] + blockIdx.x;
+  const int64_t k = owner(h.L.chunk_start, h.k0, h.k1, c);
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!a.chg[v]) return;  // uniform: only hubs changed in this sweep
   const int64_t rb = a.off[v], re = a.off[v + 1];
-  const int64_t b = rb + (c - h.chunk_start[k]) * kHubChunk;
+  const int64_t b = rb + (c - h.L.chunk_start[k]) * kHubChunk;
   const int64_t e = b + kHubChunk < re ? b + kHubChunk : re;
   for (int64_t p = b + threadIdx.x; p < e; p += kHubBlock) {
     const int32_t jj = a.cols[p];
@@ -273,32 +370,32 @@ __global__ __launch_bounds__(kHubBlock) void hub_mark(SweepArgs a, HubArgs h) {
 
 }  // namespace
 
-hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, int64_t *chunk_start,
-                             int64_t *tab_start, int64_t *tchunk_start, hipStream_t s) {
+hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, HubLayout L,
+                             hipStream_t s) {
   if (H <= 0) return hipSuccess;
-  hub_sizes<<<(unsigned)((H + 255) / 256), 256, 0, s>>>(off, hubs, H, chunk_start, tab_start, tchunk_start);
-  hub_scan_prefix<<<1, 1024, 0, s>>>(chunk_start, tab_start, tchunk_start, H);
+  hub_sizes<<<(unsigned)((H + 255) / 256), 256, 0, s>>>(off, hubs, H, L.chunk_start, L.part_start,
+                                                        L.hist_start);
+  hub_scan_prefix<<<1, 1024, 0, s>>>(L.chunk_start, L.part_start, L.hist_start, H);
   return hipGetLastError();
 }
 
 // The hub kernels for hubs [k0, k1): stage 0 is hub_insert, stage 1 the
-// scan, decision and marking.  Host arrays give the prefix sums so grid sizes
-// are known without a device round trip.
-hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, const int64_t *chunk_start,
-                            const int64_t *tab_start, const int64_t *tchunk_start,
-                            const int64_t *chunk_start_h, const int64_t *tchunk_start_h,
-                            unsigned long long *tab, unsigned long long *best,
-                            unsigned long long *rowsum, int64_t k0, int64_t k1, int stage,
-                            hipStream_t s) {
+// merge, decision and marking.  Host copies of the prefix arrays give the grid
+// sizes without a device round trip.
+hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L,
+                            const int64_t *chunk_start_h, const int64_t *part_start_h,
+                            unsigned long long *staging, int32_t *hist, unsigned long long *best,
+                            unsigned long long *rowsum, int64_t k0, int64_t k1, int max_parts,
+                            int stage, hipStream_t s) {
   if (k1 <= k0) return hipSuccess;
-  HubArgs h{hubs, chunk_start, tab_start, tchunk_start, tab, best, rowsum, k0, k1};
+  HubArgs h{hubs, L, staging, hist, best, rowsum, k0, k1};
   const int64_t chunks = chunk_start_h[k1] - chunk_start_h[k0];
-  const int64_t tchunks = tchunk_start_h[k1] - tchunk_start_h[k0];
+  const int64_t parts = part_start_h[k1] - part_start_h[k0];
   if (stage == 0) {
-    hub_insert<<<(unsigned)chunks, kHubBlock, 0, s>>>(a, h);
+    hub_insert<<<(unsigned)chunks, kHubBlock, (size_t)(max_parts + 1) * sizeof(int), s>>>(a, h);
     return hipGetLastError();
   }
-  hub_scan<<<(unsigned)tchunks, kScanBlock, 0, s>>>(a, h);
+  hub_merge<<<(unsigned)parts, kMergeBlock, 0, s>>>(a, h);
   hub_decide<<<(unsigned)((k1 - k0 + 255) / 256), 256, 0, s>>>(a, h);
   if (a.mark) hub_mark<<<(unsigned)chunks, kHubBlock, 0, s>>>(a, h);
   return hipGetLastError();

@@ -184,12 +184,12 @@ __global__ __launch_bounds__(BLOCK) void reorder_rows(CopyArgs c, int64_t first,
     atomicOr(c.flags, (unsigned long long)(any_unsorted ? 1 : 0) | (any_ovf ? 2 : 0));
 }
 
-// Hub rows in chunks of kChunk entries, one block per chunk; chunk_start is
-// the hub layout (prefix of chunks per hub, hubs = new ids 0..H-1).  The
+// Hub rows in chunks of kHubChunk entries, one block per chunk; chunk_start
+// is the hub layout (prefix of chunks per hub, hubs = new ids 0..H-1).  The
 // first-sweep key and weight sum of a hub are combined across its chunks.
-constexpr int kChunk = 8192;
-__global__ __launch_bounds__(1024) void reorder_hub_rows(CopyArgs c, const int64_t *chunk_start, int64_t H) {
-  __shared__ unsigned long long red[1024 / kWave], red2[1024 / kWave];
+constexpr int kChunk = kHubChunk;
+__global__ __launch_bounds__(256) void reorder_hub_rows(CopyArgs c, const int64_t *chunk_start, int64_t H) {
+  __shared__ unsigned long long red[256 / kWave], red2[256 / kWave];
   const int64_t ch = blockIdx.x;
   int64_t lo = 0, hi = H;
   while (hi - lo > 1) {
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(1024) void reorder_hub_rows(CopyArgs c, const int64
   const int64_t e = b + kChunk < re ? b + kChunk : re;
   unsigned long long best = 0, rowsum = 0;
   int unsorted = 0;
-  for (int64_t q = b + threadIdx.x; q < e; q += 1024) {
+  for (int64_t q = b + threadIdx.x; q < e; q += 256) {
     c.cols2[b2 + (q - rb)] = c.old2new[c.cols[q]];
     if (c.w) c.w2[b2 + (q - rb)] = c.w[q];
     first_entry(c, v, q, re, best, rowsum, unsorted);
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(1024) void reorder_hub_rows(CopyArgs c, const int64
   }
   const int any_unsorted = __syncthreads_or(unsorted);
   if (threadIdx.x == 0) {
-    for (int w = 1; w < 1024 / kWave; ++w) {
+    for (int w = 1; w < 256 / kWave; ++w) {
       red[0] = red[w] > red[0] ? red[w] : red[0];
       red2[0] += red2[w];
     }
@@ -323,10 +323,8 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
       reorder_rows<64, 256, 8><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
     else if (t == 7)
       reorder_rows<256, 256, 8><<<grid_of(cnt, 1, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t == 8)
-      reorder_rows<1024, 1024, 8><<<grid_of(cnt, 1, kCap), 1024, 0, s>>>(c, first, cnt);
     else if (hub_chunks > 0)
-      reorder_hub_rows<<<(unsigned)hub_chunks, 1024, 0, s>>>(c, hub_chunk_start, cnt);
+      reorder_hub_rows<<<(unsigned)hub_chunks, 256, 0, s>>>(c, hub_chunk_start, cnt);
   }
   if (np > 0)
     first_apply<<<grid_of(np, 256, 1024), 256, 0, s>>>(first_key, list, np, hub_rowsum, H, flags, lab, dn0,

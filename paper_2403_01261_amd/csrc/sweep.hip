@@ -306,10 +306,6 @@ hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, 
       grid = grid_for(count, 1, kCap);
       sweep_lds<256, 12, 256, 8><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
-    case 8:
-      grid = grid_for(count, 1, 256 * 2);
-      sweep_lds<1024, 14, 1024, 8><<<grid, 1024, 0, s>>>(a, list, first, count);
-      break;
     default:
       return hipErrorInvalidValue;
   }
