@@ -77,6 +77,16 @@ struct Scratch {
   int32_t *cols2 = nullptr;
   uint32_t *w2 = nullptr;
   bool w2_ok = false;
+  // device loop state and the cached loop graph
+  gsl::SweepCtrl *ctrl = nullptr;
+  hipGraphExec_t loop_exec = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the loop graph is captured on
+  std::vector<uint64_t> loop_key;
+  // batches: graph of every vertex, per-graph limits / counts / flags
+  int64_t batch_n_cap = -1, batch_g_cap = -1;
+  int32_t *gid = nullptr, *giters = nullptr;
+  int64_t *glimit = nullptr, *gdn = nullptr;
+  uint8_t *gdone = nullptr;
 };
 
 // Returns event k of the pool, creating events on demand.
@@ -115,6 +125,14 @@ void free_scratch(Scratch &s) {
     if (e) hipEventDestroy(e);
   for (auto &e : s.pool) hipEventDestroy(e);
   if (s.ev_reorder) hipEventDestroy(s.ev_reorder);
+  if (s.loop_exec) hipGraphExecDestroy(s.loop_exec);
+  if (s.cap_stream) hipStreamDestroy(s.cap_stream);
+  hipFree(s.ctrl);
+  hipFree(s.gid);
+  hipFree(s.giters);
+  hipFree(s.glimit);
+  hipFree(s.gdn);
+  hipFree(s.gdone);
   hipFree(s.old2new);
   hipFree(s.lab2);
   hipFree(s.minorig);
@@ -163,7 +181,8 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
         dmalloc(&s.tier_part, (int64_t)gsl::kNumTiers * gsl::kMaxTierGrid * gsl::kCountFields) != hipSuccess)
       return fail(GSL_ENOMEM, "device allocation failed");
   }
-  const int64_t need = (int64_t)sizeof(Counters) + 3 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
+  if (!s.ctrl && dmalloc(&s.ctrl, 1) != hipSuccess) return fail(GSL_ENOMEM, "device allocation failed");
+  const int64_t need = (int64_t)sizeof(Counters) + 4 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
   if (need > s.ctr_bytes) {
     hipFree(s.ctr);
     if (s.ctr_host) hipHostFree(s.ctr_host);
@@ -353,9 +372,23 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
+// A batch of independent graphs laid out as one graph with global ids (see
+// gsl_lpa_batched); NULL for a single graph.
+struct Batch {
+  int64_t graphs;
+  const int64_t *vtx_base;  // device [graphs + 1]
+};
+
+// One timing record: an event pair around a launch of tier `tier` in sweep
+// `sweep` (kind 0: the tier kernel, 1: the hub finishing kernels).
+struct Launch {
+  int tier, sweep, kind;
+  size_t ev;
+};
+
 int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
              int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
-             int32_t *labels_out) {
+             int32_t *labels_out, const Batch *batch = nullptr) {
   gsl_options o = {1, 1, 0, 0};
   if (opt) o = *opt;
   if (stats) memset(stats, 0, sizeof(*stats));
@@ -381,10 +414,11 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   const int64_t H = plan.tier_count[gsl::kHubTier];
   if ((rc = prepare_hubs(s, offsets, s.list, H, st))) return rc;
   // Renumbered layout: chosen when vertices of degree > 64 hold most entries
-  // (their labels are the usual gather targets).
+  // (their labels are the usual gather targets).  Batches keep their layout
+  // (per-graph vertex ranges).
   int64_t heavy = 0;
   for (int t = 5; t < gsl::kNumTiers; ++t) heavy += plan.tier_edges[t];
-  const bool renumber = o.layout == 1 || (o.layout == 0 && 2 * heavy > nnz);
+  const bool renumber = !batch && (o.layout == 1 || (o.layout == 0 && 2 * heavy > nnz));
   const int64_t np = n - plan.tier_count[0];  // non-isolated vertices
   const int64_t *g_off = offsets;
   const int32_t *g_cols = cols;
@@ -392,6 +426,10 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   const int32_t *g_list = s.list;
   int32_t *C = labels_out;
   int64_t n_sweep = n;
+  unsigned long long *dn_arr = sweep_array(s.ctr, 0, max_iters);
+  unsigned long long *pr_arr = sweep_array(s.ctr, 1, max_iters);
+  unsigned long long *ed_arr = sweep_array(s.ctr, 2, max_iters);
+  unsigned long long *mk_arr = sweep_array(s.ctr, 3, max_iters);
   if (renumber) {
     if ((rc = ensure_copy(s, n, nnz, weights != nullptr))) return rc;
     if (o.timing) {
@@ -403,7 +441,7 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
                                 s.hub_chunk_start, H > 0 ? s.h_chunk[(size_t)H] : 0, s.old2new, s.off2,
                                 s.cols2, weights ? s.w2 : nullptr, s.lab2, s.blk_counts, s.first_key,
                                 s.hub_rowsum, reinterpret_cast<unsigned long long *>(&s.ctr->first_flags),
-                                sweep_array(s.ctr, 0, max_iters), max_iters > 0 ? 1 : 0, st));
+                                dn_arr, max_iters > 0 ? 1 : 0, st));
     g_off = s.off2;
     g_cols = s.cols2;
     g_w = weights ? s.w2 : nullptr;
@@ -413,75 +451,64 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   } else {
     HIP_TRY(gsl::launch_init_labels(C, s.Cn, n, st));
   }
-  const int64_t limit = gsl_convergence_limit(n, tolerance);
   const int64_t flag_bytes = (n + 3) / 4 * 4;
   HIP_TRY(gsl::launch_fill_u8(s.chg, 0, flag_bytes, st));
   HIP_TRY(gsl::launch_fill_u8(s.act[0], 0, flag_bytes, st));
   HIP_TRY(gsl::launch_fill_u8(s.act[1], 0, flag_bytes, st));
+  // Loop state on the device; the renumbered layout may have run sweep 0.
+  gsl::SweepCtrl hc;
+  memset(&hc, 0, sizeof(hc));
+  hc.max_iters = max_iters;
+  hc.prune = o.prune ? 1 : 0;
+  hc.limit = gsl_convergence_limit(n, tolerance);
+  hc.n = n;
+  hc.graphs = batch ? batch->graphs : 0;
+  HIP_TRY(hipMemcpyAsync(s.ctrl, &hc, sizeof(hc), hipMemcpyHostToDevice, st));
+  HIP_TRY(gsl::launch_loop_init(
+      s.ctrl, renumber ? reinterpret_cast<const unsigned long long *>(&s.ctr->first_flags) : nullptr, dn_arr,
+      mk_arr, st));
+  if (batch)
+    HIP_TRY(gsl::launch_batch_init(batch->vtx_base, batch->graphs, max_iters, tolerance, s.gid, s.glimit,
+                                   s.giters, s.gdone, st));
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[1], st));
-  unsigned long long *dn_arr = sweep_array(s.ctr, 0, max_iters);
-  unsigned long long *pr_arr = sweep_array(s.ctr, 1, max_iters);
-  unsigned long long *ed_arr = sweep_array(s.ctr, 2, max_iters);
-  int32_t it = 0;
-  bool marked_prev = false;
-  int64_t dn_prev = n;
-  int overflow = 0;
-  // Timing events: per sweep (start, end) and per tier launch (start, end).
-  struct Launch { int tier; size_t ev; };
+
+  gsl::SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.off = g_off;
+  a.cols = g_cols;
+  a.w = g_w;
+  a.C = C;
+  a.Cn = s.Cn;
+  a.chg = s.chg;
+  a.act0 = s.act[0];
+  a.act1 = s.act[1];
+  a.ctrl = s.ctrl;
+  a.dn = dn_arr;
+  a.processed = pr_arr;
+  a.edges = ed_arr;
+  a.marked_sweeps = mk_arr;
+  a.overflow = reinterpret_cast<unsigned long long *>(&s.ctr->overflow);
+  a.gid = batch ? s.gid : nullptr;
+  a.gdone = batch ? s.gdone : nullptr;
+  const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
+
+  // Timing records (timing mode only).
   std::vector<Launch> launches;
-  // Hub tier segments after the first hub_insert: (kind, event index); kind
-  // 0 = a hub_insert of a later batch, 1 = the finishing kernels.
-  std::vector<Launch> hub_finish_ev;
   std::vector<size_t> sweep_ev;
   size_t nev = 0;
-  int64_t tier_launches[gsl::kNumTiers] = {0}, tier_sparse[gsl::kNumTiers] = {0};
   auto rec = [&](size_t k) -> int {
     hipEvent_t e = pool_event(s, k);
     if (!e) return fail(GSL_EDEVICE, "hipEventCreate failed");
     HIP_TRY(hipEventRecord(e, st));
     return GSL_OK;
   };
-  // The renumbering copy has already run the first sweep when every row was
-  // strictly increasing (see reorder.hip); pick up its result.
-  bool fused_first = false, converged = false;
-  if (renumber && max_iters > 0) {
-    unsigned long long fl[2] = {0, 0};
-    HIP_TRY(hipMemcpyAsync(&fl[0], &s.ctr->first_flags, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&fl[1], dn_arr, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (!(fl[0] & 1ull)) {
-      if (fl[0] & 2ull)
-        return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; weights are summed in 32 bits");
-      fused_first = true;
-      it = 1;
-      dn_prev = (int64_t)fl[1];
-      converged = dn_prev <= limit;
-    } else {
-      HIP_TRY(hipMemsetAsync(dn_arr, 0, sizeof(unsigned long long), st));
-    }
-  }
-  while (!converged && it < max_iters) {
-    // Pruning: sweep `it` processes only flagged vertices if the previous
-    // sweep marked; this sweep marks if the previous one changed few vertices
-    // (otherwise the next sweep simply runs dense).
-    const bool dense = !(o.prune && marked_prev);
-    const bool mark = o.prune && it >= 1 && dn_prev * 8 <= n;
-    gsl::SweepArgs a;
-    a.off = g_off;
-    a.cols = g_cols;
-    a.w = g_w;
-    a.C = C;
-    a.Cn = s.Cn;
-    a.chg = s.chg;
-    a.act = s.act[it & 1];
-    a.nact = s.act[(it + 1) & 1];
-    a.dense = dense ? 1 : 0;
-    a.mark = mark ? 1 : 0;
-    a.dn = dn_arr + it;
-    a.processed = pr_arr + it;
-    a.edges = ed_arr + it;
-    a.overflow = reinterpret_cast<unsigned long long *>(&s.ctr->overflow);
-    if (o.timing) {
+  const bool timed = o.timing != 0;
+
+  // Enqueues one sweep; every kernel checks the device loop state, so a sweep
+  // enqueued after convergence costs only empty launches.
+  hipStream_t cur = st;  // stream the sweeps are enqueued on
+  auto enqueue_sweep = [&](int k) -> int {
+    if (timed) {
       sweep_ev.push_back(nev);
       if ((rc = rec(nev++))) return rc;
     }
@@ -492,55 +519,100 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
       if (cnt <= 0) continue;
       a.tier = &s.ctr->tier_stats[t][0];
       a.part = s.tier_part + (size_t)t * gsl::kMaxTierGrid * gsl::kCountFields;
-      if (o.timing) {
-        launches.push_back({t, nev});
+      if (timed) {
+        launches.push_back({t, k, 0, nev});
         if ((rc = rec(nev++))) return rc;
       }
       if (t == gsl::kHubTier) {
-        // Tier-9 timing covers hub_insert only; the merge / decide / mark
-        // kernels are timed as ms_hub_finish.
-        const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
         for (size_t bi = 0; bi < s.hub_batches.size(); ++bi) {
           const auto &bt = s.hub_batches[bi];
           for (int stage = 0; stage < 2; ++stage) {
-            if (o.timing && (bi > 0 || stage > 0)) {
-              hub_finish_ev.push_back({stage == 0 ? 0 : 1, nev});
+            if (timed && (bi > 0 || stage > 0)) {
+              launches.push_back({t, k, stage, nev});
               if ((rc = rec(nev++))) return rc;
             }
-            HIP_TRY(gsl::launch_hub_sweep(a, g_list, L, s.h_chunk.data(), s.h_part.data(),
-                                          s.hub_staging, s.hub_hist, s.hub_best, s.hub_rowsum,
-                                          bt.first, bt.second, s.hub_max_parts[bi], stage, st));
+            HIP_TRY(gsl::launch_hub_sweep(a, g_list, L, s.h_chunk.data(), s.h_part.data(), s.hub_staging,
+                                          s.hub_hist, s.hub_best, s.hub_rowsum, bt.first, bt.second,
+                                          s.hub_max_parts[bi], stage, cur));
           }
         }
       } else {
-        HIP_TRY(gsl::launch_sweep_tier(t, a, g_list, plan.tier_start[t], cnt, &grids.g[t], st));
+        HIP_TRY(gsl::launch_sweep_tier(t, a, g_list, plan.tier_start[t], cnt, &grids.g[t], cur));
       }
-      if (o.timing && (rc = rec(nev++))) return rc;
-      tier_launches[t] += 1;
-      tier_sparse[t] += dense ? 0 : 1;
+      if (timed && (rc = rec(nev++))) return rc;
     }
-    HIP_TRY(gsl::launch_reduce_counts(s.tier_part, grids, s.ctr->tier_stats, dn_arr + it, pr_arr + it,
-                                      ed_arr + it, reinterpret_cast<unsigned long long *>(&s.ctr->overflow),
-                                      st));
-    HIP_TRY(gsl::launch_apply(C, s.Cn, s.chg, dense ? nullptr : s.act[it & 1], n_sweep, st));
-    if (o.timing && (rc = rec(nev++))) return rc;
-    unsigned long long dn_host[2] = {0, 0};
-    HIP_TRY(hipMemcpyAsync(&dn_host[0], dn_arr + it, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&dn_host[1], &s.ctr->overflow, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (stats && it < GSL_STATS_MAX_ITERS) stats->marked[it] = mark ? 1 : 0;
-    ++it;
-    if (dn_host[1]) {
-      overflow = 1;
-      break;
+    HIP_TRY(gsl::launch_reduce_counts(s.tier_part, grids, s.ctr->tier_stats, s.ctrl, dn_arr, pr_arr, ed_arr,
+                                      a.overflow, cur));
+    if (batch) HIP_TRY(gsl::launch_graph_count(a, batch->vtx_base, batch->graphs, s.gdn, cur));
+    HIP_TRY(gsl::launch_apply(a, C, n_sweep, cur));
+    if (batch)
+      HIP_TRY(gsl::launch_graph_end(s.ctrl, s.gdn, s.glimit, s.giters, s.gdone, batch->graphs, cur));
+    HIP_TRY(gsl::launch_sweep_end(s.ctrl, dn_arr, mk_arr, a.overflow, cur));
+    if (timed && (rc = rec(nev++))) return rc;
+    return GSL_OK;
+  };
+
+  if (timed || max_iters == 0) {
+    for (int k = 0; k < max_iters; ++k)
+      if ((rc = enqueue_sweep(k))) return rc;
+  } else {
+    // The whole loop (max_iters sweeps) as one captured graph, reused while
+    // every pointer and size it was built from stays the same.
+    std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)n_sweep, (uint64_t)nnz, (uint64_t)max_iters,
+                                 (uint64_t)o.prune, (uint64_t)renumber,
+                                 (uint64_t)(uintptr_t)g_off, (uint64_t)(uintptr_t)g_cols,
+                                 (uint64_t)(uintptr_t)g_w, (uint64_t)(uintptr_t)C, (uint64_t)(uintptr_t)g_list,
+                                 (uint64_t)(uintptr_t)s.Cn, (uint64_t)(uintptr_t)s.chg,
+                                 (uint64_t)(uintptr_t)s.act[0], (uint64_t)(uintptr_t)s.act[1],
+                                 (uint64_t)(uintptr_t)s.ctr, (uint64_t)(uintptr_t)s.ctrl,
+                                 (uint64_t)(uintptr_t)s.tier_part, (uint64_t)(uintptr_t)s.hub_staging,
+                                 (uint64_t)(uintptr_t)s.hub_hist, (uint64_t)(uintptr_t)s.hub_best,
+                                 (uint64_t)(uintptr_t)s.hub_rowsum, (uint64_t)(uintptr_t)s.hub_chunk_start,
+                                 (uint64_t)(uintptr_t)s.hub_part_start, (uint64_t)(uintptr_t)s.hub_hist_start,
+                                 (uint64_t)(uintptr_t)(batch ? batch->vtx_base : nullptr),
+                                 (uint64_t)(batch ? batch->graphs : 0), (uint64_t)(uintptr_t)s.gid,
+                                 (uint64_t)(uintptr_t)s.gdn, (uint64_t)(uintptr_t)s.glimit,
+                                 (uint64_t)(uintptr_t)s.giters, (uint64_t)(uintptr_t)s.gdone};
+    for (int t = 0; t < gsl::kNumTiers; ++t) {
+      key.push_back((uint64_t)plan.tier_count[t]);
+      key.push_back((uint64_t)plan.tier_start[t]);
     }
-    marked_prev = mark;
-    dn_prev = (int64_t)dn_host[0];
-    if ((int64_t)dn_host[0] <= limit) break;
+    for (size_t bi = 0; bi < s.hub_batches.size(); ++bi) {
+      key.push_back((uint64_t)s.hub_batches[bi].first);
+      key.push_back((uint64_t)s.hub_batches[bi].second);
+      key.push_back((uint64_t)s.hub_max_parts[bi]);
+    }
+    if (!s.loop_exec || key != s.loop_key) {
+      if (s.loop_exec) hipGraphExecDestroy(s.loop_exec);
+      s.loop_exec = nullptr;
+      s.loop_key.clear();
+      // Captured on a private stream (the caller's may be the null stream,
+      // which cannot be captured); launched on the caller's stream.
+      if (!s.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
+      const hipStream_t user_st = st;
+      cur = s.cap_stream;
+      HIP_TRY(hipStreamBeginCapture(cur, hipStreamCaptureModeThreadLocal));
+      int crc = GSL_OK;
+      for (int k = 0; k < max_iters && crc == GSL_OK; ++k) crc = enqueue_sweep(k);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(cur, &graph);
+      cur = user_st;
+      if (crc != GSL_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return crc;
+      }
+      if (ec != hipSuccess) return fail(GSL_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&s.loop_exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        s.loop_exec = nullptr;
+        return fail(GSL_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+      }
+      s.loop_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(s.loop_exec, st));
   }
-  if (o.timing) HIP_TRY(hipEventRecord(s.ev[2], st));
-  if (overflow)
-    return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; weights are summed in 32 bits");
+  if (timed) HIP_TRY(hipEventRecord(s.ev[2], st));
   if (renumber) {
     if (o.split)
       HIP_TRY(gsl::launch_split(g_off, g_cols, np, C, s.parent, labels_out, nullptr, plan.tier_count,
@@ -551,12 +623,19 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
     HIP_TRY(gsl::launch_split(offsets, cols, n, C, s.parent, labels_out, s.list, plan.tier_count,
                               plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), st));
   }
-  if (o.timing) HIP_TRY(hipEventRecord(s.ev[3], st));
-  if (stats) {
-    HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, (size_t)s.ctr_bytes, hipMemcpyDeviceToHost, st));
-  }
+  if (timed) HIP_TRY(hipEventRecord(s.ev[3], st));
+  gsl::SweepCtrl fc;
+  HIP_TRY(hipMemcpyAsync(&fc, s.ctrl, sizeof(fc), hipMemcpyDeviceToHost, st));
+  if (stats) HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, (size_t)s.ctr_bytes, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (fc.error)
+    return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; weights are summed in 32 bits");
+  const int32_t it = fc.it;
   if (stats) {
+    // Sweep 0 ran inside the renumbering copy when the loop started at 1.
+    const unsigned long long ff = s.ctr_host->first_flags;
+    const bool fused_first = renumber && max_iters > 0 && !(ff & 1ull);
+    const int first_kernel_sweep = fused_first ? 1 : 0;
     stats->iterations = it;
     stats->split_rounds = o.split ? 1 : 0;
     stats->nnz = nnz;
@@ -564,43 +643,48 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
     const unsigned long long *hd = sweep_array(s.ctr_host, 0, max_iters);
     const unsigned long long *hp = sweep_array(s.ctr_host, 1, max_iters);
     const unsigned long long *he = sweep_array(s.ctr_host, 2, max_iters);
+    const unsigned long long *hm = sweep_array(s.ctr_host, 3, max_iters);
     for (int k = 0; k < it && k < GSL_STATS_MAX_ITERS; ++k) {
       stats->changed[k] = (int64_t)hd[k];
       stats->processed[k] = (int64_t)hp[k];
       stats->edges[k] = (int64_t)he[k];
+      stats->marked[k] = (int64_t)hm[k];
     }
-    if (fused_first) {
+    if (fused_first && it > 0) {
       stats->processed[0] = np;
       stats->edges[0] = nnz;
     }
     for (int t = 0; t < gsl::kNumTiers; ++t) {
       stats->tier_vertices[t] = plan.tier_count[t];
-      stats->tier_launches[t] = tier_launches[t];
-      stats->tier_sparse[t] = tier_sparse[t];
       stats->tier_processed[t] = (int64_t)s.ctr_host->tier_stats[t][0];
       stats->tier_edges[t] = (int64_t)s.ctr_host->tier_stats[t][1];
       stats->tier_changed[t] = (int64_t)s.ctr_host->tier_stats[t][2];
       stats->tier_marked[t] = (int64_t)s.ctr_host->tier_stats[t][3];
+      if (t == 0 || plan.tier_count[t] <= 0) continue;
+      for (int k = first_kernel_sweep; k < it; ++k) {
+        stats->tier_launches[t] += 1;
+        stats->tier_sparse[t] += (k > 0 && o.prune && hm[k - 1]) ? 1 : 0;
+      }
     }
     stats->renumbered = renumber ? 1 : 0;
-    if (o.timing) {
+    if (timed) {
       if (renumber) stats->ms_reorder = elapsed(s.ev_reorder, s.ev[1]);
       stats->ms_plan = elapsed(s.ev[0], s.ev[1]);
       stats->ms_sweeps = elapsed(s.ev[1], s.ev[2]);
       stats->ms_split = elapsed(s.ev[2], s.ev[3]);
       stats->ms_total = elapsed(s.ev[0], s.ev[3]);
-      // Each recorded launch spans its start event to the next event; a hub
-      // segment of kind 1 (finish) counts towards ms_hub_finish instead.
-      for (const Launch &l : launches) stats->ms_tier[l.tier] += elapsed(s.pool[l.ev], s.pool[l.ev + 1]);
-      for (const Launch &l : hub_finish_ev) {
+      // Only sweeps that ran (k < it) count; a record spans its event to the
+      // next one.  Hub finishing kernels (kind 1) go to ms_hub_finish.
+      for (const Launch &l : launches) {
+        if (l.sweep >= it) continue;
         const float ms = elapsed(s.pool[l.ev], s.pool[l.ev + 1]);
-        if (l.tier == 1)
+        if (l.kind == 1)
           stats->ms_hub_finish += ms;
         else
-          stats->ms_tier[gsl::kHubTier] += ms;
+          stats->ms_tier[l.tier] += ms;
       }
-      for (size_t k = 0; k < sweep_ev.size() && k < GSL_STATS_MAX_ITERS; ++k) {
-        const size_t end = k + 1 < sweep_ev.size() ? sweep_ev[k + 1] - 1 : nev - 1;
+      for (int k = first_kernel_sweep; k < it && k < (int)sweep_ev.size() && k < GSL_STATS_MAX_ITERS; ++k) {
+        const size_t end = k + 1 < (int)sweep_ev.size() ? sweep_ev[k + 1] - 1 : nev - 1;
         stats->ms_sweep[k] = elapsed(s.pool[sweep_ev[k]], s.pool[end]);
       }
     }

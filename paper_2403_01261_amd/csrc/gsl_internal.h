@@ -38,7 +38,26 @@ struct Counters {
   int64_t tier_edges[16];   // row entries per tier
   // per tier, summed over sweeps: processed, edges, changed, marked
   unsigned long long tier_stats[kNumTiers][4];
-  // followed by per-sweep arrays dn[max_iters], processed[], edges[]
+  // followed by per-sweep arrays dn[max_iters], processed[], edges[], marked[]
+};
+
+// Loop state kept on the device, so a whole sequence of sweeps can be
+// enqueued (or captured in a graph) without the host reading anything back:
+// every sweep kernel returns at once when `done` is set, and sweep_end
+// advances the state after each sweep.
+struct SweepCtrl {
+  int32_t it;          // index of the sweep about to run
+  int32_t done;        // converged, iteration cap reached, or error
+  int32_t dense;       // this sweep processes every listed vertex
+  int32_t mark;        // this sweep marks the neighbours of changed vertices
+  int32_t max_iters;
+  int32_t prune;
+  int32_t error;       // 1: a row's weight sum reached 2^32
+  int32_t pad;
+  int64_t limit;       // largest dN that counts as converged (one graph)
+  int64_t n;           // vertices, for the marking heuristic
+  int64_t graphs;      // 0: one graph; else graphs of a batch
+  int64_t active;      // graphs still running after the last sweep (batch)
 };
 
 // Arguments common to every sweep kernel.
@@ -49,16 +68,43 @@ struct SweepArgs {
   const int32_t *C;       // labels read by this sweep
   int32_t *Cn;            // new label of each changed vertex
   uint8_t *chg;           // 1 where the vertex changed in this sweep
-  const uint8_t *act;     // processed set of this sweep (ignored when dense)
-  uint8_t *nact;          // marks for the next sweep (written when mark)
-  int dense;              // process every listed vertex
-  int mark;               // mark neighbours of changed vertices in nact
-  unsigned long long *dn, *processed, *edges, *overflow;
+  uint8_t *act0, *act1;   // active flags: sweep t reads act[t & 1], marks act[(t + 1) & 1]
+  const SweepCtrl *ctrl;  // loop state (dense / mark / it / done)
+  // Per-sweep counters (indexed by ctrl->it) and the overflow flag.
+  unsigned long long *dn, *processed, *edges, *marked_sweeps, *overflow;
   unsigned long long *tier;  // this tier's [processed, edges, changed, marked]
   // Per-block count records of the tier kernels (kCountFields per block);
   // summed by launch_reduce_counts instead of contended global atomics.
   unsigned long long *part;
+  // Batches: graph of every vertex and the graphs that have stopped (NULL
+  // for a single graph).
+  const int32_t *gid;
+  const uint8_t *gdone;
 };
+
+// What a sweep kernel needs from the loop state.
+struct SweepView {
+  int it, dense, mark;
+  const uint8_t *act;
+  uint8_t *nact;
+};
+
+__device__ __forceinline__ bool sweep_view(const SweepArgs &a, SweepView &v) {
+  const SweepCtrl *c = a.ctrl;
+  if (c->done) return false;
+  v.it = c->it;
+  v.dense = c->dense;
+  v.mark = c->mark;
+  v.act = (v.it & 1) ? a.act1 : a.act0;
+  v.nact = (v.it & 1) ? a.act0 : a.act1;
+  return true;
+}
+
+// Vertex v takes part in this sweep.
+__device__ __forceinline__ bool sweep_takes(const SweepArgs &a, const SweepView &sv, int32_t v) {
+  if (a.gid && a.gdone[a.gid[v]]) return false;
+  return sv.dense || sv.act[v];
+}
 
 constexpr int kCountFields = 5;        // dn, processed, edges, marked, overflow
 constexpr int kMaxTierGrid = 256 * 16; // largest grid of a tier kernel
@@ -77,9 +123,9 @@ hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, 
 // Sums the per-block records of tier t (part + t * kMaxTierGrid * kCountFields,
 // g.g[t] blocks) into the tier and sweep counters.
 hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
-                                unsigned long long (*tier_stats)[4], unsigned long long *dn,
-                                unsigned long long *processed, unsigned long long *edges,
-                                unsigned long long *overflow, hipStream_t s);
+                                unsigned long long (*tier_stats)[4], const SweepCtrl *ctrl,
+                                unsigned long long *dn, unsigned long long *processed,
+                                unsigned long long *edges, unsigned long long *overflow, hipStream_t s);
 // Hub tier layout: rows cut into chunks of kHubChunk entries; prefix sums
 // over the hubs (H + 1 entries each) of their chunks, hash partitions and
 // partition-boundary records (chunks * (partitions + 1)).
@@ -96,8 +142,24 @@ hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L
                             unsigned long long *staging, int32_t *hist, unsigned long long *best,
                             unsigned long long *rowsum, int64_t k0, int64_t k1, int max_parts,
                             int stage, hipStream_t s);
-hipError_t launch_apply(int32_t *C, const int32_t *Cn, uint8_t *chg, uint8_t *act_clear,
-                        int64_t n, hipStream_t s);
+// Copies changed labels into C and clears the consumed flags (this sweep's
+// active flags when it was sparse).
+hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, hipStream_t s);
+// Advances the loop state after a sweep.
+hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsigned long long *marked_sweeps,
+                            const unsigned long long *overflow, hipStream_t s);
+// Loop state before the first sweep; first_flags (NULL unless renumbered)
+// tells whether the renumbering copy already ran sweep 0.
+hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_flags, unsigned long long *dn,
+                            unsigned long long *marked_sweeps, hipStream_t s);
+// Batches: graph id per vertex, per-graph limits, sweep counts and stop flags.
+hipError_t launch_batch_init(const int64_t *vtx_base, int64_t graphs, int32_t max_iters, double tol,
+                             int32_t *gid, int64_t *glimit, int32_t *giters, uint8_t *gdone, hipStream_t s);
+// Batches: per-graph change counts and stop decisions (before sweep_end).
+hipError_t launch_graph_count(const SweepArgs &a, const int64_t *vtx_base, int64_t graphs,
+                              int64_t *gdn, hipStream_t s);
+hipError_t launch_graph_end(SweepCtrl *ctrl, const int64_t *gdn, const int64_t *glimit, int32_t *giters,
+                            uint8_t *gdone, int64_t graphs, hipStream_t s);
 hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);

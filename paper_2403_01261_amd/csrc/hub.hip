@@ -165,10 +165,12 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
   extern __shared__ int hist[];
   __shared__ int scan_part[kHubBlock];
   __shared__ unsigned long long red[kHubBlock / kWave];
+  SweepView sv;
+  if (!sweep_view(a, sv)) return;
   const int64_t c = h.L.chunk_start[h.k0] + blockIdx.x;
   const int64_t k = owner(h.L.chunk_start, h.k0, h.k1, c);
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
-  if (!a.dense && !a.act[v]) return;  // uniform over the block
+  if (!sweep_takes(a, sv, v)) return;  // uniform over the block
   const int64_t rb = a.off[v], re = a.off[v + 1];
   const int P = hub_parts(re - rb);
   const int64_t cl = c - h.L.chunk_start[k];
@@ -227,10 +229,12 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
   __shared__ int scan_part[kMergeBlock];
   __shared__ int claimed, overflow;
   __shared__ unsigned long long red[kMergeBlock / kWave];
+  SweepView sv;
+  if (!sweep_view(a, sv)) return;
   const int64_t gp = h.L.part_start[h.k0] + blockIdx.x;
   const int64_t k = owner(h.L.part_start, h.k0, h.k1, gp);
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
-  if (!a.dense && !a.act[v]) return;
+  if (!sweep_takes(a, sv, v)) return;
   const int p = (int)(gp - h.L.part_start[k]);
   const int P = hub_parts(a.off[v + 1] - a.off[v]);
   const int64_t c0 = h.L.chunk_start[k], nc = h.L.chunk_start[k + 1] - c0;
@@ -308,11 +312,13 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
 
 __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
   __shared__ unsigned long long red[256 / kWave];
+  SweepView sv;
+  if (!sweep_view(a, sv)) return;
   LocalCounts lc;
   const int64_t k = h.k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < h.k1) {
     const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
-    if (a.dense || a.act[v]) {
+    if (sweep_takes(a, sv, v)) {
       const unsigned long long best = h.best[k];
       const unsigned long long rs = h.rowsum[k];
       h.best[k] = 0;
@@ -326,7 +332,7 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
           a.Cn[v] = (int32_t)cstar;
           a.chg[v] = 1;
           lc.dn = 1;
-          if (a.mark) lc.marked = lc.edges;  // hub_mark flags the whole row
+          if (sv.mark) lc.marked = lc.edges;  // hub_mark flags the whole row
         }
       }
     }
@@ -339,15 +345,15 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
   if (threadIdx.x == 0) {
     if (mk) atomicAdd(a.tier + 3, mk);
     if (dn) {
-      atomicAdd(a.dn, dn);
+      atomicAdd(a.dn + sv.it, dn);
       atomicAdd(a.tier + 2, dn);
     }
     if (pr) {
-      atomicAdd(a.processed, pr);
+      atomicAdd(a.processed + sv.it, pr);
       atomicAdd(a.tier + 0, pr);
     }
     if (ed) {
-      atomicAdd(a.edges, ed);
+      atomicAdd(a.edges + sv.it, ed);
       atomicAdd(a.tier + 1, ed);
     }
     if (ov) atomicAdd(a.overflow, ov);
@@ -355,6 +361,8 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
 }
 
 __global__ __launch_bounds__(kHubBlock) void hub_mark(SweepArgs a, HubArgs h) {
+  SweepView sv;
+  if (!sweep_view(a, sv) || !sv.mark) return;
   const int64_t c = h.L.chunk_start[h.k0] + blockIdx.x;
   const int64_t k = owner(h.L.chunk_start, h.k0, h.k1, c);
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
@@ -364,7 +372,7 @@ __global__ __launch_bounds__(kHubBlock) void hub_mark(SweepArgs a, HubArgs h) {
   const int64_t e = b + kHubChunk < re ? b + kHubChunk : re;
   for (int64_t p = b + threadIdx.x; p < e; p += kHubBlock) {
     const int32_t jj = a.cols[p];
-    if (!a.nact[jj]) a.nact[jj] = 1;
+    if (!sv.nact[jj]) sv.nact[jj] = 1;
   }
 }
 
@@ -397,7 +405,7 @@ hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L
   }
   hub_merge<<<(unsigned)parts, kMergeBlock, 0, s>>>(a, h);
   hub_decide<<<(unsigned)((k1 - k0 + 255) / 256), 256, 0, s>>>(a, h);
-  if (a.mark) hub_mark<<<(unsigned)chunks, kHubBlock, 0, s>>>(a, h);
+  hub_mark<<<(unsigned)chunks, kHubBlock, 0, s>>>(a, h);  // returns at once unless marking
   return hipGetLastError();
 }
 

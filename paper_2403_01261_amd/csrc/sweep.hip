@@ -57,11 +57,13 @@ template <int D>
 __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *__restrict__ list,
                                                     int64_t first, int64_t count) {
   __shared__ unsigned long long red[256 / kWave];
+  SweepView sv;
+  if (!sweep_view(a, sv)) return;
   LocalCounts lc;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
     const int32_t v = list ? list[first + idx] : (int32_t)(first + idx);
-    if (!a.dense && !a.act[v]) continue;
+    if (!sweep_takes(a, sv, v)) continue;
     const int64_t b = a.off[v];
     const int d = (int)(a.off[v + 1] - b);
     int32_t col[D];
@@ -93,11 +95,11 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
       const uint32_t cstar = key_label(best);
       if (cstar != (uint32_t)a.C[v]) {
         record_change(a, v, cstar, lc);
-        if (a.mark)
+        if (sv.mark)
 #pragma unroll
           for (int k = 0; k < D; ++k)
             if (k < d) {
-              if (!a.nact[col[k]]) a.nact[col[k]] = 1;
+              if (!sv.nact[col[k]]) sv.nact[col[k]] = 1;
               lc.marked += 1;
             }
       }
@@ -125,6 +127,8 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
   __shared__ unsigned long long tab[GPB * S];
   __shared__ unsigned long long red[NW];
   __shared__ unsigned long long red2[NW];
+  SweepView sv;
+  if (!sweep_view(a, sv)) return;
   for (int s = threadIdx.x; s < GPB * S; s += BLOCK) tab[s] = kEmptySlot;
   __syncthreads();
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
     int32_t v = -1;
     if (idx < count) {
       v = list ? list[first + idx] : (int32_t)(first + idx);
-      if (!a.dense && !a.act[v]) v = -1;
+      if (!sweep_takes(a, sv, v)) v = -1;
     }
     int64_t b = 0, e = 0;
     int log2s = 1;
@@ -201,11 +205,11 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
         const uint32_t cstar = key_label(best);
         if (cstar != (uint32_t)a.C[v]) {
           if (lane == 0) record_change(a, v, cstar, lc);
-          if (a.mark) {
+          if (sv.mark) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
               if (j[k] >= 0) {
-                if (!a.nact[j[k]]) a.nact[j[k]] = 1;
+                if (!sv.nact[j[k]]) sv.nact[j[k]] = 1;
                 lc.marked += 1;
               }
           }
@@ -220,10 +224,12 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
 // Copies the new label of every changed vertex into C, clears chg and, when
 // requested, clears the active flags consumed by the sweep.  Four vertices per
 // thread; the flag arrays are padded to a multiple of 4 bytes.
-__global__ __launch_bounds__(256) void apply_changes(int32_t *__restrict__ C,
-                                                     const int32_t *__restrict__ Cn,
-                                                     uint8_t *__restrict__ chg,
-                                                     uint8_t *__restrict__ act_clear, int64_t n) {
+__global__ __launch_bounds__(256) void apply_changes(SweepArgs a, int32_t *__restrict__ C, int64_t n) {
+  SweepView sv;
+  if (!sweep_view(a, sv)) return;
+  const int32_t *__restrict__ Cn = a.Cn;
+  uint8_t *__restrict__ chg = a.chg;
+  uint8_t *act_clear = sv.dense ? nullptr : const_cast<uint8_t *>(sv.act);
   const int64_t quads = (n + 3) / 4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
@@ -315,13 +321,17 @@ hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, 
 
 namespace {
 __global__ void reduce_counts(const unsigned long long *__restrict__ part, TierGrids g,
-                              unsigned long long (*tier_stats)[4], unsigned long long *dn,
-                              unsigned long long *processed, unsigned long long *edges,
-                              unsigned long long *overflow) {
+                              unsigned long long (*tier_stats)[4], const SweepCtrl *ctrl,
+                              unsigned long long *dn, unsigned long long *processed,
+                              unsigned long long *edges, unsigned long long *overflow) {
   __shared__ unsigned long long red[256 / kWave];
   const int t = blockIdx.x;
   const int nb = g.g[t];
-  if (nb <= 0) return;
+  if (nb <= 0 || ctrl->done) return;
+  const int it = ctrl->it;
+  dn += it;
+  processed += it;
+  edges += it;
   const unsigned long long *r = part + (size_t)t * kMaxTierGrid * kCountFields;
   unsigned long long v[kCountFields] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
@@ -343,17 +353,178 @@ __global__ void reduce_counts(const unsigned long long *__restrict__ part, TierG
 }  // namespace
 
 hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
-                                unsigned long long (*tier_stats)[4], unsigned long long *dn,
-                                unsigned long long *processed, unsigned long long *edges,
-                                unsigned long long *overflow, hipStream_t s) {
-  reduce_counts<<<kNumTiers, 256, 0, s>>>(part, g, tier_stats, dn, processed, edges, overflow);
+                                unsigned long long (*tier_stats)[4], const SweepCtrl *ctrl,
+                                unsigned long long *dn, unsigned long long *processed,
+                                unsigned long long *edges, unsigned long long *overflow, hipStream_t s) {
+  reduce_counts<<<kNumTiers, 256, 0, s>>>(part, g, tier_stats, ctrl, dn, processed, edges, overflow);
   return hipGetLastError();
 }
 
-hipError_t launch_apply(int32_t *C, const int32_t *Cn, uint8_t *chg, uint8_t *act_clear, int64_t n,
-                        hipStream_t s) {
+hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  apply_changes<<<grid_for((n + 3) / 4, 256, 256 * 32), 256, 0, s>>>(C, Cn, chg, act_clear, n);
+  apply_changes<<<grid_for((n + 3) / 4, 256, 256 * 32), 256, 0, s>>>(a, C, n);
+  return hipGetLastError();
+}
+
+namespace {
+
+// After a sweep: stop on overflow, convergence or the iteration cap; choose
+// the next sweep's mode.  A sweep marks neighbours only when the previous one
+// changed at most n/8 vertices; the sweep after a non-marking sweep runs
+// dense (pruning is exact, so processing extra vertices changes nothing).
+__global__ void sweep_end(SweepCtrl *c, const unsigned long long *dn, unsigned long long *marked_sweeps,
+                          const unsigned long long *overflow) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || c->done) return;
+  const unsigned long long d = dn[c->it];
+  marked_sweeps[c->it] = (unsigned long long)c->mark;
+  const int marked = c->mark;
+  c->it += 1;
+  if (*overflow) {
+    c->error = 1;
+    c->done = 1;
+    return;
+  }
+  bool stop = c->it >= c->max_iters;
+  if (c->graphs > 0) {
+    stop = stop || c->active == 0;
+    c->active = 0;
+  } else {
+    stop = stop || (int64_t)d <= c->limit;
+  }
+  c->done = stop ? 1 : 0;
+  c->dense = (c->prune && marked) ? 0 : 1;
+  c->mark = (c->prune && (int64_t)d * 8 <= c->n) ? 1 : 0;
+}
+
+// Sets up the loop state before the first sweep.  When the renumbering copy
+// already ran sweep 0 (first_flags bit 0 clear: every row strictly
+// increasing), the loop resumes at sweep 1 with that sweep's change count.
+__global__ void loop_init(SweepCtrl *c, const unsigned long long *first_flags, unsigned long long *dn,
+                          unsigned long long *marked_sweeps) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  c->it = 0;
+  c->error = 0;
+  c->active = 0;
+  c->dense = 1;
+  c->mark = 0;
+  c->done = c->max_iters <= 0 ? 1 : 0;
+  if (!first_flags || c->max_iters <= 0) return;
+  const unsigned long long ff = *first_flags;
+  if (ff & 1ull) {
+    dn[0] = 0;
+    return;
+  }
+  marked_sweeps[0] = 0;
+  c->it = 1;
+  if (ff & 2ull) {
+    c->error = 1;
+    c->done = 1;
+    return;
+  }
+  const int64_t d = (int64_t)dn[0];
+  c->done = (d <= c->limit || c->max_iters <= 1) ? 1 : 0;
+  c->mark = (c->prune && d * 8 <= c->n) ? 1 : 0;
+}
+
+// Largest dN with dN / n <= tolerance in IEEE double (n > 0); the same
+// search as the host's gsl_convergence_limit.
+__device__ int64_t conv_limit(int64_t n, double tol) {
+  const double dn = (double)n;
+  int64_t k = (int64_t)floor(__dmul_rn(tol, dn));
+  if (k < 0) k = 0;
+  if (k > n) k = n;
+  while (k > 0 && !(__ddiv_rn((double)k, dn) <= tol)) --k;
+  while (k < n && __ddiv_rn((double)(k + 1), dn) <= tol) ++k;
+  return k;
+}
+
+// Block per graph of a batch: graph id of each vertex, convergence limit,
+// sweep count and stop flag (graphs without vertices, or max_iters 0, never
+// run).
+__global__ __launch_bounds__(256) void batch_init(const int64_t *__restrict__ vtx_base, int64_t graphs,
+                                                  int32_t max_iters, double tol, int32_t *__restrict__ gid,
+                                                  int64_t *__restrict__ glimit, int32_t *__restrict__ giters,
+                                                  uint8_t *__restrict__ gdone) {
+  for (int64_t g = blockIdx.x; g < graphs; g += gridDim.x) {
+    const int64_t b = vtx_base[g], e = vtx_base[g + 1];
+    for (int64_t v = b + threadIdx.x; v < e; v += blockDim.x) gid[v] = (int32_t)g;
+    if (threadIdx.x == 0) {
+      glimit[g] = e > b ? conv_limit(e - b, tol) : 0;
+      giters[g] = 0;
+      gdone[g] = (e <= b || max_iters <= 0) ? 1 : 0;
+    }
+  }
+}
+
+// Block per graph: changes of this sweep inside the graph's vertex range.
+__global__ __launch_bounds__(256) void graph_count(SweepArgs a, const int64_t *__restrict__ vtx_base,
+                                                   int64_t graphs, int64_t *__restrict__ gdn) {
+  __shared__ unsigned long long red[256 / kWave];
+  if (a.ctrl->done) return;
+  for (int64_t g = blockIdx.x; g < graphs; g += gridDim.x) {
+    unsigned long long cnt = 0;
+    if (!a.gdone[g])
+      for (int64_t v = vtx_base[g] + threadIdx.x; v < vtx_base[g + 1]; v += blockDim.x) cnt += a.chg[v];
+    cnt = block_sum(cnt, red);
+    if (threadIdx.x == 0) gdn[g] = (int64_t)cnt;
+    __syncthreads();
+  }
+}
+
+// Thread per graph: count the sweep, stop graphs that converged or reached
+// the cap, and add the graphs still running to ctrl->active.
+__global__ __launch_bounds__(256) void graph_end(SweepCtrl *c, const int64_t *__restrict__ gdn,
+                                                 const int64_t *__restrict__ glimit, int32_t *giters,
+                                                 uint8_t *gdone, int64_t graphs) {
+  __shared__ unsigned long long red[256 / kWave];
+  if (c->done) return;
+  unsigned long long running = 0;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < graphs && !gdone[g]) {
+    const int32_t it = giters[g] + 1;
+    giters[g] = it;
+    if (gdn[g] <= glimit[g] || it >= c->max_iters)
+      gdone[g] = 1;
+    else
+      running = 1;
+  }
+  running = block_sum(running, red);
+  if (threadIdx.x == 0 && running) atomicAdd(reinterpret_cast<unsigned long long *>(&c->active), running);
+}
+
+}  // namespace
+
+hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsigned long long *marked_sweeps,
+                            const unsigned long long *overflow, hipStream_t s) {
+  sweep_end<<<1, 64, 0, s>>>(ctrl, dn, marked_sweeps, overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_flags, unsigned long long *dn,
+                            unsigned long long *marked_sweeps, hipStream_t s) {
+  loop_init<<<1, 64, 0, s>>>(ctrl, first_flags, dn, marked_sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const int64_t *vtx_base, int64_t graphs, int32_t max_iters, double tol,
+                             int32_t *gid, int64_t *glimit, int32_t *giters, uint8_t *gdone, hipStream_t s) {
+  if (graphs <= 0) return hipSuccess;
+  batch_init<<<grid_for(graphs, 1, 256 * 16), 256, 0, s>>>(vtx_base, graphs, max_iters, tol, gid, glimit,
+                                                          giters, gdone);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_count(const SweepArgs &a, const int64_t *vtx_base, int64_t graphs, int64_t *gdn,
+                              hipStream_t s) {
+  if (graphs <= 0) return hipSuccess;
+  graph_count<<<grid_for(graphs, 1, 256 * 16), 256, 0, s>>>(a, vtx_base, graphs, gdn);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_end(SweepCtrl *ctrl, const int64_t *gdn, const int64_t *glimit, int32_t *giters,
+                            uint8_t *gdone, int64_t graphs, hipStream_t s) {
+  if (graphs <= 0) return hipSuccess;
+  graph_end<<<grid_for(graphs, 256, 1 << 20), 256, 0, s>>>(ctrl, gdn, glimit, giters, gdone, graphs);
   return hipGetLastError();
 }
 
