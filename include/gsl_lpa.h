@@ -24,8 +24,11 @@
  *  - Calls return a gsl_status.  No C++ exception crosses the ABI.  On error
  *    gsl_last_error() returns a message for the calling thread; outputs are
  *    unspecified.
- *  - Calls are not re-entrant on one device: two threads must not run calls
- *    on the same device at the same time.
+ *  - Calls without a context argument share one scratch cache per device
+ *    and are serialised by a process-wide lock.  Calls on different
+ *    gsl_context objects (gsl_lpa_graphs) have their own scratch and stream
+ *    and may run at the same time from different host threads; their work
+ *    then overlaps on the device.
  */
 #ifndef GSL_LPA_H
 #define GSL_LPA_H
@@ -148,6 +151,80 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
  */
 int gsl_modularity(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
                    const int32_t *labels, double *q_out);
+
+/*
+ * gsl_lpa_batched -- GSL-LPA on a batch of independent graphs in one run.
+ *
+ * Every graph gets exactly the result gsl_lpa would give it alone: its own
+ * sweeps, its own convergence test dN_g / n_g <= tolerance and its own sweep
+ * count (a graph that has stopped takes no further part), then the split.
+ * The batch is one concatenated CSR with LOCAL vertex ids:
+ *
+ *   num_graphs : G >= 0
+ *   vtx_base   : int64[G+1]; graph g owns rows [vtx_base[g], vtx_base[g+1]),
+ *                vtx_base[0] == 0, non-decreasing, N = vtx_base[G] < 2^31
+ *   edge_base  : int64[G+1]; graph g owns entries [edge_base[g],
+ *                edge_base[g+1]), edge_base[0] == 0, non-decreasing,
+ *                edge_base[g] == offsets[vtx_base[g]]
+ *   offsets    : int64[N+1], positions in the concatenated cols array
+ *   cols       : int32[nnz], graph g's entries in [0, n_g) (local ids)
+ *   weights    : uint32[nnz] or NULL (every weight 1)
+ *   labels_out : int32[N]; graph g's labels (local ids) at vtx_base[g] ...
+ *
+ * Base arrays that do not start at 0, end at N and offsets[N], or decrease
+ * give GSL_EINVAL (checked on the device).  The library builds a global-id
+ * copy of cols (nnz * 4 bytes of scratch).
+ */
+int gsl_lpa_batched(int64_t num_graphs, const int64_t *vtx_base, const int64_t *edge_base,
+                    const int64_t *offsets, const int32_t *cols, const uint32_t *weights,
+                    int32_t max_iters, double tolerance, int32_t *labels_out);
+
+/*
+ * gsl_lpa_batched_ex -- gsl_lpa_batched with options (the layout field is
+ * ignored: batches keep their vertex order), statistics of the whole batch
+ * (iterations = the largest per-graph sweep count) and iterations_out, an
+ * int32[G] DEVICE array receiving each graph's sweep count (may be NULL).
+ */
+int gsl_lpa_batched_ex(int64_t num_graphs, const int64_t *vtx_base, const int64_t *edge_base,
+                       const int64_t *offsets, const int32_t *cols, const uint32_t *weights,
+                       int32_t max_iters, double tolerance, const gsl_options *opt,
+                       gsl_stats *stats, int32_t *labels_out, int32_t *iterations_out);
+
+/* One graph of a batch of separate graphs; all pointers are device pointers.
+ * Row v's entries are cols[offsets[v] .. offsets[v+1]) (offsets[0] need not
+ * be 0), with local ids in [0, n). */
+typedef struct gsl_graph {
+  const int64_t *offsets;  /* int64[n+1] (may be NULL when n == 0) */
+  const int32_t *cols;
+  const uint32_t *weights; /* NULL: every weight 1 */
+  int32_t *labels_out;     /* int32[n] */
+  int64_t n;
+} gsl_graph;
+
+/* A context: scratch memory and a stream of its own (created non-blocking, at
+ * default priority, on the current device). */
+typedef struct gsl_context gsl_context;
+
+int gsl_context_create(gsl_context **out);
+/* Waits for the context's stream, frees its scratch (and its stream unless
+ * one was set with gsl_context_set_stream). */
+void gsl_context_destroy(gsl_context *ctx);
+/* Use a caller-owned stream (hipStream_t) from now on. */
+int gsl_context_set_stream(gsl_context *ctx, void *hip_stream);
+/* The context's stream (hipStream_t). */
+void *gsl_context_stream(gsl_context *ctx);
+
+/*
+ * gsl_lpa_graphs -- gsl_lpa_batched for G graphs held in separate arrays
+ * (host array graphs[G] of descriptors), run in one batch on the context
+ * (NULL: the shared per-device scratch and the gsl_set_stream stream).  The
+ * library gathers the graphs into one global CSR (offsets, cols and, if any
+ * graph has weights, weights: (N + 1) * 8 + nnz * 4 (* 2) bytes of scratch)
+ * and writes each graph's labels to its labels_out.  iterations_out is a
+ * HOST int32[G] array (may be NULL).  Synchronous like every call.
+ */
+int gsl_lpa_graphs(gsl_context *ctx, int64_t num_graphs, const gsl_graph *graphs, int32_t max_iters,
+                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iterations_out);
 
 /*
  * gsl_convergence_limit -- host-only helper: the largest k in [0, n] with

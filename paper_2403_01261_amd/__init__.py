@@ -14,8 +14,9 @@ import os
 
 import torch
 
-__all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_split", "gsl_modularity", "gsl_convergence_limit",
-           "gsl_set_stream", "gsl_release", "gsl_version", "GslError", "LIB_PATH", "load"]
+__all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_batched", "gsl_lpa_graphs", "Context", "gsl_split",
+           "gsl_modularity", "gsl_convergence_limit", "gsl_set_stream", "gsl_release", "gsl_version",
+           "GslError", "LIB_PATH", "load"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgsl_lpa.so")
 STATS_MAX_ITERS = 64
@@ -57,6 +58,11 @@ class _Stats(ctypes.Structure):
                 ("ms_tier", ctypes.c_float * STATS_TIERS)]
 
 
+class _Graph(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("labels_out", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
 _lib = None
 _VP = ctypes.c_void_p
 
@@ -75,6 +81,20 @@ def load(path: str = None):
     lib.gsl_lpa.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _VP]
     lib.gsl_lpa_ex.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                ctypes.POINTER(_Options), ctypes.POINTER(_Stats), _VP]
+    lib.gsl_lpa_batched.argtypes = [ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32,
+                                    ctypes.c_double, _VP]
+    lib.gsl_lpa_batched_ex.argtypes = [ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.POINTER(_Options), ctypes.POINTER(_Stats),
+                                       _VP, _VP]
+    lib.gsl_context_create.argtypes = [ctypes.POINTER(_VP)]
+    lib.gsl_context_destroy.argtypes = [_VP]
+    lib.gsl_context_destroy.restype = None
+    lib.gsl_context_set_stream.argtypes = [_VP, _VP]
+    lib.gsl_context_stream.argtypes = [_VP]
+    lib.gsl_context_stream.restype = _VP
+    lib.gsl_lpa_graphs.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_Graph), ctypes.c_int32,
+                                   ctypes.c_double, ctypes.POINTER(_Options), ctypes.POINTER(_Stats),
+                                   ctypes.POINTER(ctypes.c_int32)]
     lib.gsl_split.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP]
     lib.gsl_modularity.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]
     lib.gsl_convergence_limit.argtypes = [ctypes.c_int64, ctypes.c_double]
@@ -83,7 +103,9 @@ def load(path: str = None):
     lib.gsl_last_error.restype = ctypes.c_char_p
     lib.gsl_version.restype = ctypes.c_char_p
     lib.gsl_release.restype = None
-    for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream):
+    for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream,
+              lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
+              lib.gsl_lpa_graphs):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -163,6 +185,119 @@ def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=
                         "sparse_launches": st.tier_sparse[t], "ms": st.ms_tier[t]}
                        for t in range(STATS_TIERS)]}
     return out, stats
+
+
+def _stats_dict(st):
+    it = st.iterations
+    k = min(it, STATS_MAX_ITERS)
+    return {"iterations": it, "changed": list(st.changed[:k]), "processed": list(st.processed[:k]),
+            "edges": list(st.edges[:k]), "marked": list(st.marked[:k]), "nnz": st.nnz,
+            "max_degree": st.max_degree, "ms_plan": st.ms_plan, "ms_sweeps": st.ms_sweeps,
+            "ms_split": st.ms_split, "ms_total": st.ms_total, "ms_sweep": list(st.ms_sweep[:k])}
+
+
+def gsl_lpa_batched(vtx_base, edge_base, offsets, cols, weights=None, max_iters=20, tolerance=0.05,
+                    prune=True, split=True, timing=False, out=None):
+    """A batch of independent graphs as one concatenated CSR (local ids; see
+    include/gsl_lpa.h).  Returns (labels, per-graph sweep counts, stats)."""
+    lib = _bind_stream()
+    G = vtx_base.numel() - 1
+    if G < 0 or edge_base.numel() != G + 1:
+        raise ValueError("vtx_base and edge_base must hold num_graphs + 1 entries")
+    po, pc, pw, n = _graph_args(offsets, cols, weights)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    if out.numel() != n:
+        raise ValueError("out must hold N labels")
+    iters = torch.zeros(max(G, 0), dtype=torch.int32, device=offsets.device)
+    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), 2)
+    st = _Stats()
+    _check(lib.gsl_lpa_batched_ex(G, _dev(vtx_base, (torch.int64,), "vtx_base"),
+                                  _dev(edge_base, (torch.int64,), "edge_base"), po, pc, pw,
+                                  int(max_iters), float(tolerance), ctypes.byref(opt), ctypes.byref(st),
+                                  _dev(out, (torch.int32,), "out"),
+                                  _dev(iters, (torch.int32,), "iters") if G else None))
+    return out, iters, _stats_dict(st)
+
+
+def _graph_table(graphs):
+    tab = (_Graph * max(len(graphs), 1))()
+    outs = []
+    for k, gr in enumerate(graphs):
+        offsets, cols, weights = gr[0], gr[1], gr[2] if len(gr) > 2 else None
+        out = gr[3] if len(gr) > 3 and gr[3] is not None else None
+        n = offsets.numel() - 1
+        if n < 0:
+            raise ValueError("graph %d: offsets must hold n + 1 entries" % k)
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=offsets.device)
+        if out.numel() != n:
+            raise ValueError("graph %d: out must hold n labels" % k)
+        tab[k].offsets = _dev(offsets, (torch.int64,), "offsets")
+        tab[k].cols = _dev(cols, (torch.int32,), "cols")
+        tab[k].weights = _dev(weights, _U32, "weights", allow_none=True)
+        tab[k].labels_out = _dev(out, (torch.int32,), "out")
+        tab[k].n = n
+        outs.append(out)
+    return tab, outs
+
+
+def gsl_lpa_graphs(graphs, max_iters=20, tolerance=0.05, prune=True, split=True, ctx=None):
+    """A batch of separate graphs: graphs is a list of (offsets, cols[,
+    weights[, out]]) tensors.  Returns (list of labels, list of sweep counts,
+    stats).  ctx: a Context (its own scratch and stream) or None."""
+    if ctx is not None:
+        return ctx.lpa_graphs(graphs, max_iters, tolerance, prune, split)
+    lib = _bind_stream()
+    return _run_graphs(lib, None, graphs, max_iters, tolerance, prune, split)
+
+
+def _run_graphs(lib, handle, graphs, max_iters, tolerance, prune, split):
+    tab, outs = _graph_table(graphs)
+    G = len(graphs)
+    iters = (ctypes.c_int32 * max(G, 1))()
+    opt = _Options(int(bool(prune)), int(bool(split)), 0, 2)
+    st = _Stats()
+    _check(lib.gsl_lpa_graphs(handle, G, tab, int(max_iters), float(tolerance), ctypes.byref(opt),
+                              ctypes.byref(st), iters))
+    return outs, list(iters[:G]), _stats_dict(st)
+
+
+class Context:
+    """Scratch memory and a stream of its own (gsl_context).  Calls on
+    different contexts may run at once from different threads; ctypes drops
+    the GIL during the call, so their work overlaps on the device."""
+
+    def __init__(self):
+        self._lib = load()
+        h = _VP()
+        _check(self._lib.gsl_context_create(ctypes.byref(h)))
+        self._h = h
+        self.stream = torch.cuda.ExternalStream(self._lib.gsl_context_stream(h))
+
+    def lpa_graphs(self, graphs, max_iters=20, tolerance=0.05, prune=True, split=True):
+        if self._h is None:
+            raise RuntimeError("context closed")
+        # inputs written on torch's current stream must be ready first
+        self.stream.wait_stream(torch.cuda.current_stream())
+        return _run_graphs(self._lib, self._h, graphs, max_iters, tolerance, prune, split)
+
+    def close(self):
+        if self._h is not None:
+            self._lib.gsl_context_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gsl_split(offsets, cols, labels_in, out=None):

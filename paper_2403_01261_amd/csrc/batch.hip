@@ -1,0 +1,205 @@
+// Batches of independent graphs run as one graph.
+//
+// A batch is laid out as one CSR over the concatenated vertex ranges, with
+// global vertex ids: graph g owns vertices [vtx_base[g], vtx_base[g+1]) and
+// entries [edge_base[g], edge_base[g+1]).  The graphs share no edge, so every
+// sweep, the split and the per-graph convergence tests see exactly what each
+// graph would see alone; only the vertex ids carry the graph's base.  The
+// kernels here build that layout from the caller's local-id input and turn the
+// result back into local labels.
+//
+// Work is spread over fixed tiles of consecutive entries (or vertices); a
+// tile finds its first graph by binary search over the base array and each
+// thread steps forward from there, so graph sizes that differ by 1000x do not
+// unbalance the launch.
+#include "device_common.h"
+#include "gsl_internal.h"
+
+namespace gsl {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kPerThread = 16;
+constexpr int64_t kTile = (int64_t)kBlock * kPerThread;
+
+// Last g in [0, G) with base[g] <= x (base non-decreasing, base[0] <= x).
+__device__ int64_t graph_of(const int64_t *__restrict__ base, int64_t G, int64_t x) {
+  int64_t lo = 0, hi = G - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// First graph of each tile, found once per block.
+__device__ int64_t tile_graph(const int64_t *__restrict__ base, int64_t G, int64_t x0) {
+  __shared__ int64_t g0;
+  __syncthreads();
+  if (threadIdx.x == 0) g0 = graph_of(base, G, x0);
+  __syncthreads();
+  return g0;
+}
+
+// Concatenated input: cols hold local ids; out = cols + vtx_base[graph].
+__global__ __launch_bounds__(kBlock) void globalize_cols(const int32_t *__restrict__ cols,
+                                                         const int64_t *__restrict__ edge_base,
+                                                         const int64_t *__restrict__ vtx_base, int64_t G,
+                                                         int64_t nnz, int32_t *__restrict__ out) {
+  for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < nnz; t0 += (int64_t)gridDim.x * kTile) {
+    int64_t g = tile_graph(edge_base, G, t0);
+#pragma unroll 4
+    for (int j = 0; j < kPerThread; ++j) {
+      const int64_t e = t0 + (int64_t)j * kBlock + threadIdx.x;
+      if (e >= nnz) break;
+      while (edge_base[g + 1] <= e) ++g;
+      out[e] = cols[e] + (int32_t)vtx_base[g];
+    }
+  }
+}
+
+// Separate graphs: entry counts offsets[n] - offsets[0] (thread per graph).
+__global__ void graph_entries(const GraphDesc *__restrict__ d, int64_t G, int64_t *__restrict__ cnt) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const GraphDesc x = d[g];
+  cnt[g] = x.n > 0 ? x.offsets[x.n] - x.offsets[0] : 0;
+}
+
+// Separate graphs -> one global CSR: offsets shifted to the graph's entry
+// base, cols shifted to its vertex base, weights copied (1 where a graph
+// passes none).
+__global__ __launch_bounds__(kBlock) void gather_offsets(const GraphDesc *__restrict__ d,
+                                                         const int64_t *__restrict__ vtx_base,
+                                                         const int64_t *__restrict__ edge_base, int64_t G,
+                                                         int64_t N, int64_t *__restrict__ off) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) off[N] = edge_base[G];
+  for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < N; t0 += (int64_t)gridDim.x * kTile) {
+    int64_t g = tile_graph(vtx_base, G, t0);
+#pragma unroll 4
+    for (int j = 0; j < kPerThread; ++j) {
+      const int64_t v = t0 + (int64_t)j * kBlock + threadIdx.x;
+      if (v >= N) break;
+      while (vtx_base[g + 1] <= v) ++g;
+      const int64_t *o = d[g].offsets;
+      off[v] = edge_base[g] + (o[v - vtx_base[g]] - o[0]);
+    }
+  }
+}
+
+// Base arrays must start at 0, end at the totals and never decrease.
+__global__ void check_bases(const int64_t *__restrict__ vtx_base, const int64_t *__restrict__ edge_base,
+                            int64_t G, int64_t N, int64_t nnz, unsigned long long *bad) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > G) return;
+  bool ok = true;
+  if (g == 0) ok = vtx_base[0] == 0 && edge_base[0] == 0;
+  else ok = vtx_base[g] >= vtx_base[g - 1] && edge_base[g] >= edge_base[g - 1];
+  if (g == G) ok = ok && vtx_base[G] == N && edge_base[G] == nnz;
+  if (!ok) atomicOr(bad, 1ull);
+}
+
+__global__ __launch_bounds__(kBlock) void gather_entries(const GraphDesc *__restrict__ d,
+                                                         const int64_t *__restrict__ vtx_base,
+                                                         const int64_t *__restrict__ edge_base, int64_t G,
+                                                         int64_t nnz, int32_t *__restrict__ cols,
+                                                         uint32_t *__restrict__ w) {
+  for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < nnz; t0 += (int64_t)gridDim.x * kTile) {
+    int64_t g = tile_graph(edge_base, G, t0);
+#pragma unroll 4
+    for (int j = 0; j < kPerThread; ++j) {
+      const int64_t e = t0 + (int64_t)j * kBlock + threadIdx.x;
+      if (e >= nnz) break;
+      while (edge_base[g + 1] <= e) ++g;
+      const GraphDesc x = d[g];
+      const int64_t src = x.offsets[0] + (e - edge_base[g]);
+      cols[e] = x.cols[src] + (int32_t)vtx_base[g];
+      if (w) w[e] = x.weights ? x.weights[src] : 1u;
+    }
+  }
+}
+
+// Global labels -> local labels (in place).
+__global__ __launch_bounds__(kBlock) void localize(int32_t *__restrict__ lab, const int64_t *__restrict__ vtx_base,
+                                                   int64_t G, int64_t N) {
+  for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < N; t0 += (int64_t)gridDim.x * kTile) {
+    int64_t g = tile_graph(vtx_base, G, t0);
+#pragma unroll 4
+    for (int j = 0; j < kPerThread; ++j) {
+      const int64_t v = t0 + (int64_t)j * kBlock + threadIdx.x;
+      if (v >= N) break;
+      while (vtx_base[g + 1] <= v) ++g;
+      lab[v] -= (int32_t)vtx_base[g];
+    }
+  }
+}
+
+// Local labels of the batch -> each graph's own output array.
+__global__ __launch_bounds__(kBlock) void scatter_labels(const GraphDesc *__restrict__ d,
+                                                         const int32_t *__restrict__ lab,
+                                                         const int64_t *__restrict__ vtx_base, int64_t G,
+                                                         int64_t N) {
+  for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < N; t0 += (int64_t)gridDim.x * kTile) {
+    int64_t g = tile_graph(vtx_base, G, t0);
+#pragma unroll 4
+    for (int j = 0; j < kPerThread; ++j) {
+      const int64_t v = t0 + (int64_t)j * kBlock + threadIdx.x;
+      if (v >= N) break;
+      while (vtx_base[g + 1] <= v) ++g;
+      d[g].labels_out[v - vtx_base[g]] = lab[v];
+    }
+  }
+}
+
+unsigned tiles(int64_t count) {
+  const int64_t t = (count + kTile - 1) / kTile;
+  const int64_t cap = 256 * 64;
+  return (unsigned)(t < 1 ? 1 : (t > cap ? cap : t));
+}
+
+}  // namespace
+
+hipError_t launch_globalize_cols(const int32_t *cols, const int64_t *edge_base, const int64_t *vtx_base,
+                                 int64_t G, int64_t nnz, int32_t *out, hipStream_t s) {
+  if (nnz <= 0 || G <= 0) return hipSuccess;
+  globalize_cols<<<tiles(nnz), kBlock, 0, s>>>(cols, edge_base, vtx_base, G, nnz, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_bases(const int64_t *vtx_base, const int64_t *edge_base, int64_t G, int64_t N,
+                              int64_t nnz, unsigned long long *bad, hipStream_t s) {
+  check_bases<<<(unsigned)((G + 1 + 255) / 256), 256, 0, s>>>(vtx_base, edge_base, G, N, nnz, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_entries(const GraphDesc *d, int64_t G, int64_t *cnt, hipStream_t s) {
+  if (G <= 0) return hipSuccess;
+  graph_entries<<<(unsigned)((G + 255) / 256), 256, 0, s>>>(d, G, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GraphDesc *d, const int64_t *vtx_base, const int64_t *edge_base, int64_t G,
+                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, hipStream_t s) {
+  if (G <= 0) return hipSuccess;
+  gather_offsets<<<tiles(N + 1), kBlock, 0, s>>>(d, vtx_base, edge_base, G, N, off);
+  if (nnz > 0) gather_entries<<<tiles(nnz), kBlock, 0, s>>>(d, vtx_base, edge_base, G, nnz, cols, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_localize(int32_t *lab, const int64_t *vtx_base, int64_t G, int64_t N, hipStream_t s) {
+  if (N <= 0 || G <= 0) return hipSuccess;
+  localize<<<tiles(N), kBlock, 0, s>>>(lab, vtx_base, G, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_labels(const GraphDesc *d, const int32_t *lab, const int64_t *vtx_base, int64_t G,
+                                 int64_t N, hipStream_t s) {
+  if (N <= 0 || G <= 0) return hipSuccess;
+  scatter_labels<<<tiles(N), kBlock, 0, s>>>(d, lab, vtx_base, G, N);
+  return hipGetLastError();
+}
+
+}  // namespace gsl

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -82,12 +83,35 @@ struct Scratch {
   hipGraphExec_t loop_exec = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream the loop graph is captured on
   std::vector<uint64_t> loop_key;
-  // batches: graph of every vertex, per-graph limits / counts / flags
+  // batches: graph of every vertex, per-graph limits / counts / flags, the
+  // base arrays and descriptors of separate graphs, and the global copy
   int64_t batch_n_cap = -1, batch_g_cap = -1;
   int32_t *gid = nullptr, *giters = nullptr;
   int64_t *glimit = nullptr, *gdn = nullptr;
   uint8_t *gdone = nullptr;
+  int64_t *gvb = nullptr, *geb = nullptr, *gcnt = nullptr;
+  gsl::GraphDesc *gdesc = nullptr;
+  unsigned long long *gbad = nullptr;
+  int32_t *glab = nullptr;
+  int64_t *goff = nullptr;
+  int64_t gcols_cap = -1, gw_cap = -1, goff_cap = -1, batch_glab_cap = -1;
+  int32_t *gcols = nullptr;
+  uint32_t *gw = nullptr;
 };
+
+}  // namespace
+
+// A context: its own scratch and stream, so calls on different contexts (from
+// different host threads) run concurrently on the device.
+struct gsl_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::mutex mu;
+  Scratch s;
+};
+
+namespace {
 
 // Returns event k of the pool, creating events on demand.
 hipEvent_t pool_event(Scratch &s, size_t k) {
@@ -133,6 +157,15 @@ void free_scratch(Scratch &s) {
   hipFree(s.glimit);
   hipFree(s.gdn);
   hipFree(s.gdone);
+  hipFree(s.gvb);
+  hipFree(s.geb);
+  hipFree(s.gcnt);
+  hipFree(s.gdesc);
+  hipFree(s.gbad);
+  hipFree(s.glab);
+  hipFree(s.goff);
+  hipFree(s.gcols);
+  hipFree(s.gw);
   hipFree(s.old2new);
   hipFree(s.lab2);
   hipFree(s.minorig);
@@ -376,7 +409,10 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 // gsl_lpa_batched); NULL for a single graph.
 struct Batch {
   int64_t graphs;
-  const int64_t *vtx_base;  // device [graphs + 1]
+  const int64_t *vtx_base;         // device [graphs + 1]
+  int32_t *iters_dev;              // per-graph sweep counts out (device) or NULL
+  int32_t *iters_host;             // per-graph sweep counts out (host) or NULL
+  const gsl::GraphDesc *scatter;   // separate graphs: descriptors of the outputs, else NULL
 };
 
 // One timing record: an event pair around a launch of tier `tier` in sweep
@@ -386,8 +422,8 @@ struct Launch {
   size_t ev;
 };
 
-int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
-             int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
+int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *cols, const uint32_t *weights,
+             int64_t n, int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
              int32_t *labels_out, const Batch *batch = nullptr) {
   gsl_options o = {1, 1, 0, 0};
   if (opt) o = *opt;
@@ -397,11 +433,7 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
   if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
   if (n == 0) return GSL_OK;
   if (!offsets || !labels_out) return fail(GSL_EINVAL, "offsets and labels_out must not be NULL");
-  const hipStream_t st = g_stream;
-  Scratch *sp = nullptr;
-  int rc = get_scratch(&sp);
-  if (rc) return rc;
-  Scratch &s = *sp;
+  int rc = GSL_OK;
   int64_t nnz = 0;
   if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
   if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
@@ -623,6 +655,17 @@ int lpa_impl(const int64_t *offsets, const int32_t *cols, const uint32_t *weight
     HIP_TRY(gsl::launch_split(offsets, cols, n, C, s.parent, labels_out, s.list, plan.tier_count,
                               plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), st));
   }
+  if (batch) {
+    HIP_TRY(gsl::launch_localize(labels_out, batch->vtx_base, batch->graphs, n, st));
+    if (batch->scatter)
+      HIP_TRY(gsl::launch_scatter_labels(batch->scatter, labels_out, batch->vtx_base, batch->graphs, n, st));
+    if (batch->iters_dev)
+      HIP_TRY(hipMemcpyAsync(batch->iters_dev, s.giters, (size_t)batch->graphs * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, st));
+    if (batch->iters_host)
+      HIP_TRY(hipMemcpyAsync(batch->iters_host, s.giters, (size_t)batch->graphs * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, st));
+  }
   if (timed) HIP_TRY(hipEventRecord(s.ev[3], st));
   gsl::SweepCtrl fc;
   HIP_TRY(hipMemcpyAsync(&fc, s.ctrl, sizeof(fc), hipMemcpyDeviceToHost, st));
@@ -702,21 +745,297 @@ int check_labels(Scratch &s, const int32_t *labels, int64_t n, hipStream_t st) {
   return GSL_OK;
 }
 
+// Host-only argument checks, run before any HIP call.  Return GSL_OK to go
+// on, kNoop when the call has nothing to do, or an error status.
+constexpr int kNoop = 1;
+
+int check_lpa(int64_t n, int32_t max_iters, double tolerance, const int64_t *offsets, const int32_t *labels_out) {
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n = %lld out of range", (long long)n);
+  if (max_iters < 0) return fail(GSL_EINVAL, "max_iters must be >= 0");
+  if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
+  if (n == 0) return kNoop;
+  if (!offsets || !labels_out) return fail(GSL_EINVAL, "offsets and labels_out must not be NULL");
+  return GSL_OK;
+}
+
+int check_batch(int64_t G, int32_t max_iters, double tolerance) {
+  if (G < 0 || G >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "num_graphs out of range");
+  if (max_iters < 0) return fail(GSL_EINVAL, "max_iters must be >= 0");
+  if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
+  return G == 0 ? kNoop : GSL_OK;
+}
+
+// Per-graph arrays of a batch: N vertices, G graphs.
+int ensure_batch(Scratch &s, int64_t N, int64_t G) {
+  if (N > s.batch_n_cap) {
+    hipFree(s.gid);
+    s.gid = nullptr;
+    s.batch_n_cap = -1;
+    if (dmalloc(&s.gid, N) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "batch allocation (%lld vertices) failed", (long long)N);
+    }
+    s.batch_n_cap = N;
+  }
+  if (G > s.batch_g_cap) {
+    hipFree(s.giters);
+    hipFree(s.glimit);
+    hipFree(s.gdn);
+    hipFree(s.gdone);
+    hipFree(s.gvb);
+    hipFree(s.geb);
+    hipFree(s.gcnt);
+    hipFree(s.gdesc);
+    s.giters = nullptr; s.glimit = nullptr; s.gdn = nullptr; s.gdone = nullptr;
+    s.gvb = nullptr; s.geb = nullptr; s.gcnt = nullptr; s.gdesc = nullptr;
+    s.batch_g_cap = -1;
+    if (dmalloc(&s.giters, G) != hipSuccess || dmalloc(&s.glimit, G) != hipSuccess ||
+        dmalloc(&s.gdn, G) != hipSuccess || dmalloc(&s.gdone, G) != hipSuccess ||
+        dmalloc(&s.gvb, G + 1) != hipSuccess || dmalloc(&s.geb, G + 1) != hipSuccess ||
+        dmalloc(&s.gcnt, G) != hipSuccess || dmalloc(&s.gdesc, G) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "batch allocation (%lld graphs) failed", (long long)G);
+    }
+    s.batch_g_cap = G;
+  }
+  if (!s.gbad && dmalloc(&s.gbad, 1) != hipSuccess) return fail(GSL_ENOMEM, "device allocation failed");
+  return GSL_OK;
+}
+
+template <class T>
+int ensure_array(T **p, int64_t *cap, int64_t count, const char *what) {
+  if (count <= *cap) return GSL_OK;
+  hipFree(*p);
+  *p = nullptr;
+  *cap = -1;
+  if (dmalloc(p, count) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GSL_ENOMEM, "allocation of %s (%lld elements) failed", what, (long long)count);
+  }
+  *cap = count;
+  return GSL_OK;
+}
+
+// Batch as concatenated CSR: offsets index the concatenated cols (global
+// entry positions), cols hold local ids.
+int batched_concat(Scratch &s, hipStream_t st, int64_t G, const int64_t *vtx_base, const int64_t *edge_base,
+                   const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int32_t max_iters,
+                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *labels_out,
+                   int32_t *iters_out) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (G < 0 || G >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "num_graphs out of range");
+  if (max_iters < 0) return fail(GSL_EINVAL, "max_iters must be >= 0");
+  if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
+  if (G == 0) return GSL_OK;
+  if (!vtx_base || !edge_base || !offsets) return fail(GSL_EINVAL, "NULL argument");
+  int64_t ends[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&ends[0], vtx_base + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&ends[1], edge_base + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int64_t N = ends[0], nnz = ends[1];
+  if (N < 0 || N >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "total vertex count %lld out of range", (long long)N);
+  if (nnz < 0) return fail(GSL_EINVAL, "edge_base[num_graphs] must be >= 0");
+  if (N == 0) {
+    if (iters_out) HIP_TRY(hipMemsetAsync(iters_out, 0, (size_t)G * sizeof(int32_t), st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GSL_OK;
+  }
+  if (!labels_out) return fail(GSL_EINVAL, "labels_out must not be NULL");
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when entries exist");
+  int64_t total = 0;
+  int rc = read_nnz(offsets, N, &total, st);
+  if (rc) return rc;
+  if (total != nnz) return fail(GSL_EINVAL, "offsets[N] (%lld) differs from edge_base[num_graphs] (%lld)",
+                                (long long)total, (long long)nnz);
+  if ((rc = ensure_batch(s, N, G))) return rc;
+  unsigned long long bad = 0;
+  HIP_TRY(hipMemsetAsync(s.gbad, 0, sizeof(unsigned long long), st));
+  HIP_TRY(gsl::launch_check_bases(vtx_base, edge_base, G, N, nnz, s.gbad, st));
+  HIP_TRY(hipMemcpyAsync(&bad, s.gbad, sizeof(bad), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (bad) return fail(GSL_EINVAL, "vtx_base / edge_base must start at 0, end at the totals and not decrease");
+  if ((rc = ensure_array(&s.gcols, &s.gcols_cap, nnz, "global cols"))) return rc;
+  HIP_TRY(gsl::launch_globalize_cols(cols, edge_base, vtx_base, G, nnz, s.gcols, st));
+  gsl_options o = {1, 1, 0, 0};
+  if (opt) o = *opt;
+  o.layout = 2;
+  const Batch b{G, vtx_base, iters_out, nullptr, nullptr};
+  return lpa_impl(s, st, offsets, s.gcols, weights, N, max_iters, tolerance, &o, stats, labels_out, &b);
+}
+
+// Batch of separate graphs (host array of descriptors).
+int batched_graphs(Scratch &s, hipStream_t st, int64_t G, const gsl_graph *graphs, int32_t max_iters,
+                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iters_out) {
+  static_assert(sizeof(gsl_graph) == sizeof(gsl::GraphDesc), "gsl_graph layout");
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (G < 0 || G >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "num_graphs out of range");
+  if (max_iters < 0) return fail(GSL_EINVAL, "max_iters must be >= 0");
+  if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
+  if (G == 0) return GSL_OK;
+  if (!graphs) return fail(GSL_EINVAL, "graphs must not be NULL");
+  std::vector<int64_t> vb((size_t)G + 1, 0);
+  for (int64_t g = 0; g < G; ++g) {
+    const gsl_graph &x = graphs[g];
+    if (x.n < 0 || x.n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "graph %lld: n out of range", (long long)g);
+    if (x.n > 0 && (!x.offsets || !x.labels_out))
+      return fail(GSL_EINVAL, "graph %lld: offsets and labels_out must not be NULL", (long long)g);
+    vb[(size_t)g + 1] = vb[(size_t)g] + x.n;
+    if (vb[(size_t)g + 1] >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "total vertex count out of range");
+  }
+  const int64_t N = vb[(size_t)G];
+  if (iters_out) memset(iters_out, 0, (size_t)G * sizeof(int32_t));
+  if (N == 0) return GSL_OK;
+  int rc = ensure_batch(s, N, G);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(s.gdesc, graphs, (size_t)G * sizeof(gsl_graph), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s.gvb, vb.data(), (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(gsl::launch_graph_entries(s.gdesc, G, s.gcnt, st));
+  std::vector<int64_t> cnt((size_t)G);
+  HIP_TRY(hipMemcpyAsync(cnt.data(), s.gcnt, (size_t)G * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int64_t> eb((size_t)G + 1, 0);
+  bool weighted = false;
+  for (int64_t g = 0; g < G; ++g) {
+    const gsl_graph &x = graphs[g];
+    if (cnt[(size_t)g] < 0) return fail(GSL_EINVAL, "graph %lld: offsets[n] < offsets[0]", (long long)g);
+    if (cnt[(size_t)g] > 0 && !x.cols) return fail(GSL_EINVAL, "graph %lld: cols must not be NULL", (long long)g);
+    eb[(size_t)g + 1] = eb[(size_t)g] + cnt[(size_t)g];
+    weighted = weighted || (x.weights != nullptr && cnt[(size_t)g] > 0);
+  }
+  const int64_t nnz = eb[(size_t)G];
+  HIP_TRY(hipMemcpyAsync(s.geb, eb.data(), (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  if ((rc = ensure_array(&s.goff, &s.goff_cap, N + 1, "global offsets"))) return rc;
+  if ((rc = ensure_array(&s.gcols, &s.gcols_cap, nnz, "global cols"))) return rc;
+  if (weighted && (rc = ensure_array(&s.gw, &s.gw_cap, nnz, "global weights"))) return rc;
+  if ((rc = ensure_array(&s.glab, &s.batch_glab_cap, N, "batch labels"))) return rc;
+  HIP_TRY(gsl::launch_gather(s.gdesc, s.gvb, s.geb, G, N, nnz, s.goff, s.gcols, weighted ? s.gw : nullptr, st));
+  gsl_options o = {1, 1, 0, 0};
+  if (opt) o = *opt;
+  o.layout = 2;
+  const Batch b{G, s.gvb, nullptr, iters_out, s.gdesc};
+  return lpa_impl(s, st, s.goff, s.gcols, weighted ? s.gw : nullptr, N, max_iters, tolerance, &o, stats, s.glab,
+                  &b);
+}
+
 }  // namespace
 
 extern "C" {
 
 int gsl_lpa(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
             int32_t max_iters, double tolerance, int32_t *labels_out) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  return lpa_impl(offsets, cols, weights, n, max_iters, tolerance, nullptr, nullptr, labels_out);
+  return gsl_lpa_ex(offsets, cols, weights, n, max_iters, tolerance, nullptr, nullptr, labels_out);
 }
 
 int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
                int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
                int32_t *labels_out) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  int rc = check_lpa(n, max_iters, tolerance, offsets, labels_out);
+  if (rc) return rc == kNoop ? GSL_OK : rc;
   std::lock_guard<std::mutex> lk(g_mu);
-  return lpa_impl(offsets, cols, weights, n, max_iters, tolerance, opt, stats, labels_out);
+  Scratch *sp = nullptr;
+  if ((rc = get_scratch(&sp))) return rc;
+  return lpa_impl(*sp, g_stream, offsets, cols, weights, n, max_iters, tolerance, opt, stats, labels_out);
+}
+
+int gsl_lpa_batched(int64_t num_graphs, const int64_t *vtx_base, const int64_t *edge_base, const int64_t *offsets,
+                    const int32_t *cols, const uint32_t *weights, int32_t max_iters, double tolerance,
+                    int32_t *labels_out) {
+  return gsl_lpa_batched_ex(num_graphs, vtx_base, edge_base, offsets, cols, weights, max_iters, tolerance,
+                            nullptr, nullptr, labels_out, nullptr);
+}
+
+int gsl_lpa_batched_ex(int64_t num_graphs, const int64_t *vtx_base, const int64_t *edge_base,
+                       const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int32_t max_iters,
+                       double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *labels_out,
+                       int32_t *iterations_out) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  int rc = check_batch(num_graphs, max_iters, tolerance);
+  if (rc) return rc == kNoop ? GSL_OK : rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Scratch *sp = nullptr;
+  if ((rc = get_scratch(&sp))) return rc;
+  return batched_concat(*sp, g_stream, num_graphs, vtx_base, edge_base, offsets, cols, weights, max_iters,
+                        tolerance, opt, stats, labels_out, iterations_out);
+}
+
+int gsl_context_create(gsl_context **out) {
+  if (!out) return fail(GSL_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  gsl_context *c = new (std::nothrow) gsl_context();
+  if (!c) return fail(GSL_ENOMEM, "host allocation failed");
+  c->device = dev;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(GSL_EDEVICE, "hipStreamCreateWithFlags failed");
+  }
+  c->own_stream = true;
+  *out = c;
+  return GSL_OK;
+}
+
+void gsl_context_destroy(gsl_context *ctx) {
+  if (!ctx) return;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (hipSetDevice(ctx->device) == hipSuccess) {
+      if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+      free_scratch(ctx->s);
+      if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+    }
+    if (have) (void)hipSetDevice(cur);
+  }
+  delete ctx;
+}
+
+int gsl_context_set_stream(gsl_context *ctx, void *hip_stream) {
+  if (!ctx) return fail(GSL_EINVAL, "ctx must not be NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (ctx->own_stream && ctx->stream) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipStreamDestroy(ctx->stream));
+  }
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  ctx->own_stream = false;
+  return GSL_OK;
+}
+
+void *gsl_context_stream(gsl_context *ctx) { return ctx ? reinterpret_cast<void *>(ctx->stream) : nullptr; }
+
+int gsl_lpa_graphs(gsl_context *ctx, int64_t num_graphs, const gsl_graph *graphs, int32_t max_iters,
+                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iterations_out) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  int rc = check_batch(num_graphs, max_iters, tolerance);
+  if (rc) return rc == kNoop ? GSL_OK : rc;
+  if (!graphs) return fail(GSL_EINVAL, "graphs must not be NULL");
+  int64_t total = 0;
+  for (int64_t g = 0; g < num_graphs; ++g) {
+    const gsl_graph &x = graphs[g];
+    if (x.n < 0 || x.n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "graph %lld: n out of range", (long long)g);
+    if (x.n > 0 && (!x.offsets || !x.labels_out))
+      return fail(GSL_EINVAL, "graph %lld: offsets and labels_out must not be NULL", (long long)g);
+    total += x.n;
+    if (total >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "total vertex count out of range");
+  }
+  if (total == 0) {
+    if (iterations_out) memset(iterations_out, 0, (size_t)num_graphs * sizeof(int32_t));
+    return GSL_OK;
+  }
+  if (!ctx) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Scratch *sp = nullptr;
+    if ((rc = get_scratch(&sp))) return rc;
+    return batched_graphs(*sp, g_stream, num_graphs, graphs, max_iters, tolerance, opt, stats, iterations_out);
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != ctx->device) return fail(GSL_EINVAL, "the context belongs to device %d, current is %d", ctx->device, cur);
+  return batched_graphs(ctx->s, ctx->stream, num_graphs, graphs, max_iters, tolerance, opt, stats, iterations_out);
 }
 
 int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels_in,

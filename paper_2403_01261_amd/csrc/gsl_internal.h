@@ -160,6 +160,34 @@ hipError_t launch_graph_count(const SweepArgs &a, const int64_t *vtx_base, int64
                               int64_t *gdn, hipStream_t s);
 hipError_t launch_graph_end(SweepCtrl *ctrl, const int64_t *gdn, const int64_t *glimit, int32_t *giters,
                             uint8_t *gdone, int64_t graphs, hipStream_t s);
+// ---- batches (batch.hip) ----
+// One graph of a batch given as its own arrays; the same layout as gsl_graph
+// in the public header.
+struct GraphDesc {
+  const int64_t *offsets;
+  const int32_t *cols;
+  const uint32_t *weights;
+  int32_t *labels_out;
+  int64_t n;
+};
+// Sets *bad when vtx_base / edge_base ([G + 1] each) do not start at 0, end
+// at N / nnz and stay non-decreasing.
+hipError_t launch_check_bases(const int64_t *vtx_base, const int64_t *edge_base, int64_t G, int64_t N,
+                              int64_t nnz, unsigned long long *bad, hipStream_t s);
+// out[e] = cols[e] + vtx_base[graph of entry e].
+hipError_t launch_globalize_cols(const int32_t *cols, const int64_t *edge_base, const int64_t *vtx_base,
+                                 int64_t G, int64_t nnz, int32_t *out, hipStream_t s);
+// cnt[g] = offsets[n] - offsets[0] of graph g.
+hipError_t launch_graph_entries(const GraphDesc *d, int64_t G, int64_t *cnt, hipStream_t s);
+// Separate graphs -> one global CSR (off [N + 1], cols [nnz], w [nnz] or NULL).
+hipError_t launch_gather(const GraphDesc *d, const int64_t *vtx_base, const int64_t *edge_base, int64_t G,
+                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, hipStream_t s);
+// lab[v] -= vtx_base[graph of v].
+hipError_t launch_localize(int32_t *lab, const int64_t *vtx_base, int64_t G, int64_t N, hipStream_t s);
+// d[g].labels_out[i] = lab[vtx_base[g] + i].
+hipError_t launch_scatter_labels(const GraphDesc *d, const int32_t *lab, const int64_t *vtx_base, int64_t G,
+                                 int64_t N, hipStream_t s);
+
 hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
