@@ -5,15 +5,26 @@
 A step is one full gsl_lpa call (degree plan, synchronous sweeps with pruning
 until dN/N <= 0.05 or 20 sweeps, split) on a graph already resident in HBM.
 value = |E| / time per step, |E| = directed CSR entries (every undirected edge
-twice, as the paper counts edges after adding reverse edges).
+twice, as the paper counts edges after adding reverse edges).  The timed steps
+run the production path (the sweep loop as one captured graph, no per-launch
+events).
 
 Extra objects on the JSON line:
   roofline      the dominant sweep kernel: algorithmic bytes per launch over
-                its average launch time (HIP events on the library's stream,
-                taken over the timed steps) against the 8 TB/s HBM peak;
-                traffic = measured HBM bytes per launch from rocprofv3 counters
-                (profiles/traffic.json), null when absent or stale.
+                its average launch time, from HIP events recorded around every
+                launch on the library's stream in a second pass of the same
+                number of steps right after the timed ones (same kernels and
+                launch shapes; events inside the timed steps would add gaps
+                to them), against the 8 TB/s HBM peak; traffic = measured HBM
+                bytes per launch from rocprofv3 counters (profiles/traffic.json),
+                null when absent or stale.
   cpu_baseline  the CPU oracle (single thread, untuned) timed on this host.
+
+--workload 5 measures the batch of 4,096 planted graphs instead: graphs/s of
+the plain per-graph loop (one gsl_lpa call per graph), of one gsl_lpa_batched
+call, and of the continuous-batching server against a plain one-graph-per-call
+server on the same Poisson stream (2,000 requests/s), with p50/p99 latency;
+every path's labels are checked to be identical.
 """
 from __future__ import annotations
 
@@ -37,6 +48,8 @@ WORKLOAD_TEXT = {
        "neighbours, unit weights",
     4: "web-scale R-MAT scale 26 (67,108,864 vertices), edge factor 32, a/b/c/d "
        "0.57/0.19/0.19/0.05, symmetrised, unit weights",
+    5: "batch of 4,096 planted-partition graphs, N log-uniform in [200, 200,000], 5-500 blocks, "
+       "mean degree U[8, 32] with 2 inter-block, unit weights",
 }
 # Kernel launched for each degree tier (as rocprofv3 names it, template
 # arguments in order).
@@ -186,13 +199,158 @@ def cpu_baseline(g, max_iters, tol):
             "iterations": int(r.iterations)}, r
 
 
+def roofline_from_stats(stats, weighted, steps, wname):
+    """Dominant sweep kernel over a list of timing-mode stats dicts."""
+    ms_tier = [sum(st["tiers"][t]["ms"] for st in stats) for t in range(NUM_TIERS)]
+    dom = max(range(1, NUM_TIERS), key=lambda t: ms_tier[t])
+    agg = {key: sum(st["tiers"][dom][key] for st in stats)
+           for key in ("vertices", "launches", "processed", "edges", "changed", "marked",
+                       "sparse_launches")}
+    agg["vertices"] = stats[0]["tiers"][dom]["vertices"]
+    launches = agg["launches"]
+    bytes_total = tier_bytes(agg, weighted)
+    avg_ms = ms_tier[dom] / max(launches, 1)
+    achieved = bytes_total / max(launches, 1) / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
+    kernel = TIER_KERNEL[dom]
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel),
+            "kernel": kernel, "tier": dom, "launches_per_step": launches // max(steps, 1),
+            "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": bytes_total // max(launches, 1)}
+
+
+def bench_batched(args):
+    """Workload 5: plain per-graph loop vs one batched call vs the served
+    stream, all on graphs resident in HBM, with identical labels."""
+    import numpy as np
+    import torch
+
+    import paper_2403_01261_amd as gsl
+    from graphgen import workloads
+    from paper_2403_01261_amd.serve import (GpuExecutor, PlainExecutor, Request, Server, poisson_arrivals,
+                                            summarize)
+
+    gsl.load()
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    b = workloads.make(5, small=args.small)
+    G, N, nnz = b.num_graphs, b.n, b.nnz
+    log("generated batch: %d graphs, N=%d, nnz=%d in %.1fs" % (G, N, nnz, time.time() - t0))
+    mi, tol = workloads.MAX_ITERS, workloads.TOLERANCE
+    vb, eb = b.vtx_base, b.edge_base
+    off = torch.from_numpy(b.offsets).to(dev)
+    cols = torch.from_numpy(b.cols).to(dev)
+    vb_d = torch.from_numpy(vb).to(dev)
+    eb_d = torch.from_numpy(eb).to(dev)
+    # per-graph CSR with local offsets (the plain path's input) on the device
+    loc_off = [torch.from_numpy(b.offsets[vb[k]:vb[k + 1] + 1] - eb[k]).to(dev) for k in range(G)]
+    loc_cols = [cols[eb[k]:eb[k + 1]] for k in range(G)]
+    out_plain = torch.empty(N, dtype=torch.int32, device=dev)
+    out_batch = torch.empty(N, dtype=torch.int32, device=dev)
+    views = [out_plain[vb[k]:vb[k + 1]] for k in range(G)]
+    torch.cuda.synchronize()
+    log("resident on the device")
+
+    def plain_loop(count):
+        for k in range(count):
+            gsl.gsl_lpa_ex(loc_off[k], loc_cols[k], None, mi, tol, out=views[k])
+
+    for k in range(args.warmup):
+        gsl.gsl_lpa_batched(vb_d, eb_d, off, cols, None, mi, tol, out=out_batch)
+        plain_loop(min(G, 64))
+        log("warmup %d done" % k)
+    torch.cuda.synchronize()
+    # (a) plain: one gsl_lpa call per graph, back to back on one stream
+    ts = time.perf_counter()
+    plain_loop(G)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - ts
+    log("plain loop: %.3f s, %.1f graphs/s" % (plain_s, G / plain_s))
+    # (b) batched: one gsl_lpa_batched call per step
+    ts = time.perf_counter()
+    for k in range(args.steps):
+        gsl.gsl_lpa_batched(vb_d, eb_d, off, cols, None, mi, tol, out=out_batch)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - ts) / max(args.steps, 1)
+    log("batched: %.3f s/step, %.1f graphs/s" % (batch_s, G / batch_s))
+    _, iters_b, st_b = gsl.gsl_lpa_batched(vb_d, eb_d, off, cols, None, mi, tol, out=out_batch, timing=True)
+    same_plain_batch = bool(torch.equal(out_plain, out_batch))
+    # (c) served: Poisson stream through the continuous-batching server, and
+    # the same stream through a plain one-graph-per-call server
+    times = poisson_arrivals(G, 2000.0, 240301261)
+    served = {}
+    for mode in ("batched", "plain"):
+        if mode == "batched":
+            ex = GpuExecutor(2, mi, tol)
+            reqs = [Request(rid=k, arrival=float(times[k]), n=int(vb[k + 1] - vb[k]), nnz=int(eb[k + 1] - eb[k]),
+                            payload=(off[vb[k]:vb[k + 1] + 1], cols, None)) for k in range(G)]
+            srv = Server(ex, slots=2, budget_bytes=64 << 30)
+        else:
+            ex = PlainExecutor(mi, tol)
+            reqs = [Request(rid=k, arrival=float(times[k]), n=int(vb[k + 1] - vb[k]), nnz=int(eb[k + 1] - eb[k]),
+                            payload=(loc_off[k], loc_cols[k], None)) for k in range(G)]
+            srv = Server(ex, slots=1, budget_bytes=64 << 30, max_batch_graphs=1)
+        torch.cuda.synchronize()
+        srv.serve(reqs)
+        if mode == "batched":
+            ex.close()
+        summ = summarize(reqs, srv.batches)
+        summ["identical_to_plain"] = all(r.state == "done" and torch.equal(r.labels, views[r.rid]) for r in reqs)
+        served[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+        log("served (%s): %s" % (mode, served[mode]))
+        del reqs
+    # CPU oracle on a bounded sample (graphs in order, about 15 s)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        done, edges, match = 0, 0, True
+        host = out_plain.cpu().numpy()
+        ts = time.perf_counter()
+        while done < G and time.perf_counter() - ts < 15.0:
+            sub = b.subgraph(done)
+            r = oracle.lpa(sub, mi, tol)
+            match = match and bool(np.array_equal(r.labels, host[vb[done]:vb[done + 1]]))
+            edges += sub.nnz
+            done += 1
+        dt = time.perf_counter() - ts
+        cpu = {"value": done / dt, "unit": "graphs/s", "cores": 1, "kind": "oracle",
+               "sample": "the first %d of the %d graphs (%d entries), one oracle GSL-LPA run each, "
+                         "single thread, %.1f s; host has %d CPUs" % (done, G, edges, dt, os.cpu_count()),
+               "edges_per_s": edges / dt, "labels_match_gpu": match}
+        log("oracle: %.1f graphs/s on %d graphs, labels match: %s" % (done / dt, done, match))
+    wname = workloads.NAMES[5]
+    line = {"metric": "graphs/s, batched (one gsl_lpa_batched call) vs plain per-graph gsl_lpa calls",
+            "value": G / batch_s, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1000.0 * batch_s, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "%s: %s" % (workloads.describe(5, args.small),
+                                                "small variant: 64 planted graphs, N log-uniform in "
+                                                "[200, 20,000]" if args.small else WORKLOAD_TEXT[5]),
+                       "graphs": G, "n": N, "nnz": nnz,
+                       "max_iters": mi, "tolerance": tol, "weights": "NULL (unit)"},
+            "batched": {"graphs_per_s": round(G / batch_s, 1), "edges_per_s": nnz / batch_s,
+                        "ms": round(1000.0 * batch_s, 3), "iterations_max": st_b["iterations"],
+                        "iterations_mean": round(float(iters_b.float().mean()), 2),
+                        "ms_plan": round(st_b["ms_plan"], 3), "ms_sweeps": round(st_b["ms_sweeps"], 3),
+                        "ms_split": round(st_b["ms_split"], 3)},
+            "plain": {"graphs_per_s": round(G / plain_s, 1), "edges_per_s": nnz / plain_s,
+                      "ms": round(1000.0 * plain_s, 3)},
+            "speedup_batched_vs_plain": round(plain_s / batch_s, 2),
+            "served": served, "labels_identical_plain_batched": same_plain_batch,
+            "roofline": roofline_from_stats([st_b], False, 1, wname), "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOAD_TEXT),
+                    help="1 planted-10k, 2 rmat-s22, 3 road-24m, 4 rmat-s26, 5 batched-4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--small", action="store_true", help="the small variant of the workload (quick checks)")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"),
@@ -208,6 +366,8 @@ def main(argv=None):
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
+    if args.workload == 5:
+        return bench_batched(args)
 
     import numpy as np
     import torch
@@ -224,7 +384,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         del src, dst
     t0 = time.time()
-    g = workloads.make(args.workload)
+    g = workloads.make(args.workload, small=args.small)
     log("generated %s: n=%d nnz=%d in %.1fs" % (workloads.NAMES[args.workload], g.n, g.nnz,
                                                  time.time() - t0))
     weighted = g.weights is not None
@@ -239,35 +399,23 @@ def main(argv=None):
         gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels)
         log("warmup %d done" % k)
     torch.cuda.synchronize()
-    stats = []
     t_start = time.perf_counter()
     for k in range(args.steps):
-        _, st = gsl.gsl_lpa_ex(off, cols, w, mi, tol, timing=True, out=labels)
-        stats.append(st)
+        gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1000.0 * elapsed / max(args.steps, 1)
     value = g.nnz * args.steps / elapsed
     log("timed %d steps: %.3f ms/step, %.3g edges/s" % (args.steps, ms_per_step, value))
+    stats = []
+    for k in range(args.steps):
+        _, st = gsl.gsl_lpa_ex(off, cols, w, mi, tol, timing=True, out=labels)
+        stats.append(st)
+    log("event pass: %.3f ms/step with per-launch events" % (sum(s["ms_total"] for s in stats) / len(stats)))
 
-    # Dominant sweep kernel over the timed steps.
-    ms_tier = [sum(st["tiers"][t]["ms"] for st in stats) for t in range(NUM_TIERS)]
-    dom = max(range(1, NUM_TIERS), key=lambda t: ms_tier[t])
-    agg = {key: sum(st["tiers"][dom][key] for st in stats)
-           for key in ("vertices", "launches", "processed", "edges", "changed", "marked",
-                       "sparse_launches")}
-    agg["vertices"] = stats[0]["tiers"][dom]["vertices"]
-    launches = agg["launches"]
-    bytes_total = tier_bytes(agg, weighted)
-    avg_ms = ms_tier[dom] / max(launches, 1)
-    achieved = bytes_total / max(launches, 1) / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
-    kernel = TIER_KERNEL[dom]
+    # Dominant sweep kernel over the event pass.
     wname = workloads.NAMES[args.workload]
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel),
-                "kernel": kernel, "tier": dom, "launches_per_step": launches // max(args.steps, 1),
-                "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_bytes_per_launch": bytes_total // max(launches, 1)}
+    roofline = roofline_from_stats(stats, weighted, args.steps, wname)
     # Whole sweep phase (all tier kernels + apply) for context.
     sweep_ms = sum(st["ms_sweeps"] for st in stats) / len(stats)
     sweep_bytes = sum(tier_bytes(dict(st["tiers"][t], vertices=st["tiers"][t]["vertices"]), weighted)
@@ -279,6 +427,7 @@ def main(argv=None):
               "sweep_phase_GBps": round(sweep_bytes / (sweep_ms / 1000.0) / 1e9, 1) if sweep_ms else None,
               "ms_reorder": round(sum(s["ms_reorder"] for s in stats) / len(stats), 3),
               "renumbered": last["renumbered"],
+              "ms_per_step_with_events": round(sum(s["ms_total"] for s in stats) / len(stats), 3),
               "iterations": last["iterations"], "changed": last["changed"]}
 
     cpu = None

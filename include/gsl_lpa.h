@@ -220,11 +220,32 @@ void *gsl_context_stream(gsl_context *ctx);
  * (NULL: the shared per-device scratch and the gsl_set_stream stream).  The
  * library gathers the graphs into one global CSR (offsets, cols and, if any
  * graph has weights, weights: (N + 1) * 8 + nnz * 4 (* 2) bytes of scratch)
- * and writes each graph's labels to its labels_out.  iterations_out is a
- * HOST int32[G] array (may be NULL).  Synchronous like every call.
+ * and writes each graph's labels to its labels_out.  Synchronous like every
+ * call.
+ *
+ *   iterations_out : HOST int32[G], each graph's sweep count (may be NULL)
+ *   status_out     : HOST int32[G] (may be NULL).  A graph whose offsets
+ *                    decrease or whose cols leave [0, n) is checked on the
+ *                    device while it is gathered; it gets GSL_EINVAL here,
+ *                    its labels_out is left untouched, and the other graphs
+ *                    still get their results.  With status_out == NULL such
+ *                    a graph makes the call return GSL_EINVAL instead (the
+ *                    other graphs' labels are still written).
+ * A weight overflow (GSL_EOVERFLOW) fails the whole call.
  */
 int gsl_lpa_graphs(gsl_context *ctx, int64_t num_graphs, const gsl_graph *graphs, int32_t max_iters,
-                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iterations_out);
+                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iterations_out,
+                   int32_t *status_out);
+
+/*
+ * gsl_check_graph -- checks a CSR on the device: offsets[0] == 0, offsets
+ * non-decreasing, every column in [0, n).  Returns GSL_OK or GSL_EINVAL (the
+ * message names the defect).  Symmetry is not checked.  Every other entry
+ * point assumes these properties without checking them (except
+ * gsl_lpa_graphs, above); a server that accepts graphs from elsewhere calls
+ * this first.
+ */
+int gsl_check_graph(const int64_t *offsets, const int32_t *cols, int64_t n);
 
 /*
  * gsl_convergence_limit -- host-only helper: the largest k in [0, n] with

@@ -14,7 +14,8 @@ import os
 
 import torch
 
-__all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_batched", "gsl_lpa_graphs", "Context", "gsl_split",
+__all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_batched", "gsl_lpa_graphs", "gsl_check_graph", "Context",
+           "gsl_split",
            "gsl_modularity", "gsl_convergence_limit", "gsl_set_stream", "gsl_release", "gsl_version",
            "GslError", "LIB_PATH", "load"]
 
@@ -94,7 +95,8 @@ def load(path: str = None):
     lib.gsl_context_stream.restype = _VP
     lib.gsl_lpa_graphs.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_Graph), ctypes.c_int32,
                                    ctypes.c_double, ctypes.POINTER(_Options), ctypes.POINTER(_Stats),
-                                   ctypes.POINTER(ctypes.c_int32)]
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.gsl_check_graph.argtypes = [_VP, _VP, ctypes.c_int64]
     lib.gsl_split.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP]
     lib.gsl_modularity.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]
     lib.gsl_convergence_limit.argtypes = [ctypes.c_int64, ctypes.c_double]
@@ -105,7 +107,7 @@ def load(path: str = None):
     lib.gsl_release.restype = None
     for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream,
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
-              lib.gsl_lpa_graphs):
+              lib.gsl_lpa_graphs, lib.gsl_check_graph):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -171,20 +173,7 @@ def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=
     st = _Stats()
     _check(lib.gsl_lpa_ex(po, pc, pw, n, int(max_iters), float(tolerance), ctypes.byref(opt),
                           ctypes.byref(st), pl))
-    it = st.iterations
-    k = min(it, STATS_MAX_ITERS)
-    stats = {"iterations": it, "changed": list(st.changed[:k]), "processed": list(st.processed[:k]),
-             "edges": list(st.edges[:k]), "marked": list(st.marked[:k]), "nnz": st.nnz,
-             "max_degree": st.max_degree, "ms_plan": st.ms_plan, "ms_sweeps": st.ms_sweeps,
-             "ms_split": st.ms_split, "ms_total": st.ms_total, "ms_sweep": list(st.ms_sweep[:k]),
-             "renumbered": bool(st.renumbered), "ms_reorder": st.ms_reorder,
-             "ms_hub_finish": st.ms_hub_finish,
-             "tiers": [{"vertices": st.tier_vertices[t], "launches": st.tier_launches[t],
-                        "processed": st.tier_processed[t], "edges": st.tier_edges[t],
-                        "changed": st.tier_changed[t], "marked": st.tier_marked[t],
-                        "sparse_launches": st.tier_sparse[t], "ms": st.ms_tier[t]}
-                       for t in range(STATS_TIERS)]}
-    return out, stats
+    return out, _stats_dict(st)
 
 
 def _stats_dict(st):
@@ -193,7 +182,14 @@ def _stats_dict(st):
     return {"iterations": it, "changed": list(st.changed[:k]), "processed": list(st.processed[:k]),
             "edges": list(st.edges[:k]), "marked": list(st.marked[:k]), "nnz": st.nnz,
             "max_degree": st.max_degree, "ms_plan": st.ms_plan, "ms_sweeps": st.ms_sweeps,
-            "ms_split": st.ms_split, "ms_total": st.ms_total, "ms_sweep": list(st.ms_sweep[:k])}
+            "ms_split": st.ms_split, "ms_total": st.ms_total, "ms_sweep": list(st.ms_sweep[:k]),
+            "renumbered": bool(st.renumbered), "ms_reorder": st.ms_reorder,
+            "ms_hub_finish": st.ms_hub_finish,
+            "tiers": [{"vertices": st.tier_vertices[t], "launches": st.tier_launches[t],
+                       "processed": st.tier_processed[t], "edges": st.tier_edges[t],
+                       "changed": st.tier_changed[t], "marked": st.tier_marked[t],
+                       "sparse_launches": st.tier_sparse[t], "ms": st.ms_tier[t]}
+                      for t in range(STATS_TIERS)]}
 
 
 def gsl_lpa_batched(vtx_base, edge_base, offsets, cols, weights=None, max_iters=20, tolerance=0.05,
@@ -242,25 +238,39 @@ def _graph_table(graphs):
     return tab, outs
 
 
-def gsl_lpa_graphs(graphs, max_iters=20, tolerance=0.05, prune=True, split=True, ctx=None):
+def gsl_lpa_graphs(graphs, max_iters=20, tolerance=0.05, prune=True, split=True, ctx=None,
+                   return_status=False):
     """A batch of separate graphs: graphs is a list of (offsets, cols[,
     weights[, out]]) tensors.  Returns (list of labels, list of sweep counts,
-    stats).  ctx: a Context (its own scratch and stream) or None."""
+    stats), plus the list of per-graph statuses if return_status (a malformed
+    graph then gets GSL_EINVAL there instead of failing the call).  ctx: a
+    Context (its own scratch and stream) or None."""
     if ctx is not None:
-        return ctx.lpa_graphs(graphs, max_iters, tolerance, prune, split)
+        return ctx.lpa_graphs(graphs, max_iters, tolerance, prune, split, return_status)
     lib = _bind_stream()
-    return _run_graphs(lib, None, graphs, max_iters, tolerance, prune, split)
+    return _run_graphs(lib, None, graphs, max_iters, tolerance, prune, split, return_status)
 
 
-def _run_graphs(lib, handle, graphs, max_iters, tolerance, prune, split):
+def _run_graphs(lib, handle, graphs, max_iters, tolerance, prune, split, return_status=False):
     tab, outs = _graph_table(graphs)
     G = len(graphs)
     iters = (ctypes.c_int32 * max(G, 1))()
+    status = (ctypes.c_int32 * max(G, 1))() if return_status else None
     opt = _Options(int(bool(prune)), int(bool(split)), 0, 2)
     st = _Stats()
     _check(lib.gsl_lpa_graphs(handle, G, tab, int(max_iters), float(tolerance), ctypes.byref(opt),
-                              ctypes.byref(st), iters))
+                              ctypes.byref(st), iters, status))
+    if return_status:
+        return outs, list(iters[:G]), _stats_dict(st), list(status[:G])
     return outs, list(iters[:G]), _stats_dict(st)
+
+
+def gsl_check_graph(offsets, cols) -> None:
+    """Raises GslError(GSL_EINVAL) unless offsets start at 0, never decrease
+    and every column is in [0, n)."""
+    lib = _bind_stream()
+    po, pc, _, n = _graph_args(offsets, cols, None)
+    _check(lib.gsl_check_graph(po, pc, n))
 
 
 class Context:
@@ -275,12 +285,12 @@ class Context:
         self._h = h
         self.stream = torch.cuda.ExternalStream(self._lib.gsl_context_stream(h))
 
-    def lpa_graphs(self, graphs, max_iters=20, tolerance=0.05, prune=True, split=True):
+    def lpa_graphs(self, graphs, max_iters=20, tolerance=0.05, prune=True, split=True, return_status=False):
         if self._h is None:
             raise RuntimeError("context closed")
         # inputs written on torch's current stream must be ready first
         self.stream.wait_stream(torch.cuda.current_stream())
-        return _run_graphs(self._lib, self._h, graphs, max_iters, tolerance, prune, split)
+        return _run_graphs(self._lib, self._h, graphs, max_iters, tolerance, prune, split, return_status)
 
     def close(self):
         if self._h is not None:

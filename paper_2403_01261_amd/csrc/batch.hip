@@ -61,12 +61,17 @@ __global__ __launch_bounds__(kBlock) void globalize_cols(const int32_t *__restri
   }
 }
 
-// Separate graphs: entry counts offsets[n] - offsets[0] (thread per graph).
-__global__ void graph_entries(const GraphDesc *__restrict__ d, int64_t G, int64_t *__restrict__ cnt) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  const GraphDesc x = d[g];
-  cnt[g] = x.n > 0 ? x.offsets[x.n] - x.offsets[0] : 0;
+// Separate graphs: entry counts offsets[n] - offsets[0], or -1 when the
+// offsets decrease somewhere (block per graph).
+__global__ __launch_bounds__(kBlock) void graph_entries(const GraphDesc *__restrict__ d, int64_t G,
+                                                        int64_t *__restrict__ cnt) {
+  for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
+    const GraphDesc x = d[g];
+    int bad = 0;
+    for (int64_t i = threadIdx.x; i < x.n; i += kBlock) bad |= x.offsets[i] > x.offsets[i + 1] ? 1 : 0;
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) cnt[g] = bad ? -1 : (x.n > 0 ? x.offsets[x.n] - x.offsets[0] : 0);
+  }
 }
 
 // Separate graphs -> one global CSR: offsets shifted to the graph's entry
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void gather_entries(const GraphDesc *__rest
                                                          const int64_t *__restrict__ vtx_base,
                                                          const int64_t *__restrict__ edge_base, int64_t G,
                                                          int64_t nnz, int32_t *__restrict__ cols,
-                                                         uint32_t *__restrict__ w) {
+                                                         uint32_t *__restrict__ w, uint32_t *__restrict__ bad) {
   for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < nnz; t0 += (int64_t)gridDim.x * kTile) {
     int64_t g = tile_graph(edge_base, G, t0);
 #pragma unroll 4
@@ -116,7 +121,13 @@ __global__ __launch_bounds__(kBlock) void gather_entries(const GraphDesc *__rest
       while (edge_base[g + 1] <= e) ++g;
       const GraphDesc x = d[g];
       const int64_t src = x.offsets[0] + (e - edge_base[g]);
-      cols[e] = x.cols[src] + (int32_t)vtx_base[g];
+      int32_t c = x.cols[src];
+      if ((uint64_t)(uint32_t)c >= (uint64_t)(vtx_base[g + 1] - vtx_base[g])) {
+        // out of range: flag the graph and keep the batch safe to run
+        atomicOr(&bad[g], 1u);
+        c = 0;
+      }
+      cols[e] = c + (int32_t)vtx_base[g];
       if (w) w[e] = x.weights ? x.weights[src] : 1u;
     }
   }
@@ -137,11 +148,12 @@ __global__ __launch_bounds__(kBlock) void localize(int32_t *__restrict__ lab, co
   }
 }
 
-// Local labels of the batch -> each graph's own output array.
+// Local labels of the batch -> each graph's own output array (graphs flagged
+// bad keep their output untouched).
 __global__ __launch_bounds__(kBlock) void scatter_labels(const GraphDesc *__restrict__ d,
                                                          const int32_t *__restrict__ lab,
-                                                         const int64_t *__restrict__ vtx_base, int64_t G,
-                                                         int64_t N) {
+                                                         const int64_t *__restrict__ vtx_base,
+                                                         const uint32_t *__restrict__ bad, int64_t G, int64_t N) {
   for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < N; t0 += (int64_t)gridDim.x * kTile) {
     int64_t g = tile_graph(vtx_base, G, t0);
 #pragma unroll 4
@@ -149,9 +161,22 @@ __global__ __launch_bounds__(kBlock) void scatter_labels(const GraphDesc *__rest
       const int64_t v = t0 + (int64_t)j * kBlock + threadIdx.x;
       if (v >= N) break;
       while (vtx_base[g + 1] <= v) ++g;
-      d[g].labels_out[v - vtx_base[g]] = lab[v];
+      if (!bad[g]) d[g].labels_out[v - vtx_base[g]] = lab[v];
     }
   }
+}
+
+// One graph: offsets[0] == 0, non-decreasing, cols in [0, n).
+__global__ __launch_bounds__(kBlock) void check_graph(const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ cols, int64_t n, int64_t nnz,
+                                                      unsigned long long *bad) {
+  int b = 0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t == 0 && off[0] != 0) b = 1;
+  for (int64_t i = t; i < n; i += stride) b |= off[i] > off[i + 1] ? 1 : 0;
+  for (int64_t e = t; e < nnz; e += stride) b |= (uint64_t)(uint32_t)cols[e] >= (uint64_t)n ? 2 : 0;
+  if (b) atomicOr(bad, (unsigned long long)b);
 }
 
 unsigned tiles(int64_t count) {
@@ -161,6 +186,15 @@ unsigned tiles(int64_t count) {
 }
 
 }  // namespace
+
+hipError_t launch_check_graph(const int64_t *off, const int32_t *cols, int64_t n, int64_t nnz,
+                              unsigned long long *bad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t work = n > nnz ? n : nnz;
+  const int64_t b = (work + 4 * kBlock - 1) / (4 * kBlock);
+  check_graph<<<(unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b)), kBlock, 0, s>>>(off, cols, n, nnz, bad);
+  return hipGetLastError();
+}
 
 hipError_t launch_globalize_cols(const int32_t *cols, const int64_t *edge_base, const int64_t *vtx_base,
                                  int64_t G, int64_t nnz, int32_t *out, hipStream_t s) {
@@ -177,15 +211,16 @@ hipError_t launch_check_bases(const int64_t *vtx_base, const int64_t *edge_base,
 
 hipError_t launch_graph_entries(const GraphDesc *d, int64_t G, int64_t *cnt, hipStream_t s) {
   if (G <= 0) return hipSuccess;
-  graph_entries<<<(unsigned)((G + 255) / 256), 256, 0, s>>>(d, G, cnt);
+  graph_entries<<<(unsigned)(G < 4096 ? G : 4096), kBlock, 0, s>>>(d, G, cnt);
   return hipGetLastError();
 }
 
 hipError_t launch_gather(const GraphDesc *d, const int64_t *vtx_base, const int64_t *edge_base, int64_t G,
-                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, hipStream_t s) {
+                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, uint32_t *bad,
+                         hipStream_t s) {
   if (G <= 0) return hipSuccess;
   gather_offsets<<<tiles(N + 1), kBlock, 0, s>>>(d, vtx_base, edge_base, G, N, off);
-  if (nnz > 0) gather_entries<<<tiles(nnz), kBlock, 0, s>>>(d, vtx_base, edge_base, G, nnz, cols, w);
+  if (nnz > 0) gather_entries<<<tiles(nnz), kBlock, 0, s>>>(d, vtx_base, edge_base, G, nnz, cols, w, bad);
   return hipGetLastError();
 }
 
@@ -195,10 +230,10 @@ hipError_t launch_localize(int32_t *lab, const int64_t *vtx_base, int64_t G, int
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_labels(const GraphDesc *d, const int32_t *lab, const int64_t *vtx_base, int64_t G,
-                                 int64_t N, hipStream_t s) {
+hipError_t launch_scatter_labels(const GraphDesc *d, const int32_t *lab, const int64_t *vtx_base,
+                                 const uint32_t *bad, int64_t G, int64_t N, hipStream_t s) {
   if (N <= 0 || G <= 0) return hipSuccess;
-  scatter_labels<<<tiles(N), kBlock, 0, s>>>(d, lab, vtx_base, G, N);
+  scatter_labels<<<tiles(N), kBlock, 0, s>>>(d, lab, vtx_base, bad, G, N);
   return hipGetLastError();
 }
 

@@ -92,6 +92,7 @@ struct Scratch {
   int64_t *gvb = nullptr, *geb = nullptr, *gcnt = nullptr;
   gsl::GraphDesc *gdesc = nullptr;
   unsigned long long *gbad = nullptr;
+  uint32_t *gflag = nullptr;  // per-graph: entry outside the graph's range
   int32_t *glab = nullptr;
   int64_t *goff = nullptr;
   int64_t gcols_cap = -1, gw_cap = -1, goff_cap = -1, batch_glab_cap = -1;
@@ -162,6 +163,7 @@ void free_scratch(Scratch &s) {
   hipFree(s.gcnt);
   hipFree(s.gdesc);
   hipFree(s.gbad);
+  hipFree(s.gflag);
   hipFree(s.glab);
   hipFree(s.goff);
   hipFree(s.gcols);
@@ -413,6 +415,8 @@ struct Batch {
   int32_t *iters_dev;              // per-graph sweep counts out (device) or NULL
   int32_t *iters_host;             // per-graph sweep counts out (host) or NULL
   const gsl::GraphDesc *scatter;   // separate graphs: descriptors of the outputs, else NULL
+  const uint32_t *flags;           // separate graphs: per-graph bad-entry flags (device)
+  uint32_t *flags_host;            // copy of those flags (host) or NULL
 };
 
 // One timing record: an event pair around a launch of tier `tier` in sweep
@@ -658,7 +662,11 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if (batch) {
     HIP_TRY(gsl::launch_localize(labels_out, batch->vtx_base, batch->graphs, n, st));
     if (batch->scatter)
-      HIP_TRY(gsl::launch_scatter_labels(batch->scatter, labels_out, batch->vtx_base, batch->graphs, n, st));
+      HIP_TRY(gsl::launch_scatter_labels(batch->scatter, labels_out, batch->vtx_base, batch->flags,
+                                         batch->graphs, n, st));
+    if (batch->flags_host)
+      HIP_TRY(hipMemcpyAsync(batch->flags_host, batch->flags, (size_t)batch->graphs * sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, st));
     if (batch->iters_dev)
       HIP_TRY(hipMemcpyAsync(batch->iters_dev, s.giters, (size_t)batch->graphs * sizeof(int32_t),
                              hipMemcpyDeviceToDevice, st));
@@ -786,13 +794,15 @@ int ensure_batch(Scratch &s, int64_t N, int64_t G) {
     hipFree(s.geb);
     hipFree(s.gcnt);
     hipFree(s.gdesc);
+    hipFree(s.gflag);
     s.giters = nullptr; s.glimit = nullptr; s.gdn = nullptr; s.gdone = nullptr;
-    s.gvb = nullptr; s.geb = nullptr; s.gcnt = nullptr; s.gdesc = nullptr;
+    s.gvb = nullptr; s.geb = nullptr; s.gcnt = nullptr; s.gdesc = nullptr; s.gflag = nullptr;
     s.batch_g_cap = -1;
     if (dmalloc(&s.giters, G) != hipSuccess || dmalloc(&s.glimit, G) != hipSuccess ||
         dmalloc(&s.gdn, G) != hipSuccess || dmalloc(&s.gdone, G) != hipSuccess ||
         dmalloc(&s.gvb, G + 1) != hipSuccess || dmalloc(&s.geb, G + 1) != hipSuccess ||
-        dmalloc(&s.gcnt, G) != hipSuccess || dmalloc(&s.gdesc, G) != hipSuccess) {
+        dmalloc(&s.gcnt, G) != hipSuccess || dmalloc(&s.gdesc, G) != hipSuccess ||
+        dmalloc(&s.gflag, G) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSL_ENOMEM, "batch allocation (%lld graphs) failed", (long long)G);
     }
@@ -859,62 +869,99 @@ int batched_concat(Scratch &s, hipStream_t st, int64_t G, const int64_t *vtx_bas
   gsl_options o = {1, 1, 0, 0};
   if (opt) o = *opt;
   o.layout = 2;
-  const Batch b{G, vtx_base, iters_out, nullptr, nullptr};
+  const Batch b{G, vtx_base, iters_out, nullptr, nullptr, nullptr, nullptr};
   return lpa_impl(s, st, offsets, s.gcols, weights, N, max_iters, tolerance, &o, stats, labels_out, &b);
 }
 
-// Batch of separate graphs (host array of descriptors).
+// Batch of separate graphs (host array of descriptors).  A graph whose
+// offsets decrease or whose entries leave [0, n) gets status GSL_EINVAL and
+// keeps its output untouched; the others run as usual.
 int batched_graphs(Scratch &s, hipStream_t st, int64_t G, const gsl_graph *graphs, int32_t max_iters,
-                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iters_out) {
+                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iters_out,
+                   int32_t *status_out) {
   static_assert(sizeof(gsl_graph) == sizeof(gsl::GraphDesc), "gsl_graph layout");
-  if (stats) memset(stats, 0, sizeof(*stats));
-  if (G < 0 || G >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "num_graphs out of range");
-  if (max_iters < 0) return fail(GSL_EINVAL, "max_iters must be >= 0");
-  if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
-  if (G == 0) return GSL_OK;
-  if (!graphs) return fail(GSL_EINVAL, "graphs must not be NULL");
-  std::vector<int64_t> vb((size_t)G + 1, 0);
-  for (int64_t g = 0; g < G; ++g) {
-    const gsl_graph &x = graphs[g];
-    if (x.n < 0 || x.n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "graph %lld: n out of range", (long long)g);
-    if (x.n > 0 && (!x.offsets || !x.labels_out))
-      return fail(GSL_EINVAL, "graph %lld: offsets and labels_out must not be NULL", (long long)g);
-    vb[(size_t)g + 1] = vb[(size_t)g] + x.n;
-    if (vb[(size_t)g + 1] >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "total vertex count out of range");
-  }
-  const int64_t N = vb[(size_t)G];
-  if (iters_out) memset(iters_out, 0, (size_t)G * sizeof(int32_t));
-  if (N == 0) return GSL_OK;
-  int rc = ensure_batch(s, N, G);
+  int rc = ensure_batch(s, 1, G);
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(s.gdesc, graphs, (size_t)G * sizeof(gsl_graph), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(s.gvb, vb.data(), (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
   HIP_TRY(gsl::launch_graph_entries(s.gdesc, G, s.gcnt, st));
   std::vector<int64_t> cnt((size_t)G);
   HIP_TRY(hipMemcpyAsync(cnt.data(), s.gcnt, (size_t)G * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  std::vector<int64_t> eb((size_t)G + 1, 0);
+  // Graphs with decreasing offsets are left out (no vertices in the batch).
+  std::vector<int64_t> vb((size_t)G + 1, 0), eb((size_t)G + 1, 0);
+  std::vector<int32_t> status((size_t)G, GSL_OK);
   bool weighted = false;
   for (int64_t g = 0; g < G; ++g) {
     const gsl_graph &x = graphs[g];
-    if (cnt[(size_t)g] < 0) return fail(GSL_EINVAL, "graph %lld: offsets[n] < offsets[0]", (long long)g);
-    if (cnt[(size_t)g] > 0 && !x.cols) return fail(GSL_EINVAL, "graph %lld: cols must not be NULL", (long long)g);
-    eb[(size_t)g + 1] = eb[(size_t)g] + cnt[(size_t)g];
-    weighted = weighted || (x.weights != nullptr && cnt[(size_t)g] > 0);
+    int64_t n = x.n, c = cnt[(size_t)g];
+    if (c < 0 || (c > 0 && !x.cols)) {
+      status[(size_t)g] = GSL_EINVAL;
+      n = 0;
+      c = 0;
+    }
+    vb[(size_t)g + 1] = vb[(size_t)g] + n;
+    eb[(size_t)g + 1] = eb[(size_t)g] + c;
+    weighted = weighted || (x.weights != nullptr && c > 0);
   }
-  const int64_t nnz = eb[(size_t)G];
-  HIP_TRY(hipMemcpyAsync(s.geb, eb.data(), (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  if ((rc = ensure_array(&s.goff, &s.goff_cap, N + 1, "global offsets"))) return rc;
-  if ((rc = ensure_array(&s.gcols, &s.gcols_cap, nnz, "global cols"))) return rc;
-  if (weighted && (rc = ensure_array(&s.gw, &s.gw_cap, nnz, "global weights"))) return rc;
-  if ((rc = ensure_array(&s.glab, &s.batch_glab_cap, N, "batch labels"))) return rc;
-  HIP_TRY(gsl::launch_gather(s.gdesc, s.gvb, s.geb, G, N, nnz, s.goff, s.gcols, weighted ? s.gw : nullptr, st));
-  gsl_options o = {1, 1, 0, 0};
-  if (opt) o = *opt;
-  o.layout = 2;
-  const Batch b{G, s.gvb, nullptr, iters_out, s.gdesc};
-  return lpa_impl(s, st, s.goff, s.gcols, weighted ? s.gw : nullptr, N, max_iters, tolerance, &o, stats, s.glab,
+  const int64_t N = vb[(size_t)G], nnz = eb[(size_t)G];
+  std::vector<uint32_t> flags((size_t)G, 0);
+  if (iters_out) memset(iters_out, 0, (size_t)G * sizeof(int32_t));
+  if (N > 0) {
+    if ((rc = ensure_batch(s, N, G))) return rc;
+    HIP_TRY(hipMemcpyAsync(s.gvb, vb.data(), (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s.geb, eb.data(), (size_t)(G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(s.gflag, 0, (size_t)G * sizeof(uint32_t), st));
+    if ((rc = ensure_array(&s.goff, &s.goff_cap, N + 1, "global offsets"))) return rc;
+    if ((rc = ensure_array(&s.gcols, &s.gcols_cap, nnz, "global cols"))) return rc;
+    if (weighted && (rc = ensure_array(&s.gw, &s.gw_cap, nnz, "global weights"))) return rc;
+    if ((rc = ensure_array(&s.glab, &s.batch_glab_cap, N, "batch labels"))) return rc;
+    HIP_TRY(gsl::launch_gather(s.gdesc, s.gvb, s.geb, G, N, nnz, s.goff, s.gcols, weighted ? s.gw : nullptr,
+                               s.gflag, st));
+    gsl_options o = {1, 1, 0, 0};
+    if (opt) o = *opt;
+    o.layout = 2;
+    const Batch b{G, s.gvb, nullptr, iters_out, s.gdesc, s.gflag, flags.data()};
+    rc = lpa_impl(s, st, s.goff, s.gcols, weighted ? s.gw : nullptr, N, max_iters, tolerance, &o, stats, s.glab,
                   &b);
+    if (rc) return rc;
+  }
+  bool any_bad = false;
+  for (int64_t g = 0; g < G; ++g) {
+    if (flags[(size_t)g]) status[(size_t)g] = GSL_EINVAL;
+    if (status[(size_t)g] != GSL_OK) {
+      any_bad = true;
+      if (iters_out) iters_out[g] = 0;
+    }
+  }
+  if (status_out) {
+    memcpy(status_out, status.data(), (size_t)G * sizeof(int32_t));
+    return GSL_OK;
+  }
+  return any_bad ? fail(GSL_EINVAL, "a graph of the batch has decreasing offsets or an entry outside [0, n)")
+                 : GSL_OK;
+}
+
+// One graph: offsets start at 0 and never decrease, cols in [0, n).
+int check_graph_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *cols, int64_t n) {
+  int64_t nnz = 0;
+  int64_t ends[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&ends[1], offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ends[0] != 0) return fail(GSL_EINVAL, "offsets[0] must be 0");
+  if (ends[1] < 0) return fail(GSL_EINVAL, "offsets[n] must be >= 0");
+  nnz = ends[1];
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
+  int rc = ensure_batch(s, 1, 1);
+  if (rc) return rc;
+  unsigned long long bad = 0;
+  HIP_TRY(hipMemsetAsync(s.gbad, 0, sizeof(unsigned long long), st));
+  HIP_TRY(gsl::launch_check_graph(offsets, cols, n, nnz, s.gbad, st));
+  HIP_TRY(hipMemcpyAsync(&bad, s.gbad, sizeof(bad), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (bad & 1) return fail(GSL_EINVAL, "offsets decrease");
+  if (bad & 2) return fail(GSL_EINVAL, "a column index is outside [0, n)");
+  return GSL_OK;
 }
 
 }  // namespace
@@ -957,6 +1004,17 @@ int gsl_lpa_batched_ex(int64_t num_graphs, const int64_t *vtx_base, const int64_
   if ((rc = get_scratch(&sp))) return rc;
   return batched_concat(*sp, g_stream, num_graphs, vtx_base, edge_base, offsets, cols, weights, max_iters,
                         tolerance, opt, stats, labels_out, iterations_out);
+}
+
+int gsl_check_graph(const int64_t *offsets, const int32_t *cols, int64_t n) {
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n = %lld out of range", (long long)n);
+  if (n == 0) return GSL_OK;
+  if (!offsets) return fail(GSL_EINVAL, "offsets must not be NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Scratch *sp = nullptr;
+  const int rc = get_scratch(&sp);
+  if (rc) return rc;
+  return check_graph_impl(*sp, g_stream, offsets, cols, n);
 }
 
 int gsl_context_create(gsl_context **out) {
@@ -1007,7 +1065,8 @@ int gsl_context_set_stream(gsl_context *ctx, void *hip_stream) {
 void *gsl_context_stream(gsl_context *ctx) { return ctx ? reinterpret_cast<void *>(ctx->stream) : nullptr; }
 
 int gsl_lpa_graphs(gsl_context *ctx, int64_t num_graphs, const gsl_graph *graphs, int32_t max_iters,
-                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iterations_out) {
+                   double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iterations_out,
+                   int32_t *status_out) {
   if (stats) memset(stats, 0, sizeof(*stats));
   int rc = check_batch(num_graphs, max_iters, tolerance);
   if (rc) return rc == kNoop ? GSL_OK : rc;
@@ -1023,19 +1082,22 @@ int gsl_lpa_graphs(gsl_context *ctx, int64_t num_graphs, const gsl_graph *graphs
   }
   if (total == 0) {
     if (iterations_out) memset(iterations_out, 0, (size_t)num_graphs * sizeof(int32_t));
+    if (status_out) memset(status_out, 0, (size_t)num_graphs * sizeof(int32_t));
     return GSL_OK;
   }
   if (!ctx) {
     std::lock_guard<std::mutex> lk(g_mu);
     Scratch *sp = nullptr;
     if ((rc = get_scratch(&sp))) return rc;
-    return batched_graphs(*sp, g_stream, num_graphs, graphs, max_iters, tolerance, opt, stats, iterations_out);
+    return batched_graphs(*sp, g_stream, num_graphs, graphs, max_iters, tolerance, opt, stats, iterations_out,
+                          status_out);
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
   int cur = 0;
   HIP_TRY(hipGetDevice(&cur));
   if (cur != ctx->device) return fail(GSL_EINVAL, "the context belongs to device %d, current is %d", ctx->device, cur);
-  return batched_graphs(ctx->s, ctx->stream, num_graphs, graphs, max_iters, tolerance, opt, stats, iterations_out);
+  return batched_graphs(ctx->s, ctx->stream, num_graphs, graphs, max_iters, tolerance, opt, stats, iterations_out,
+                        status_out);
 }
 
 int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels_in,

@@ -177,16 +177,22 @@ hipError_t launch_check_bases(const int64_t *vtx_base, const int64_t *edge_base,
 // out[e] = cols[e] + vtx_base[graph of entry e].
 hipError_t launch_globalize_cols(const int32_t *cols, const int64_t *edge_base, const int64_t *vtx_base,
                                  int64_t G, int64_t nnz, int32_t *out, hipStream_t s);
-// cnt[g] = offsets[n] - offsets[0] of graph g.
+// cnt[g] = offsets[n] - offsets[0] of graph g, -1 if its offsets decrease.
 hipError_t launch_graph_entries(const GraphDesc *d, int64_t G, int64_t *cnt, hipStream_t s);
 // Separate graphs -> one global CSR (off [N + 1], cols [nnz], w [nnz] or NULL).
+// An entry outside [0, n_g) sets bad[g] and is replaced by local vertex 0.
 hipError_t launch_gather(const GraphDesc *d, const int64_t *vtx_base, const int64_t *edge_base, int64_t G,
-                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, hipStream_t s);
+                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, uint32_t *bad,
+                         hipStream_t s);
+// One graph: *bad |= 1 if offsets[0] != 0 or offsets decrease, |= 2 if a
+// column is outside [0, n).
+hipError_t launch_check_graph(const int64_t *off, const int32_t *cols, int64_t n, int64_t nnz,
+                              unsigned long long *bad, hipStream_t s);
 // lab[v] -= vtx_base[graph of v].
 hipError_t launch_localize(int32_t *lab, const int64_t *vtx_base, int64_t G, int64_t N, hipStream_t s);
-// d[g].labels_out[i] = lab[vtx_base[g] + i].
-hipError_t launch_scatter_labels(const GraphDesc *d, const int32_t *lab, const int64_t *vtx_base, int64_t G,
-                                 int64_t N, hipStream_t s);
+// d[g].labels_out[i] = lab[vtx_base[g] + i] for graphs with bad[g] == 0.
+hipError_t launch_scatter_labels(const GraphDesc *d, const int32_t *lab, const int64_t *vtx_base,
+                                 const uint32_t *bad, int64_t G, int64_t N, hipStream_t s);
 
 hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);

@@ -1,0 +1,301 @@
+"""Serving loop: continuous batching of community-detection requests.
+
+A request carries one graph already resident in device memory (CSR tensors
+the client uploaded).  Requests arrive over time.  A dispatcher keeps a FIFO
+queue and a set of slots; a slot is a worker thread that owns a gsl_context
+(its own scratch and stream).  Whenever a slot is idle, the dispatcher admits
+requests from the head of the queue into one batch, as many as the HBM budget
+and the batch limits allow, and hands the batch to the slot, which runs it as
+one gsl_lpa_graphs call.  Requests that arrive meanwhile wait for the next
+idle slot, so batches of different slots overlap on the device, and a new
+request never waits for a whole earlier batch to drain unless every slot is
+busy or the budget is spent.
+
+Admission is by device-memory footprint (footprint()): the scratch the
+library allocates per vertex and per entry for a batch, plus the labels.  The
+sum over admitted, unfinished requests never exceeds the budget; a request
+whose own footprint exceeds it is rejected at once.  Errors stay with their
+request: gsl_lpa_graphs reports a malformed graph on its own (status
+GSL_EINVAL), and if a whole batch fails (for instance a weight overflow), the
+slot reruns its requests one by one so only the culprit fails.
+
+The scheduling logic (Scheduler, Server) is plain Python and takes the
+executor as a parameter, so it is tested on the CPU with a fake executor; the
+GPU executor is GpuExecutor.  PlainExecutor runs one gsl_lpa call per
+request, the baseline the batched server is compared with.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import queue
+import threading
+import time
+from typing import Any, Callable, List, Optional
+
+# Library scratch per vertex of a batch (label and flag arrays, vertex list,
+# split parents, graph ids, gathered offsets, batch labels) plus the 4-byte
+# output label, and per CSR entry (gathered global cols; weights double it).
+BYTES_PER_VERTEX = 64
+BYTES_PER_ENTRY = 4
+
+
+def footprint(n: int, nnz: int, weighted: bool = False) -> int:
+    """Device bytes a request adds to a batch while it runs."""
+    return BYTES_PER_VERTEX * (n + 1) + BYTES_PER_ENTRY * nnz * (2 if weighted else 1)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float              # seconds after the start of the stream
+    n: int
+    nnz: int
+    weighted: bool = False
+    payload: Any = None         # what the executor needs (device tensors, or a CPU graph in tests)
+    # filled in by the server
+    state: str = "new"          # new, queued, running, done, failed, rejected, cancelled
+    code: int = 0               # gsl_status of a failed request
+    error: str = ""
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    slot: int = -1
+    batch_id: int = -1
+    labels: Any = None
+    iterations: int = -1
+
+    @property
+    def bytes(self) -> int:
+        return footprint(self.n, self.nnz, self.weighted)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+class Scheduler:
+    """FIFO admission under a device-memory budget (no GPU involved)."""
+
+    def __init__(self, budget_bytes: int, max_batch_graphs: int = 1024, max_batch_bytes: Optional[int] = None):
+        if budget_bytes <= 0 or max_batch_graphs <= 0:
+            raise ValueError("budget and batch size must be positive")
+        self.budget = int(budget_bytes)
+        self.max_graphs = int(max_batch_graphs)
+        self.max_bytes = int(max_batch_bytes) if max_batch_bytes else self.budget
+        self.queue: collections.deque = collections.deque()
+        self.in_flight = 0
+        self.peak_in_flight = 0
+
+    def submit(self, req: Request) -> bool:
+        if req.bytes > min(self.budget, self.max_bytes):
+            req.state = "rejected"
+            req.code = -2  # GSL_ENOMEM: can never fit
+            req.error = "footprint %d bytes exceeds the budget" % req.bytes
+            return False
+        req.state = "queued"
+        self.queue.append(req)
+        return True
+
+    def cancel(self, rid: int) -> bool:
+        for r in self.queue:
+            if r.rid == rid:
+                self.queue.remove(r)
+                r.state = "cancelled"
+                return True
+        return False
+
+    def next_batch(self) -> List[Request]:
+        """Requests from the head of the queue that fit now (possibly none)."""
+        batch, size = [], 0
+        while self.queue and len(batch) < self.max_graphs:
+            b = self.queue[0].bytes
+            if self.in_flight + size + b > self.budget or size + b > self.max_bytes:
+                break
+            batch.append(self.queue.popleft())
+            size += b
+        self.in_flight += size
+        self.peak_in_flight = max(self.peak_in_flight, self.in_flight)
+        return batch
+
+    def release(self, batch: List[Request]) -> None:
+        self.in_flight -= sum(r.bytes for r in batch)
+
+
+class Server:
+    """Continuous-batching request loop over `slots` worker threads.
+
+    executor.run(slot, batch) returns one (labels, iterations, status) per
+    request of the batch or raises; status 0 is success."""
+
+    def __init__(self, executor, slots: int = 2, budget_bytes: int = 32 << 30, max_batch_graphs: int = 1024,
+                 max_batch_bytes: Optional[int] = None, clock: Callable[[], float] = time.perf_counter):
+        if slots <= 0:
+            raise ValueError("slots must be positive")
+        self.executor = executor
+        self.slots = slots
+        self.sched = Scheduler(budget_bytes, max_batch_graphs, max_batch_bytes)
+        self.clock = clock
+        self.batches: List[List[Request]] = []
+
+    def _work(self, slot: int, inbox: queue.Queue, done: queue.Queue, t0: float):
+        while True:
+            batch = inbox.get()
+            if batch is None:
+                return
+            try:
+                out = self.executor.run(slot, batch)
+                t = self.clock() - t0
+                for r, (lab, it, st) in zip(batch, out):
+                    self._finish(r, lab, it, st, t)
+            except Exception as e:  # the whole batch failed: isolate the culprit
+                if len(batch) == 1:
+                    self._fail(batch[0], e, self.clock() - t0)
+                else:
+                    for r in batch:
+                        try:
+                            (lab, it, st), = self.executor.run(slot, [r])
+                            self._finish(r, lab, it, st, self.clock() - t0)
+                        except Exception as e1:
+                            self._fail(r, e1, self.clock() - t0)
+            done.put((slot, batch))
+
+    @staticmethod
+    def _finish(r: Request, lab, it, st, t):
+        r.t_done = t
+        if st == 0:
+            r.state, r.labels, r.iterations = "done", lab, it
+        else:
+            r.state, r.code, r.error = "failed", st, "graph rejected by the library"
+
+    @staticmethod
+    def _fail(r: Request, e: Exception, t):
+        r.t_done = t
+        r.state = "failed"
+        r.code = getattr(e, "code", -3)
+        r.error = str(e)
+
+    def serve(self, requests: List[Request], cancel: Optional[dict] = None) -> List[Request]:
+        """Runs the stream to completion.  `cancel` maps a time (s) to request
+        ids cancelled at that moment if still queued."""
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        pending = collections.deque(reqs)
+        cancels = sorted((cancel or {}).items())
+        inboxes = [queue.Queue() for _ in range(self.slots)]
+        done: queue.Queue = queue.Queue()
+        t0 = self.clock()
+        workers = [threading.Thread(target=self._work, args=(s, inboxes[s], done, t0), daemon=True)
+                   for s in range(self.slots)]
+        for w in workers:
+            w.start()
+        idle = list(range(self.slots))
+        busy = 0
+        try:
+            while pending or self.sched.queue or busy:
+                now = self.clock() - t0
+                while pending and pending[0].arrival <= now:
+                    self.sched.submit(pending.popleft())
+                while cancels and cancels[0][0] <= now:
+                    for rid in cancels.pop(0)[1]:
+                        self.sched.cancel(rid)
+                while idle and self.sched.queue:
+                    batch = self.sched.next_batch()
+                    if not batch:
+                        break
+                    slot = idle.pop(0)
+                    t = self.clock() - t0
+                    for r in batch:
+                        r.state, r.t_admit, r.slot, r.batch_id = "running", t, slot, len(self.batches)
+                    self.batches.append(batch)
+                    busy += 1
+                    inboxes[slot].put(batch)
+                # wait for a completion or the next arrival / cancellation
+                nxt = [pending[0].arrival] if pending else []
+                if cancels:
+                    nxt.append(cancels[0][0])
+                wait = 0.05 if not nxt else max(0.0, min(nxt) - (self.clock() - t0))
+                if busy == 0 and not nxt:
+                    # queued work that cannot be admitted with nothing in flight
+                    if self.sched.queue:
+                        raise RuntimeError("queued requests can never be admitted")
+                    break
+                try:
+                    item = done.get(timeout=min(wait, 0.002) if busy else wait)
+                except queue.Empty:
+                    continue
+                while True:
+                    slot, batch = item
+                    self.sched.release(batch)
+                    idle.append(slot)
+                    busy -= 1
+                    try:
+                        item = done.get_nowait()
+                    except queue.Empty:
+                        break
+        finally:
+            for ib in inboxes:
+                ib.put(None)
+            for w in workers:
+                w.join()
+        return reqs
+
+
+def summarize(reqs: List[Request], batches: Optional[List[List[Request]]] = None) -> dict:
+    """Latency percentiles (ms), throughput (graphs/s from the first arrival
+    to the last completion) and outcome counts."""
+    import numpy as np
+    ok = [r for r in reqs if r.state == "done"]
+    lat = np.array([r.latency for r in ok]) * 1e3 if ok else np.zeros(0)
+    span = (max(r.t_done for r in ok) - min(r.arrival for r in reqs)) if ok else float("nan")
+    out = {"requests": len(reqs), "done": len(ok),
+           "failed": sum(r.state == "failed" for r in reqs),
+           "rejected": sum(r.state == "rejected" for r in reqs),
+           "cancelled": sum(r.state == "cancelled" for r in reqs),
+           "graphs_per_s": len(ok) / span if ok and span > 0 else float("nan"),
+           "p50_ms": float(np.percentile(lat, 50)) if ok else float("nan"),
+           "p99_ms": float(np.percentile(lat, 99)) if ok else float("nan"),
+           "mean_ms": float(lat.mean()) if ok else float("nan")}
+    if batches is not None:
+        out["batches"] = len(batches)
+        out["mean_batch"] = (sum(len(b) for b in batches) / len(batches)) if batches else 0.0
+    return out
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int) -> List[float]:
+    """Arrival times (s) of a Poisson stream: exponential gaps of mean 1/rate."""
+    import numpy as np
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate_per_s, size=count)
+    return list(np.cumsum(gaps) - gaps[0])
+
+
+class GpuExecutor:
+    """Runs a batch as one gsl_lpa_graphs call on the slot's own context."""
+
+    def __init__(self, slots: int, max_iters: int = 20, tolerance: float = 0.05):
+        from . import Context
+        self.ctx = [Context() for _ in range(slots)]
+        self.max_iters, self.tol = max_iters, tolerance
+
+    def run(self, slot: int, batch: List[Request]):
+        outs, iters, _, status = self.ctx[slot].lpa_graphs([r.payload for r in batch], self.max_iters, self.tol,
+                                                           return_status=True)
+        return list(zip(outs, iters, status))
+
+    def close(self):
+        for c in self.ctx:
+            c.close()
+
+
+class PlainExecutor:
+    """One gsl_lpa call per request (payload: local-offset CSR tensors)."""
+
+    def __init__(self, max_iters: int = 20, tolerance: float = 0.05):
+        self.max_iters, self.tol = max_iters, tolerance
+
+    def run(self, slot: int, batch: List[Request]):
+        from . import gsl_lpa_ex
+        res = []
+        for r in batch:
+            off, cols, w = r.payload[:3]
+            lab, st = gsl_lpa_ex(off, cols, w, self.max_iters, self.tol)
+            res.append((lab, st["iterations"], 0))
+        return res

@@ -74,6 +74,9 @@ def run_batch(idx: int) -> dict:
     G = g.num_graphs
     print("workload %d: %d graphs, n=%d nnz=%d" % (idx, G, g.n, g.nnz), flush=True)
     t0 = time.time()
+    # Workers are forked after the batch exists, so they share its arrays
+    # instead of each generating a copy.
+    _BATCH[idx] = g
     with ProcessPoolExecutor(max_workers=os.cpu_count()) as ex:
         res = list(ex.map(_batch_one, [(idx, b) for b in range(G)], chunksize=8))
     h = xxhash.xxh3_128()

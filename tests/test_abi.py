@@ -65,24 +65,27 @@ def test_batched_argument_errors_without_device_work():
     tab = (gsl._Graph * G)()
     iters = (ctypes.c_int32 * G)(7, 7, 7)
     # only empty graphs: nothing to do, every sweep count is 0
-    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters) == gsl.GSL_OK
+    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters, None) == gsl.GSL_OK
     assert list(iters) == [0, 0, 0]
     tab[1].n = -2
-    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters) == gsl.GSL_EINVAL
+    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters, None) == gsl.GSL_EINVAL
     assert b"n out of range" in lib.gsl_last_error()
     tab[1].n = 4  # offsets / labels_out missing
-    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters) == gsl.GSL_EINVAL
+    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters, None) == gsl.GSL_EINVAL
     tab[1].n = 1 << 30
     tab[2].n = 1 << 30
     tab[1].offsets = tab[2].offsets = 8
     tab[1].labels_out = tab[2].labels_out = 8
-    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters) == gsl.GSL_EINVAL
+    assert lib.gsl_lpa_graphs(None, G, tab, 20, 0.05, None, None, iters, None) == gsl.GSL_EINVAL
     assert b"total vertex count" in lib.gsl_last_error()
-    assert lib.gsl_lpa_graphs(None, 1, None, 20, 0.05, None, None, None) == gsl.GSL_EINVAL
+    assert lib.gsl_lpa_graphs(None, 1, None, 20, 0.05, None, None, None, None) == gsl.GSL_EINVAL
     assert lib.gsl_context_create(None) == gsl.GSL_EINVAL
     assert lib.gsl_context_set_stream(None, None) == gsl.GSL_EINVAL
     lib.gsl_context_destroy(None)
     assert ctypes.sizeof(gsl._Graph) == 40
+    assert lib.gsl_check_graph(None, None, -1) == gsl.GSL_EINVAL
+    assert lib.gsl_check_graph(None, None, 0) == gsl.GSL_OK
+    assert lib.gsl_check_graph(None, None, 4) == gsl.GSL_EINVAL
 
 
 def _literal_limit(n, tol):

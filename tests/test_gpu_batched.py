@@ -205,3 +205,40 @@ def test_overflow_in_one_graph_is_reported(gsl):
     with pytest.raises(gsl.GslError) as e:
         run_graphs(gsl, graphs)
     assert e.value.code == gsl.GSL_EOVERFLOW
+
+
+def test_malformed_graph_fails_alone(gsl):
+    graphs = mixed_graphs(5)
+    exp = expected(graphs, 20, 0.05)
+    dev = [list(to_device(g)) for g in graphs]
+    big = max(range(len(graphs)), key=lambda k: graphs[k].nnz)
+    # graph `big`: one column out of range; the next non-empty graph: decreasing offsets
+    bad_cols = dev[big][1].clone()
+    bad_cols[bad_cols.numel() // 2] = graphs[big].n + 5
+    dev[big][1] = bad_cols
+    other = next(k for k in range(len(graphs)) if k != big and graphs[k].n >= 3 and graphs[k].nnz > 0)
+    bad_off = dev[other][0].clone()
+    a, b = int(bad_off[1]), int(bad_off[2])
+    bad_off[1], bad_off[2] = b + 1, a  # offsets[1] > offsets[2]
+    dev[other][0] = bad_off
+    sentinel = [torch.full((g.n,), -7, dtype=torch.int32, device="cuda") for g in graphs]
+    outs, iters, _, status = gsl.gsl_lpa_graphs([(o, c, w, s) for (o, c, w), s in zip(dev, sentinel)],
+                                                return_status=True)
+    for k, g in enumerate(graphs):
+        lab = outs[k].cpu().numpy()
+        if k in (big, other):
+            assert status[k] == gsl.GSL_EINVAL, k
+            assert (lab == -7).all(), k
+            assert iters[k] == 0
+        else:
+            assert status[k] == gsl.GSL_OK, k
+            assert iters[k] == exp[k].iterations
+            np.testing.assert_array_equal(lab, exp[k].labels)
+    with pytest.raises(gsl.GslError) as e:
+        gsl.gsl_lpa_graphs([(o, c, w) for o, c, w in dev])
+    assert e.value.code == gsl.GSL_EINVAL
+    with pytest.raises(gsl.GslError):
+        gsl.gsl_check_graph(dev[big][0], dev[big][1])
+    with pytest.raises(gsl.GslError):
+        gsl.gsl_check_graph(dev[other][0], dev[other][1])
+    gsl.gsl_check_graph(*to_device(graphs[big])[:2])

@@ -1,0 +1,70 @@
+"""The served path on the GPU: a Poisson stream of requests through the
+continuous-batching server (two slots, each with its own context) gives every
+request exactly the labels and sweep count it gets alone (gsl_lpa) and from
+the oracle; a malformed graph and a weight overflow fail alone."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+from graphgen import workloads  # noqa: E402
+from tests.gpu_util import say, to_device  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_01261_amd as m
+    m.load()
+    return m
+
+
+def test_served_results_equal_alone_and_oracle(gsl):
+    from paper_2403_01261_amd.serve import GpuExecutor, Request, Server, poisson_arrivals, summarize
+    b = workloads.make(5, small=True)
+    graphs = [b.subgraph(k) for k in range(b.num_graphs)]
+    # edge cases mixed in: an isolated-only graph, a graph with a column out of
+    # range, and one whose weights overflow 32 bits
+    graphs.insert(5, graphgen.from_entries(4, [], []))
+    bad = graphgen.from_undirected(6, [(0, 1), (1, 2)])
+    graphs.insert(9, bad)
+    ovf = graphgen.from_undirected(3, [(0, 1), (0, 2)], [1 << 31, 1 << 31])
+    graphs.insert(13, ovf)
+    times = poisson_arrivals(len(graphs), 2000.0, 7)
+    reqs = []
+    for k, (g, t) in enumerate(zip(graphs, times)):
+        off, cols, w = to_device(g)
+        if k == 9:
+            cols = cols.clone()
+            cols[0] = 17  # outside [0, 6)
+        reqs.append(Request(rid=k, arrival=float(t), n=g.n, nnz=g.nnz, weighted=w is not None,
+                            payload=(off, cols, w)))
+    torch.cuda.synchronize()
+    ex = GpuExecutor(2)
+    srv = Server(ex, slots=2, budget_bytes=1 << 30)
+    try:
+        srv.serve(reqs)
+    finally:
+        ex.close()
+    s = summarize(reqs, srv.batches)
+    say("served:", s)
+    assert reqs[9].state == "failed" and reqs[9].code == gsl.GSL_EINVAL
+    assert reqs[13].state == "failed" and reqs[13].code == gsl.GSL_EOVERFLOW
+    for k, (g, r) in enumerate(zip(graphs, reqs)):
+        if k in (9, 13):
+            continue
+        assert r.state == "done", (k, r.state, r.error)
+        exp = oracle.lpa(g)
+        lab = r.labels.cpu().numpy()
+        np.testing.assert_array_equal(lab, exp.labels, err_msg="request %d" % k)
+        assert r.iterations == exp.iterations
+        off, cols, w = r.payload
+        alone, st = gsl.gsl_lpa_ex(off, cols, w)
+        np.testing.assert_array_equal(lab, alone.cpu().numpy())
+        assert st["iterations"] == r.iterations
+    assert s["done"] == len(graphs) - 2
