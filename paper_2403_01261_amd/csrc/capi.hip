@@ -505,7 +505,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
       mk_arr, st));
   if (batch)
     HIP_TRY(gsl::launch_batch_init(batch->vtx_base, batch->graphs, max_iters, tolerance, s.gid, s.glimit,
-                                   s.giters, s.gdone, st));
+                                   s.giters, s.gdone, s.gdn, st));
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[1], st));
 
   gsl::SweepArgs a;
@@ -579,8 +579,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     }
     HIP_TRY(gsl::launch_reduce_counts(s.tier_part, grids, s.ctr->tier_stats, s.ctrl, dn_arr, pr_arr, ed_arr,
                                       a.overflow, cur));
-    if (batch) HIP_TRY(gsl::launch_graph_count(a, batch->vtx_base, batch->graphs, s.gdn, cur));
-    HIP_TRY(gsl::launch_apply(a, C, n_sweep, cur));
+    HIP_TRY(gsl::launch_apply(a, C, n_sweep, batch ? s.gdn : nullptr, cur));
     if (batch)
       HIP_TRY(gsl::launch_graph_end(s.ctrl, s.gdn, s.glimit, s.giters, s.gdone, batch->graphs, cur));
     HIP_TRY(gsl::launch_sweep_end(s.ctrl, dn_arr, mk_arr, a.overflow, cur));

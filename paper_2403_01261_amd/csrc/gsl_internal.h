@@ -143,8 +143,9 @@ hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L
                             unsigned long long *rowsum, int64_t k0, int64_t k1, int max_parts,
                             int stage, hipStream_t s);
 // Copies changed labels into C and clears the consumed flags (this sweep's
-// active flags when it was sparse).
-hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, hipStream_t s);
+// active flags when it was sparse).  Batches (gdn != NULL): also adds each
+// graph's changes to gdn[graph].
+hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, int64_t *gdn, hipStream_t s);
 // Advances the loop state after a sweep.
 hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsigned long long *marked_sweeps,
                             const unsigned long long *overflow, hipStream_t s);
@@ -154,11 +155,10 @@ hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_fla
                             unsigned long long *marked_sweeps, hipStream_t s);
 // Batches: graph id per vertex, per-graph limits, sweep counts and stop flags.
 hipError_t launch_batch_init(const int64_t *vtx_base, int64_t graphs, int32_t max_iters, double tol,
-                             int32_t *gid, int64_t *glimit, int32_t *giters, uint8_t *gdone, hipStream_t s);
-// Batches: per-graph change counts and stop decisions (before sweep_end).
-hipError_t launch_graph_count(const SweepArgs &a, const int64_t *vtx_base, int64_t graphs,
-                              int64_t *gdn, hipStream_t s);
-hipError_t launch_graph_end(SweepCtrl *ctrl, const int64_t *gdn, const int64_t *glimit, int32_t *giters,
+                             int32_t *gid, int64_t *glimit, int32_t *giters, uint8_t *gdone, int64_t *gdn,
+                             hipStream_t s);
+// Batches: per-graph stop decisions after apply (before sweep_end); clears gdn.
+hipError_t launch_graph_end(SweepCtrl *ctrl, int64_t *gdn, const int64_t *glimit, int32_t *giters,
                             uint8_t *gdone, int64_t graphs, hipStream_t s);
 // ---- batches (batch.hip) ----
 // One graph of a batch given as its own arrays; the same layout as gsl_graph

@@ -109,17 +109,24 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
 }
 
 // ---------------------------------------------------------------------------
-// Tiers 2-8: a group of G lanes per vertex -- a slice of a wavefront (G <= 64)
+// Tiers 2-7: a group of G lanes per vertex -- a slice of a wavefront (G <= 64)
 // or the whole workgroup (G == BLOCK) -- with a private LDS table of up to
 // 2^LOG2S slots.  Every lane owns at most K row entries (the tier bound is
 // G * K), loads them all before inserting, and remembers the slots it
 // claimed: after the barrier the claimers read the final sums of their own
 // slots (the argmax candidates) and clear them, so no lane scans empty slots.
-// All groups of a block move through the insert / read phases together.
+//
+// The block walks the tier in windows of `win` list entries (a multiple of
+// the groups per block, at most BLOCK): one thread per entry decides whether
+// the vertex takes part in this sweep (pruning flag, stopped graph of a
+// batch), the taken vertices are packed into LDS in list order, and the
+// groups then work through the packed vertices only.  A sparse sweep thus
+// costs one flag check per thread instead of one per group.  All groups of a
+// block move through the insert / read phases together.
 // ---------------------------------------------------------------------------
 template <int G, int LOG2S, int BLOCK, int K>
 __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *__restrict__ list,
-                                                   int64_t first, int64_t count) {
+                                                   int64_t first, int64_t count, int win) {
   static_assert(G <= 64 || G == BLOCK, "group is a wave slice or the block");
   constexpr int GPB = BLOCK / G;
   constexpr int S = 1 << LOG2S;
@@ -127,96 +134,112 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
   __shared__ unsigned long long tab[GPB * S];
   __shared__ unsigned long long red[NW];
   __shared__ unsigned long long red2[NW];
+  __shared__ int32_t q[BLOCK];
+  __shared__ int wcnt[NW];
   SweepView sv;
   if (!sweep_view(a, sv)) return;
   for (int s = threadIdx.x; s < GPB * S; s += BLOCK) tab[s] = kEmptySlot;
-  __syncthreads();
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int wid = threadIdx.x / kWave, wl = threadIdx.x % kWave;
   unsigned long long *T = tab + g * S;
   LocalCounts lc;
-  for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
-    const int64_t idx = base + g;
-    int32_t v = -1;
-    if (idx < count) {
-      v = list ? list[first + idx] : (int32_t)(first + idx);
-      if (!sweep_takes(a, sv, v)) v = -1;
+  for (int64_t w0 = (int64_t)blockIdx.x * win; w0 < count; w0 += (int64_t)gridDim.x * win) {
+    // pack the taken vertices of the window
+    int32_t u = -1;
+    if (threadIdx.x < win && w0 + threadIdx.x < count) {
+      u = list ? list[first + w0 + threadIdx.x] : (int32_t)(first + w0 + threadIdx.x);
+      if (!sweep_takes(a, sv, u)) u = -1;
     }
-    int64_t b = 0, e = 0;
-    int log2s = 1;
-    if (v >= 0) {
-      b = a.off[v];
-      e = a.off[v + 1];
-      log2s = table_log2(e - b, 1, LOG2S);
-    }
-    int32_t j[K];
-    uint32_t wt[K], lab[K];
-    int slot[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t p = b + lane + (int64_t)k * G;
-      const bool in = p < e;
-      j[k] = in ? a.cols[p] : -1;
-      wt[k] = in ? (a.w ? a.w[p] : 1u) : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) lab[k] = (j[k] >= 0 && j[k] != v) ? (uint32_t)a.C[j[k]] : kNoLabel;
-    unsigned long long rowsum = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) rowsum += wt[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k) slot[k] = lab[k] != kNoLabel ? lds_insert(T, log2s, lab[k], wt[k]) : -1;
+    const unsigned long long m = __ballot(u >= 0);
+    if (wl == 0) wcnt[wid] = __popcll(m);
     __syncthreads();
-    unsigned long long best = 0;
+    int pos = __popcll(m & ((1ull << wl) - 1ull)), total = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (slot[k] >= 0) {
-        const unsigned long long x = T[slot[k]];
-        const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
-        best = key > best ? key : best;
-        T[slot[k]] = kEmptySlot;
-      }
+    for (int w = 0; w < NW; ++w) {
+      pos += w < wid ? wcnt[w] : 0;
+      total += wcnt[w];
     }
-    if constexpr (G <= 64) {
-      best = group_max<G>(best);
-      rowsum = group_sum<G>(rowsum);
-    } else {
-      best = group_max<kWave>(best);
-      rowsum = wave_sum(rowsum);
-      if (threadIdx.x % kWave == 0) {
-        red[threadIdx.x / kWave] = best;
-        red2[threadIdx.x / kWave] = rowsum;
+    if (u >= 0) q[pos] = u;
+    __syncthreads();
+    for (int r0 = 0; r0 < total; r0 += GPB) {
+      const int32_t v = r0 + g < total ? q[r0 + g] : -1;
+      int64_t b = 0, e = 0;
+      int log2s = 1;
+      if (v >= 0) {
+        b = a.off[v];
+        e = a.off[v + 1];
+        log2s = table_log2(e - b, 1, LOG2S);
       }
+      int32_t j[K];
+      uint32_t wt[K], lab[K];
+      int slot[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int64_t p = b + lane + (int64_t)k * G;
+        const bool in = p < e;
+        j[k] = in ? a.cols[p] : -1;
+        wt[k] = in ? (a.w ? a.w[p] : 1u) : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) lab[k] = (j[k] >= 0 && j[k] != v) ? (uint32_t)a.C[j[k]] : kNoLabel;
+      unsigned long long rowsum = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) rowsum += wt[k];
+#pragma unroll
+      for (int k = 0; k < K; ++k) slot[k] = lab[k] != kNoLabel ? lds_insert(T, log2s, lab[k], wt[k]) : -1;
       __syncthreads();
-      best = 0;
-      rowsum = 0;
+      unsigned long long best = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        best = red[w] > best ? red[w] : best;
-        rowsum += red2[w];
+      for (int k = 0; k < K; ++k) {
+        if (slot[k] >= 0) {
+          const unsigned long long x = T[slot[k]];
+          const unsigned long long key = argmax_key((uint32_t)(x >> 32), (uint32_t)x);
+          best = key > best ? key : best;
+          T[slot[k]] = kEmptySlot;
+        }
       }
-    }
-    if (v >= 0) {
-      if (lane == 0) {
-        lc.processed += 1;
-        lc.edges += (unsigned long long)(e - b);
-        lc.overflow += rowsum >> 32 ? 1 : 0;
-      }
-      if (best) {
-        const uint32_t cstar = key_label(best);
-        if (cstar != (uint32_t)a.C[v]) {
-          if (lane == 0) record_change(a, v, cstar, lc);
-          if (sv.mark) {
+      if constexpr (G <= 64) {
+        best = group_max<G>(best);
+        rowsum = group_sum<G>(rowsum);
+      } else {
+        best = group_max<kWave>(best);
+        rowsum = wave_sum(rowsum);
+        if (wl == 0) {
+          red[wid] = best;
+          red2[wid] = rowsum;
+        }
+        __syncthreads();
+        best = 0;
+        rowsum = 0;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-              if (j[k] >= 0) {
-                if (!sv.nact[j[k]]) sv.nact[j[k]] = 1;
-                lc.marked += 1;
-              }
+        for (int w = 0; w < NW; ++w) {
+          best = red[w] > best ? red[w] : best;
+          rowsum += red2[w];
+        }
+      }
+      if (v >= 0) {
+        if (lane == 0) {
+          lc.processed += 1;
+          lc.edges += (unsigned long long)(e - b);
+          lc.overflow += rowsum >> 32 ? 1 : 0;
+        }
+        if (best) {
+          const uint32_t cstar = key_label(best);
+          if (cstar != (uint32_t)a.C[v]) {
+            if (lane == 0) record_change(a, v, cstar, lc);
+            if (sv.mark) {
+#pragma unroll
+              for (int k = 0; k < K; ++k)
+                if (j[k] >= 0) {
+                  if (!sv.nact[j[k]]) sv.nact[j[k]] = 1;
+                  lc.marked += 1;
+                }
+            }
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
   flush_counts(a, lc, red);
 }
@@ -224,7 +247,8 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
 // Copies the new label of every changed vertex into C, clears chg and, when
 // requested, clears the active flags consumed by the sweep.  Four vertices per
 // thread; the flag arrays are padded to a multiple of 4 bytes.
-__global__ __launch_bounds__(256) void apply_changes(SweepArgs a, int32_t *__restrict__ C, int64_t n) {
+__global__ __launch_bounds__(256) void apply_changes(SweepArgs a, int32_t *__restrict__ C, int64_t n,
+                                                     unsigned long long *__restrict__ gdn) {
   SweepView sv;
   if (!sweep_view(a, sv)) return;
   const int32_t *__restrict__ Cn = a.Cn;
@@ -232,17 +256,46 @@ __global__ __launch_bounds__(256) void apply_changes(SweepArgs a, int32_t *__res
   uint8_t *act_clear = sv.dense ? nullptr : const_cast<uint8_t *>(sv.act);
   const int64_t quads = (n + 3) / 4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
-    uint32_t word = reinterpret_cast<uint32_t *>(chg)[q];
-    if (act_clear) reinterpret_cast<uint32_t *>(act_clear)[q] = 0u;
-    if (!word) continue;
-    reinterpret_cast<uint32_t *>(chg)[q] = 0u;
+  const int wl = threadIdx.x % kWave;
+  // uniform trip count per block, so the per-graph counting below can use
+  // whole-wave reductions
+  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x; q0 < quads; q0 += stride) {
+    const int64_t q = q0 + threadIdx.x;
+    uint32_t word = 0;
+    if (q < quads) {
+      word = reinterpret_cast<uint32_t *>(chg)[q];
+      if (act_clear) reinterpret_cast<uint32_t *>(act_clear)[q] = 0u;
+    }
+    int32_t gq = -1;
+    unsigned long long cnt = 0;
+    if (word) {
+      reinterpret_cast<uint32_t *>(chg)[q] = 0u;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if ((word >> (8 * k)) & 0xffu) {
-        const int64_t v = 4 * q + k;
-        C[v] = Cn[v];
-      }
+      for (int k = 0; k < 4; ++k)
+        if ((word >> (8 * k)) & 0xffu) {
+          const int64_t v = 4 * q + k;
+          C[v] = Cn[v];
+          if (gdn) {
+            const int32_t g = a.gid[v];
+            if (gq < 0) gq = g;
+            if (g == gq)
+              cnt += 1;
+            else
+              atomicAdd(&gdn[g], 1ull);  // quad straddles two graphs
+          }
+        }
+    }
+    if (!gdn) continue;
+    // changes per graph: one atomic per run of lanes with the same graph
+    unsigned long long pending = __ballot(cnt > 0);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int32_t lg = __shfl(gq, leader);
+      const bool same = cnt > 0 && gq == lg;
+      const unsigned long long sum = wave_sum(same ? cnt : 0ull);
+      if (wl == leader) atomicAdd(&gdn[lg], sum);
+      pending &= ~__ballot(same);
+    }
   }
 }
 
@@ -275,43 +328,44 @@ int grid_for(int64_t items, int per_block, int cap) {
   return (int)(g > cap ? cap : g);
 }
 
+// Window of list entries per block iteration for a tier of `count` vertices
+// handled by groups of G lanes: as large as the block (one flag check per
+// thread), but small enough that the tier still spreads over about
+// kMaxTierGrid blocks.
+int window_for(int64_t count, int gpb, int block) {
+  const int64_t per_block = (count + kMaxTierGrid - 1) / kMaxTierGrid;
+  int64_t win = (per_block + gpb - 1) / gpb * gpb;
+  if (win < gpb) win = gpb;
+  if (win > block) win = block;
+  return (int)win;
+}
+
+template <int G, int LOG2S, int BLOCK, int K>
+int launch_lds(const SweepArgs &a, const int32_t *list, int64_t first, int64_t count, hipStream_t s) {
+  const int win = window_for(count, BLOCK / G, BLOCK);
+  const int grid = grid_for(count, win, kMaxTierGrid);
+  sweep_lds<G, LOG2S, BLOCK, K><<<grid, BLOCK, 0, s>>>(a, list, first, count, win);
+  return grid;
+}
+
 }  // namespace
 
 hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t first,
                              int64_t count, int *grid_out, hipStream_t s) {
   *grid_out = 0;
   if (count <= 0) return hipSuccess;
-  constexpr int kCap = kMaxTierGrid;
   int grid = 0;
   switch (tier) {
     case 1:
-      grid = grid_for(count, 256, kCap);
+      grid = grid_for(count, 256, kMaxTierGrid);
       sweep_thread<8><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
-    case 2:
-      grid = grid_for(count, 256 / 8, kCap);
-      sweep_lds<8, 5, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
-      break;
-    case 3:
-      grid = grid_for(count, 256 / 16, kCap);
-      sweep_lds<16, 6, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
-      break;
-    case 4:
-      grid = grid_for(count, 256 / 32, kCap);
-      sweep_lds<32, 7, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
-      break;
-    case 5:
-      grid = grid_for(count, 256 / 64, kCap);
-      sweep_lds<64, 8, 256, 2><<<grid, 256, 0, s>>>(a, list, first, count);
-      break;
-    case 6:
-      grid = grid_for(count, 256 / 64, kCap);
-      sweep_lds<64, 10, 256, 8><<<grid, 256, 0, s>>>(a, list, first, count);
-      break;
-    case 7:
-      grid = grid_for(count, 1, kCap);
-      sweep_lds<256, 12, 256, 8><<<grid, 256, 0, s>>>(a, list, first, count);
-      break;
+    case 2: grid = launch_lds<8, 5, 256, 2>(a, list, first, count, s); break;
+    case 3: grid = launch_lds<16, 6, 256, 2>(a, list, first, count, s); break;
+    case 4: grid = launch_lds<32, 7, 256, 2>(a, list, first, count, s); break;
+    case 5: grid = launch_lds<64, 8, 256, 2>(a, list, first, count, s); break;
+    case 6: grid = launch_lds<64, 10, 256, 8>(a, list, first, count, s); break;
+    case 7: grid = launch_lds<256, 12, 256, 8>(a, list, first, count, s); break;
     default:
       return hipErrorInvalidValue;
   }
@@ -360,9 +414,10 @@ hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
   return hipGetLastError();
 }
 
-hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, hipStream_t s) {
+hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, int64_t *gdn, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  apply_changes<<<grid_for((n + 3) / 4, 256, 256 * 32), 256, 0, s>>>(a, C, n);
+  apply_changes<<<grid_for((n + 3) / 4, 256, 256 * 32), 256, 0, s>>>(
+      a, C, n, reinterpret_cast<unsigned long long *>(gdn));
   return hipGetLastError();
 }
 
@@ -444,36 +499,23 @@ __device__ int64_t conv_limit(int64_t n, double tol) {
 __global__ __launch_bounds__(256) void batch_init(const int64_t *__restrict__ vtx_base, int64_t graphs,
                                                   int32_t max_iters, double tol, int32_t *__restrict__ gid,
                                                   int64_t *__restrict__ glimit, int32_t *__restrict__ giters,
-                                                  uint8_t *__restrict__ gdone) {
+                                                  uint8_t *__restrict__ gdone, int64_t *__restrict__ gdn) {
   for (int64_t g = blockIdx.x; g < graphs; g += gridDim.x) {
     const int64_t b = vtx_base[g], e = vtx_base[g + 1];
     for (int64_t v = b + threadIdx.x; v < e; v += blockDim.x) gid[v] = (int32_t)g;
     if (threadIdx.x == 0) {
       glimit[g] = e > b ? conv_limit(e - b, tol) : 0;
       giters[g] = 0;
+      gdn[g] = 0;
       gdone[g] = (e <= b || max_iters <= 0) ? 1 : 0;
     }
   }
 }
 
-// Block per graph: changes of this sweep inside the graph's vertex range.
-__global__ __launch_bounds__(256) void graph_count(SweepArgs a, const int64_t *__restrict__ vtx_base,
-                                                   int64_t graphs, int64_t *__restrict__ gdn) {
-  __shared__ unsigned long long red[256 / kWave];
-  if (a.ctrl->done) return;
-  for (int64_t g = blockIdx.x; g < graphs; g += gridDim.x) {
-    unsigned long long cnt = 0;
-    if (!a.gdone[g])
-      for (int64_t v = vtx_base[g] + threadIdx.x; v < vtx_base[g + 1]; v += blockDim.x) cnt += a.chg[v];
-    cnt = block_sum(cnt, red);
-    if (threadIdx.x == 0) gdn[g] = (int64_t)cnt;
-    __syncthreads();
-  }
-}
-
 // Thread per graph: count the sweep, stop graphs that converged or reached
-// the cap, and add the graphs still running to ctrl->active.
-__global__ __launch_bounds__(256) void graph_end(SweepCtrl *c, const int64_t *__restrict__ gdn,
+// the cap, add the graphs still running to ctrl->active and clear the
+// per-graph change counts for the next sweep.
+__global__ __launch_bounds__(256) void graph_end(SweepCtrl *c, int64_t *__restrict__ gdn,
                                                  const int64_t *__restrict__ glimit, int32_t *giters,
                                                  uint8_t *gdone, int64_t graphs) {
   __shared__ unsigned long long red[256 / kWave];
@@ -487,6 +529,7 @@ __global__ __launch_bounds__(256) void graph_end(SweepCtrl *c, const int64_t *__
       gdone[g] = 1;
     else
       running = 1;
+    gdn[g] = 0;
   }
   running = block_sum(running, red);
   if (threadIdx.x == 0 && running) atomicAdd(reinterpret_cast<unsigned long long *>(&c->active), running);
@@ -507,21 +550,15 @@ hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_fla
 }
 
 hipError_t launch_batch_init(const int64_t *vtx_base, int64_t graphs, int32_t max_iters, double tol,
-                             int32_t *gid, int64_t *glimit, int32_t *giters, uint8_t *gdone, hipStream_t s) {
+                             int32_t *gid, int64_t *glimit, int32_t *giters, uint8_t *gdone, int64_t *gdn,
+                             hipStream_t s) {
   if (graphs <= 0) return hipSuccess;
   batch_init<<<grid_for(graphs, 1, 256 * 16), 256, 0, s>>>(vtx_base, graphs, max_iters, tol, gid, glimit,
-                                                          giters, gdone);
+                                                          giters, gdone, gdn);
   return hipGetLastError();
 }
 
-hipError_t launch_graph_count(const SweepArgs &a, const int64_t *vtx_base, int64_t graphs, int64_t *gdn,
-                              hipStream_t s) {
-  if (graphs <= 0) return hipSuccess;
-  graph_count<<<grid_for(graphs, 1, 256 * 16), 256, 0, s>>>(a, vtx_base, graphs, gdn);
-  return hipGetLastError();
-}
-
-hipError_t launch_graph_end(SweepCtrl *ctrl, const int64_t *gdn, const int64_t *glimit, int32_t *giters,
+hipError_t launch_graph_end(SweepCtrl *ctrl, int64_t *gdn, const int64_t *glimit, int32_t *giters,
                             uint8_t *gdone, int64_t graphs, hipStream_t s) {
   if (graphs <= 0) return hipSuccess;
   graph_end<<<grid_for(graphs, 256, 1 << 20), 256, 0, s>>>(ctrl, gdn, glimit, giters, gdone, graphs);
