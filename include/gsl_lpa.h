@@ -138,6 +138,24 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
               int32_t *labels_out);
 
 /*
+ * gsl_disconnected -- the disconnected-community check (Alg. 4): a community
+ * (the vertices sharing one label) is disconnected when its vertices are not
+ * all joined by paths whose vertices all carry that label.
+ *
+ *   labels    : int32[n] device array, each value in [0, n)
+ *   flags_out : uint8[n] DEVICE array indexed by label: 1 if that community
+ *               is disconnected, else 0 (labels no vertex carries get 0);
+ *               may be NULL
+ *   count_out : HOST pointer receiving the number of disconnected
+ *               communities; may be NULL
+ * Returns GSL_EINVAL if a label is outside [0, n).  After gsl_lpa with the
+ * split the count is 0; on raw LPA labels (split = 0) it measures what the
+ * split repairs.
+ */
+int gsl_disconnected(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels,
+                     uint8_t *flags_out, int64_t *count_out);
+
+/*
  * gsl_modularity -- modularity Q of a labelling (Eq. 1, second form):
  *   Q = sum_c [ sigma_c / 2m - (Sigma_c / 2m)^2 ]
  * where sigma_c sums w over CSR entries (i, j) with C_i = C_j = c, Sigma_c

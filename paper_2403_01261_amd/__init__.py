@@ -15,7 +15,7 @@ import os
 import torch
 
 __all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_batched", "gsl_lpa_graphs", "gsl_check_graph", "Context",
-           "gsl_split",
+           "gsl_split", "gsl_disconnected",
            "gsl_modularity", "gsl_convergence_limit", "gsl_set_stream", "gsl_release", "gsl_version",
            "GslError", "LIB_PATH", "load"]
 
@@ -97,6 +97,7 @@ def load(path: str = None):
                                    ctypes.c_double, ctypes.POINTER(_Options), ctypes.POINTER(_Stats),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.gsl_check_graph.argtypes = [_VP, _VP, ctypes.c_int64]
+    lib.gsl_disconnected.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP, ctypes.POINTER(ctypes.c_int64)]
     lib.gsl_split.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP]
     lib.gsl_modularity.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]
     lib.gsl_convergence_limit.argtypes = [ctypes.c_int64, ctypes.c_double]
@@ -107,7 +108,7 @@ def load(path: str = None):
     lib.gsl_release.restype = None
     for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream,
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
-              lib.gsl_lpa_graphs, lib.gsl_check_graph):
+              lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -320,6 +321,20 @@ def gsl_split(offsets, cols, labels_in, out=None):
         out = torch.empty(n, dtype=torch.int32, device=offsets.device)
     _check(lib.gsl_split(po, pc, n, pin, _dev(out, (torch.int32,), "out")))
     return out
+
+
+def gsl_disconnected(offsets, cols, labels, flags=True):
+    """Alg. 4: (number of disconnected communities, uint8 flags indexed by
+    label or None)."""
+    lib = _bind_stream()
+    po, pc, _, n = _graph_args(offsets, cols, None)
+    if labels.numel() != n:
+        raise ValueError("labels must hold n labels")
+    D = torch.empty(n, dtype=torch.uint8, device=offsets.device) if flags else None
+    cnt = ctypes.c_int64(0)
+    _check(lib.gsl_disconnected(po, pc, n, _dev(labels, (torch.int32,), "labels"),
+                                _dev(D, (torch.uint8,), "flags", allow_none=True), ctypes.byref(cnt)))
+    return cnt.value, D
 
 
 def gsl_modularity(offsets, cols, weights, labels) -> float:

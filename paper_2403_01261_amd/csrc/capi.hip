@@ -1124,6 +1124,38 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
   return GSL_OK;
 }
 
+int gsl_disconnected(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels,
+                     uint8_t *flags_out, int64_t *count_out) {
+  if (count_out) *count_out = 0;
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n out of range");
+  if (n == 0) return GSL_OK;
+  if (!offsets || !labels) return fail(GSL_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_mu);
+  const hipStream_t st = g_stream;
+  Scratch *sp = nullptr;
+  int rc = get_scratch(&sp);
+  if (rc) return rc;
+  Scratch &s = *sp;
+  int64_t nnz = 0;
+  if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
+  if ((rc = ensure_scratch(s, n, 1))) return rc;
+  if ((rc = check_labels(s, labels, n, st))) return rc;
+  if ((rc = run_plan(s, offsets, n, st))) return rc;
+  Counters plan = *s.ctr_host;
+  // split labels into Cn, then piece counts per community in parent
+  HIP_TRY(gsl::launch_split(offsets, cols, n, labels, s.parent, s.Cn, s.list, plan.tier_count, plan.tier_start,
+                            nullptr, nullptr, n, dominant_ptr(s), st));
+  unsigned long long *cnt = reinterpret_cast<unsigned long long *>(&s.ctr->split_changed);
+  HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
+  HIP_TRY(gsl::launch_disconnected(labels, s.Cn, n, s.parent, flags_out, cnt, st));
+  unsigned long long host = 0;
+  HIP_TRY(hipMemcpyAsync(&host, cnt, sizeof(host), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (count_out) *count_out = (int64_t)host;
+  return GSL_OK;
+}
+
 int gsl_modularity(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
                    const int32_t *labels, double *q_out) {
   std::lock_guard<std::mutex> lk(g_mu);

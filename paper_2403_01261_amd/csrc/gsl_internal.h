@@ -203,6 +203,11 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
                         hipStream_t s);
+// Alg. 4 from split labels comp (smallest id of each piece): pieces[c] =
+// number of pieces of community c, D[c] = pieces[c] > 1 (D may be NULL),
+// *count += number of such communities.
+hipError_t launch_disconnected(const int32_t *labels, const int32_t *comp, int64_t n, int32_t *pieces,
+                               uint8_t *D, unsigned long long *count, hipStream_t s);
 hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_t *w, int64_t n,
                           const int32_t *list, const int64_t *tier_count_h, const int64_t *tier_start_h,
                           const int64_t *hub_chunk_start, int64_t hub_chunks, int32_t *old2new,

@@ -246,6 +246,56 @@ int grid_cap(int64_t items, int per_block, int cap) {
 //                 vertices, orig[p] the caller id of vertex p (orig holds
 //                 n_total entries, isolated vertices last); out is written in
 //                 caller ids with the smallest caller id of each piece.
+namespace {
+
+// Alg. 4 on top of the split: a community is disconnected iff it has more
+// than one connected piece, and every piece has exactly one root (the vertex
+// whose piece label is its own id).  One count per root, summed per community
+// with one atomic per run of lanes holding the same label.
+__global__ __launch_bounds__(256) void dc_pieces(const int32_t *__restrict__ labels,
+                                                 const int32_t *__restrict__ comp, int64_t n,
+                                                 int32_t *__restrict__ pieces) {
+  const int wl = threadIdx.x % kWave;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
+    const int64_t v = v0 + threadIdx.x;
+    const int32_t c = (v < n && comp[v] == (int32_t)v) ? labels[v] : -1;
+    unsigned long long pending = __ballot(c >= 0);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int32_t lc = __shfl(c, leader);
+      const unsigned long long same = __ballot(c == lc);
+      if (wl == leader) atomicAdd(&pieces[lc], (int32_t)__popcll(same));
+      pending &= ~same;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void dc_flags(const int32_t *__restrict__ pieces, int64_t n,
+                                                uint8_t *__restrict__ D, unsigned long long *count) {
+  __shared__ unsigned long long red[256 / kWave];
+  unsigned long long cnt = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+    const bool d = pieces[c] > 1;
+    if (D) D[c] = d ? 1 : 0;
+    cnt += d ? 1 : 0;
+  }
+  cnt = block_sum(cnt, red);
+  if (threadIdx.x == 0 && cnt) atomicAdd(count, cnt);
+}
+
+}  // namespace
+
+hipError_t launch_disconnected(const int32_t *labels, const int32_t *comp, int64_t n, int32_t *pieces,
+                               uint8_t *D, unsigned long long *count, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_i32<<<grid_cap(n, 256, 256 * 16), 256, 0, s>>>(pieces, 0, n);
+  dc_pieces<<<grid_cap(n, 256, 256 * 16), 256, 0, s>>>(labels, comp, n, pieces);
+  dc_flags<<<grid_cap(n, 256, 256 * 16), 256, 0, s>>>(pieces, n, D, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,

@@ -86,6 +86,11 @@ def test_batched_argument_errors_without_device_work():
     assert lib.gsl_check_graph(None, None, -1) == gsl.GSL_EINVAL
     assert lib.gsl_check_graph(None, None, 0) == gsl.GSL_OK
     assert lib.gsl_check_graph(None, None, 4) == gsl.GSL_EINVAL
+    cnt = ctypes.c_int64(5)
+    assert lib.gsl_disconnected(None, None, 0, None, None, ctypes.byref(cnt)) == gsl.GSL_OK
+    assert cnt.value == 0
+    assert lib.gsl_disconnected(None, None, -3, None, None, None) == gsl.GSL_EINVAL
+    assert lib.gsl_disconnected(None, None, 3, None, None, None) == gsl.GSL_EINVAL
 
 
 def _literal_limit(n, tol):

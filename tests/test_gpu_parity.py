@@ -233,3 +233,27 @@ def test_full_workload_matches_oracle_hash(gsl, idx):
     off, cols, w = to_device(g)
     q = gsl.gsl_modularity(off, cols, w, torch.from_numpy(lab).cuda())
     assert abs(q - gold["modularity"]) <= 1e-12 * max(1.0, abs(gold["modularity"]))
+
+
+def test_disconnected_matches_alg4(gsl):
+    """Alg. 4 on the GPU against the oracle: raw LPA labels (split = 0),
+    random labellings and the final GSL-LPA labels (no disconnected
+    community left)."""
+    rng = np.random.default_rng(12)
+    graphs = [workloads.make(1), workloads.make(2, small=True), workloads.make(3, small=True),
+              graphgen.cliques([3, 4, 5], perm=rng.permutation(12)), graphgen.from_entries(5, [], [])]
+    for g in graphs:
+        raw = oracle.lpa(g, split=False).labels
+        labellings = [raw, oracle.lpa(g).labels, rng.integers(0, max(1, g.n // 7), size=g.n).astype(np.int32),
+                      np.zeros(g.n, dtype=np.int32)]
+        off, cols, _ = to_device(g)
+        for k, lab in enumerate(labellings):
+            D, cnt = oracle.disconnected(g, lab)
+            got_cnt, got_D = gsl.gsl_disconnected(off, cols, torch.from_numpy(lab).cuda())
+            assert got_cnt == cnt, (g.name, k, got_cnt, cnt)
+            np.testing.assert_array_equal(got_D.cpu().numpy(), D, err_msg="%s labelling %d" % (g.name, k))
+        say("%s: raw LPA leaves %d disconnected communities" % (g.name, oracle.disconnected(g, raw)[1]))
+    with pytest.raises(gsl.GslError):
+        g = graphs[0]
+        off, cols, _ = to_device(g)
+        gsl.gsl_disconnected(off, cols, torch.full((g.n,), g.n, dtype=torch.int32, device="cuda"))
