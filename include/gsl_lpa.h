@@ -274,6 +274,38 @@ int gsl_check_graph(const int64_t *offsets, const int32_t *cols, int64_t n);
  */
 int64_t gsl_convergence_limit(int64_t n, double tolerance);
 
+/*
+ * Degree tiers (the launch plan).  Vertices are bucketed by degree into
+ * GSL_TIER_LEVELS levels plus degree 0 (never processed) and hubs (every
+ * degree above the last level, processed chunk-wise).  Level l takes the
+ * degrees (max_degree[l-1], max_degree[l]] and runs the sweep kernel
+ * `variant`.  Variants differ in lanes per vertex, entries per lane, LDS
+ * table size and workgroup size (gsl_tier_variant); a variant takes rows of
+ * up to `capacity` entries.  Variant 0 (a thread per vertex) is level 0's and
+ * only level 0's.  The choice changes speed, never results.
+ */
+#define GSL_TIER_LEVELS 7
+typedef struct gsl_tier {
+  int32_t max_degree; /* non-decreasing over the levels, <= the variant's capacity */
+  int32_t variant;
+} gsl_tier;
+typedef struct gsl_variant_info {
+  int32_t group;      /* lanes per vertex (1: a thread per vertex) */
+  int32_t table_log2; /* LDS table of 2^table_log2 slots per group */
+  int32_t block;      /* threads per workgroup */
+  int32_t per_lane;   /* row entries each lane holds */
+  int32_t capacity;   /* largest degree: group * per_lane */
+} gsl_variant_info;
+
+/* Sets the tiers of all later calls in this process (levels[GSL_TIER_LEVELS];
+ * NULL restores the defaults: bounds 8/16/32/64/128/512/2048 with variants
+ * 0/1/3/5/7/9/11).  GSL_EINVAL for an invalid table (nothing changes). */
+int gsl_set_tiers(const gsl_tier *levels);
+/* Current tiers into levels_out[GSL_TIER_LEVELS]. */
+int gsl_get_tiers(gsl_tier *levels_out);
+/* Shape of sweep variant `variant` (0 .. until GSL_EINVAL). */
+int gsl_tier_variant(int32_t variant, gsl_variant_info *info);
+
 /* Stream for all subsequent calls of this process (a hipStream_t; NULL = the
  * null stream). */
 int gsl_set_stream(void *hip_stream);

@@ -15,7 +15,7 @@ import os
 import torch
 
 __all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_batched", "gsl_lpa_graphs", "gsl_check_graph", "Context",
-           "gsl_split", "gsl_disconnected",
+           "gsl_split", "gsl_disconnected", "gsl_set_tiers", "gsl_get_tiers", "gsl_tier_variants",
            "gsl_modularity", "gsl_convergence_limit", "gsl_set_stream", "gsl_release", "gsl_version",
            "GslError", "LIB_PATH", "load"]
 
@@ -59,6 +59,18 @@ class _Stats(ctypes.Structure):
                 ("ms_tier", ctypes.c_float * STATS_TIERS)]
 
 
+TIER_LEVELS = 7
+
+
+class _Tier(ctypes.Structure):
+    _fields_ = [("max_degree", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+
+class _VariantInfo(ctypes.Structure):
+    _fields_ = [("group", ctypes.c_int32), ("table_log2", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("per_lane", ctypes.c_int32), ("capacity", ctypes.c_int32)]
+
+
 class _Graph(ctypes.Structure):
     _fields_ = [("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p), ("weights", ctypes.c_void_p),
                 ("labels_out", ctypes.c_void_p), ("n", ctypes.c_int64)]
@@ -97,6 +109,9 @@ def load(path: str = None):
                                    ctypes.c_double, ctypes.POINTER(_Options), ctypes.POINTER(_Stats),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.gsl_check_graph.argtypes = [_VP, _VP, ctypes.c_int64]
+    lib.gsl_set_tiers.argtypes = [ctypes.POINTER(_Tier)]
+    lib.gsl_get_tiers.argtypes = [ctypes.POINTER(_Tier)]
+    lib.gsl_tier_variant.argtypes = [ctypes.c_int32, ctypes.POINTER(_VariantInfo)]
     lib.gsl_disconnected.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP, ctypes.POINTER(ctypes.c_int64)]
     lib.gsl_split.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP]
     lib.gsl_modularity.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]
@@ -108,7 +123,8 @@ def load(path: str = None):
     lib.gsl_release.restype = None
     for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream,
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
-              lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected):
+              lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected, lib.gsl_set_tiers,
+              lib.gsl_get_tiers, lib.gsl_tier_variant):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -345,6 +361,45 @@ def gsl_modularity(offsets, cols, weights, labels) -> float:
     q = ctypes.c_double(0.0)
     _check(lib.gsl_modularity(po, pc, pw, n, _dev(labels, (torch.int32,), "labels"), ctypes.byref(q)))
     return q.value
+
+
+def gsl_set_tiers(levels=None) -> None:
+    """Degree tiers of later calls: a list of TIER_LEVELS (max_degree,
+    variant) pairs, or None for the defaults.  Changes speed, not results."""
+    lib = load()
+    if levels is None:
+        _check(lib.gsl_set_tiers(None))
+        return
+    if len(levels) != TIER_LEVELS:
+        raise ValueError("need %d levels" % TIER_LEVELS)
+    arr = (_Tier * TIER_LEVELS)(*[_Tier(int(d), int(v)) for d, v in levels])
+    _check(lib.gsl_set_tiers(arr))
+
+
+def gsl_get_tiers():
+    lib = load()
+    arr = (_Tier * TIER_LEVELS)()
+    _check(lib.gsl_get_tiers(arr))
+    return [(t.max_degree, t.variant) for t in arr]
+
+
+def gsl_tier_variants():
+    """Shapes of the sweep kernel variants: list of dicts (index = variant)."""
+    lib = load()
+    out = []
+    while True:
+        info = _VariantInfo()
+        if lib.gsl_tier_variant(len(out), ctypes.byref(info)) != GSL_OK:
+            return out
+        out.append({"group": info.group, "table_log2": info.table_log2, "block": info.block,
+                    "per_lane": info.per_lane, "capacity": info.capacity})
+
+
+def variant_kernel_name(v: dict) -> str:
+    """The sweep kernel's name as profilers print it (template arguments)."""
+    if v["group"] == 1:
+        return "sweep_thread<%d>" % v["per_lane"]
+    return "sweep_lds<%d, %d, %d, %d>" % (v["group"], v["table_log2"], v["block"], v["per_lane"])
 
 
 def gsl_convergence_limit(n: int, tolerance: float) -> int:

@@ -22,6 +22,14 @@ using gsl::Counters;
 thread_local std::string g_err;
 hipStream_t g_stream = nullptr;
 std::mutex g_mu;
+// Degree tiers used by every call (gsl_set_tiers); read once per call.
+std::mutex g_tier_mu;
+gsl::TierConfig g_tiers = gsl::kDefaultTiers;
+
+gsl::TierConfig current_tiers() {
+  std::lock_guard<std::mutex> lk(g_tier_mu);
+  return g_tiers;
+}
 
 int fail(int code, const char *fmt, ...) {
   char buf[512];
@@ -267,9 +275,9 @@ int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st) {
 }
 
 // Runs the degree plan and copies the counters block to the host mirror.
-int run_plan(Scratch &s, const int64_t *offsets, int64_t n, hipStream_t st) {
+int run_plan(Scratch &s, const int64_t *offsets, int64_t n, const gsl::TierConfig &cfg, hipStream_t st) {
   HIP_TRY(hipMemsetAsync(s.ctr, 0, (size_t)s.ctr_bytes, st));
-  HIP_TRY(gsl::launch_plan(offsets, n, s.list, s.blk_counts, s.ctr, st));
+  HIP_TRY(gsl::launch_plan(offsets, n, s.list, s.blk_counts, s.ctr, cfg, st));
   HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return GSL_OK;
@@ -442,8 +450,9 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
   if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   if ((rc = ensure_scratch(s, n, max_iters))) return rc;
+  const gsl::TierConfig cfg = current_tiers();
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
-  if ((rc = run_plan(s, offsets, n, st))) return rc;
+  if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
   // Tier t is the id range [tier_start[t], +tier_count[t]) of s.list; hubs
   // (tier 8) come first, isolated vertices (tier 0) last.
@@ -477,7 +486,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
                                 s.hub_chunk_start, H > 0 ? s.h_chunk[(size_t)H] : 0, s.old2new, s.off2,
                                 s.cols2, weights ? s.w2 : nullptr, s.lab2, s.blk_counts, s.first_key,
                                 s.hub_rowsum, reinterpret_cast<unsigned long long *>(&s.ctr->first_flags),
-                                dn_arr, max_iters > 0 ? 1 : 0, st));
+                                dn_arr, max_iters > 0 ? 1 : 0, cfg, st));
     g_off = s.off2;
     g_cols = s.cols2;
     g_w = weights ? s.w2 : nullptr;
@@ -573,7 +582,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
           }
         }
       } else {
-        HIP_TRY(gsl::launch_sweep_tier(t, a, g_list, plan.tier_start[t], cnt, &grids.g[t], cur));
+        HIP_TRY(gsl::launch_sweep_tier(cfg.variant[t], a, g_list, plan.tier_start[t], cnt, &grids.g[t], cur));
       }
       if (timed && (rc = rec(nev++))) return rc;
     }
@@ -611,6 +620,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     for (int t = 0; t < gsl::kNumTiers; ++t) {
       key.push_back((uint64_t)plan.tier_count[t]);
       key.push_back((uint64_t)plan.tier_start[t]);
+      key.push_back((uint64_t)cfg.variant[t]);
     }
     for (size_t bi = 0; bi < s.hub_batches.size(); ++bi) {
       key.push_back((uint64_t)s.hub_batches[bi].first);
@@ -651,12 +661,12 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if (renumber) {
     if (o.split)
       HIP_TRY(gsl::launch_split(g_off, g_cols, np, C, s.parent, labels_out, nullptr, plan.tier_count,
-                                plan.tier_start, s.list, s.minorig, n, dominant_ptr(s), st));
+                                plan.tier_start, s.list, s.minorig, n, dominant_ptr(s), cfg, st));
     else
       HIP_TRY(gsl::launch_reorder_scatter(s.list, C, np, n, labels_out, st));
   } else if (o.split) {
     HIP_TRY(gsl::launch_split(offsets, cols, n, C, s.parent, labels_out, s.list, plan.tier_count,
-                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), st));
+                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), cfg, st));
   }
   if (batch) {
     HIP_TRY(gsl::launch_localize(labels_out, batch->vtx_base, batch->graphs, n, st));
@@ -1116,10 +1126,11 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
   if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   if ((rc = ensure_scratch(s, n, 1))) return rc;
   if ((rc = check_labels(s, labels_in, n, st))) return rc;
-  if ((rc = run_plan(s, offsets, n, st))) return rc;
+  const gsl::TierConfig cfg = current_tiers();
+  if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list,
-                            plan.tier_count, plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), st));
+                            plan.tier_count, plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), cfg, st));
   HIP_TRY(hipStreamSynchronize(st));
   return GSL_OK;
 }
@@ -1141,11 +1152,12 @@ int gsl_disconnected(const int64_t *offsets, const int32_t *cols, int64_t n, con
   if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   if ((rc = ensure_scratch(s, n, 1))) return rc;
   if ((rc = check_labels(s, labels, n, st))) return rc;
-  if ((rc = run_plan(s, offsets, n, st))) return rc;
+  const gsl::TierConfig cfg = current_tiers();
+  if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
   // split labels into Cn, then piece counts per community in parent
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels, s.parent, s.Cn, s.list, plan.tier_count, plan.tier_start,
-                            nullptr, nullptr, n, dominant_ptr(s), st));
+                            nullptr, nullptr, n, dominant_ptr(s), cfg, st));
   unsigned long long *cnt = reinterpret_cast<unsigned long long *>(&s.ctr->split_changed);
   HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
   HIP_TRY(gsl::launch_disconnected(labels, s.Cn, n, s.parent, flags_out, cnt, st));
@@ -1181,6 +1193,51 @@ int gsl_modularity(const int64_t *offsets, const int32_t *cols, const uint32_t *
   HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   *q_out = s.ctr_host->q;
+  return GSL_OK;
+}
+
+int gsl_set_tiers(const gsl_tier *levels) {
+  gsl::TierConfig c = gsl::kDefaultTiers;
+  if (levels) {
+    int64_t prev = 0;
+    for (int l = 0; l < GSL_TIER_LEVELS; ++l) {
+      const int t = l + 1;
+      const int32_t v = levels[l].variant;
+      const int64_t b = levels[l].max_degree;
+      if (v < 0 || v >= gsl::kNumVariants) return fail(GSL_EINVAL, "level %d: no variant %d", l, v);
+      if ((l == 0) != (v == 0)) return fail(GSL_EINVAL, "variant 0 (a thread per vertex) is level 0's only");
+      if (b < prev) return fail(GSL_EINVAL, "level %d: degree bounds must not decrease", l);
+      if (b > gsl::variant_capacity(v))
+        return fail(GSL_EINVAL, "level %d: bound %lld exceeds variant %d's %lld entries", l, (long long)b, v,
+                    (long long)gsl::variant_capacity(v));
+      c.bound[t] = b;
+      c.variant[t] = v;
+      prev = b;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tier_mu);
+  g_tiers = c;
+  return GSL_OK;
+}
+
+int gsl_get_tiers(gsl_tier *levels_out) {
+  if (!levels_out) return fail(GSL_EINVAL, "levels_out must not be NULL");
+  const gsl::TierConfig c = current_tiers();
+  for (int l = 0; l < GSL_TIER_LEVELS; ++l) {
+    levels_out[l].max_degree = (int32_t)c.bound[l + 1];
+    levels_out[l].variant = c.variant[l + 1];
+  }
+  return GSL_OK;
+}
+
+int gsl_tier_variant(int32_t variant, gsl_variant_info *info) {
+  if (variant < 0 || variant >= gsl::kNumVariants || !info) return fail(GSL_EINVAL, "no such variant");
+  const gsl::SweepVariant &x = gsl::kVariants[variant];
+  info->group = x.group;
+  info->table_log2 = x.log2s;
+  info->block = x.block;
+  info->per_lane = x.per_lane;
+  info->capacity = (int32_t)gsl::variant_capacity(variant);
   return GSL_OK;
 }
 

@@ -19,8 +19,44 @@ namespace gsl {
 // ----------------------------------------------------------------------------
 constexpr int kNumTiers = 9;
 constexpr int kHubTier = 8;
-constexpr int64_t kTierMaxDeg[kNumTiers] = {0, 8, 16, 32, 64, 128, 512, 2048,
-                                            (int64_t)0x7fffffffffffffffLL};
+
+// Sweep kernel variants a tier can use: a thread per vertex (variant 0) or a
+// group of G lanes with K entries per lane and a 2^LOG2S-slot LDS table, in
+// blocks of BLOCK threads.  A variant takes rows of up to G * K entries.
+struct SweepVariant {
+  int group, log2s, block, per_lane;
+};
+constexpr int kNumVariants = 13;
+constexpr SweepVariant kVariants[kNumVariants] = {
+    {1, 0, 256, 8},     // 0: thread per vertex, row in registers (d <= 8)
+    {8, 5, 256, 2},     // 1: d <= 16
+    {4, 5, 256, 4},     // 2: d <= 16
+    {16, 6, 256, 2},    // 3: d <= 32
+    {8, 6, 256, 4},     // 4: d <= 32
+    {32, 7, 256, 2},    // 5: d <= 64
+    {16, 7, 256, 4},    // 6: d <= 64
+    {64, 8, 256, 2},    // 7: d <= 128
+    {32, 8, 256, 4},    // 8: d <= 128
+    {64, 10, 256, 8},   // 9: d <= 512
+    {128, 10, 128, 4},  // 10: d <= 512, one 128-thread workgroup per vertex
+    {256, 12, 256, 8},  // 11: d <= 2048, one workgroup per vertex
+    {512, 12, 512, 4},  // 12: d <= 2048, one 512-thread workgroup per vertex
+};
+constexpr int64_t variant_capacity(int v) { return (int64_t)kVariants[v].group * kVariants[v].per_lane; }
+
+// Degree tiers of one call: tier t (1..7) takes degrees (bound[t-1],
+// bound[t]] with sweep variant variant[t]; tier 0 is degree 0 and tier 8
+// (hubs) every degree above bound[7].
+struct TierConfig {
+  int64_t bound[kNumTiers];
+  int variant[kNumTiers];
+};
+constexpr TierConfig kDefaultTiers = {{0, 8, 16, 32, 64, 128, 512, 2048, (int64_t)0x7fffffffffffffffLL},
+                                      {0, 0, 1, 3, 5, 7, 9, 11, 0}};
+// Bounds as a kernel argument.
+struct TierBounds {
+  int64_t b[kNumTiers];
+};
 
 // Device-side counters; one block of memory zeroed at the start of every call.
 struct Counters {
@@ -115,10 +151,11 @@ struct TierGrids {
 
 // ---- launchers (stream-ordered, no synchronisation) ----
 hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *blk_counts,
-                       Counters *ctr, hipStream_t s);
+                       Counters *ctr, const TierConfig &cfg, hipStream_t s);
 int64_t plan_blocks(int64_t n);
 
-hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t first,
+// Sweep kernel of one tier with the given variant (kVariants index).
+hipError_t launch_sweep_tier(int variant, const SweepArgs &a, const int32_t *list, int64_t first,
                              int64_t count, int *grid_out, hipStream_t s);
 // Sums the per-block records of tier t (part + t * kMaxTierGrid * kCountFields,
 // g.g[t] blocks) into the tier and sweep counters.
@@ -202,7 +239,7 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
-                        hipStream_t s);
+                        const TierConfig &cfg, hipStream_t s);
 // Alg. 4 from split labels comp (smallest id of each piece): pieces[c] =
 // number of pieces of community c, D[c] = pieces[c] > 1 (D may be NULL),
 // *count += number of such communities.
@@ -214,7 +251,7 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
                           int64_t *off2, int32_t *cols2, uint32_t *w2, int32_t *lab,
                           int64_t *scan_tmp, unsigned long long *first_key,
                           unsigned long long *hub_rowsum, unsigned long long *flags,
-                          unsigned long long *dn0, int apply_first, hipStream_t s);
+                          unsigned long long *dn0, int apply_first, const TierConfig &cfg, hipStream_t s);
 hipError_t launch_reorder_scatter(const int32_t *list, const int32_t *val, int64_t np, int64_t n,
                                   int32_t *out, hipStream_t s);
 hipError_t launch_check_labels(const int32_t *labels, int64_t n, unsigned long long *bad,

@@ -17,17 +17,17 @@ namespace {
 
 constexpr int kPlanBlock = 1024;
 
-__device__ __forceinline__ int tier_of(int64_t d) {
+__device__ __forceinline__ int tier_of(int64_t d, const TierBounds &tb) {
   if (d <= 0) return 0;
 #pragma unroll
   for (int t = 1; t < kNumTiers - 1; ++t)
-    if (d <= kTierMaxDeg[t]) return t;
+    if (d <= tb.b[t]) return t;
   return kNumTiers - 1;
 }
 
 __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restrict__ off, int64_t n,
                                                          int64_t *__restrict__ blk_counts,
-                                                         Counters *ctr) {
+                                                         Counters *ctr, TierBounds tb) {
   __shared__ int cnt[kNumTiers];
   __shared__ unsigned long long ecnt[kNumTiers];
   __shared__ unsigned long long dmax[kPlanBlock / kWave];
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restri
   int64_t d = 0;
   if (v < n) {
     d = off[v + 1] - off[v];
-    const int t = tier_of(d);
+    const int t = tier_of(d, tb);
     atomicAdd(&cnt[t], 1);
     if (d > 0) atomicAdd(&ecnt[t], (unsigned long long)d);
   }
@@ -106,13 +106,13 @@ __global__ __launch_bounds__(kPlanBlock) void plan_scan(int64_t *__restrict__ bl
 __global__ __launch_bounds__(kPlanBlock) void plan_scatter(const int64_t *__restrict__ off, int64_t n,
                                                            const int64_t *__restrict__ blk_base,
                                                            const Counters *ctr,
-                                                           int32_t *__restrict__ list) {
+                                                           int32_t *__restrict__ list, TierBounds tb) {
   constexpr int W = kPlanBlock / kWave;
   __shared__ int wcnt[W][kNumTiers];
   const int64_t v = (int64_t)blockIdx.x * kPlanBlock + threadIdx.x;
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   int t = -1;
-  if (v < n) t = tier_of(off[v + 1] - off[v]);
+  if (v < n) t = tier_of(off[v + 1] - off[v], tb);
   const unsigned long long below = (1ull << lane) - 1ull;
   int rank = 0;
 #pragma unroll
@@ -137,12 +137,14 @@ int64_t plan_blocks(int64_t n) { return (n + kPlanBlock - 1) / kPlanBlock; }
 // list receives every vertex grouped by tier (9 first, 0 last); entry
 // tier_start[t] is the first vertex of tier t.
 hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *blk_counts,
-                       Counters *ctr, hipStream_t s) {
+                       Counters *ctr, const TierConfig &cfg, hipStream_t s) {
   const int64_t nblk = plan_blocks(n);
   if (nblk <= 0) return hipSuccess;
-  plan_count<<<(unsigned)nblk, kPlanBlock, 0, s>>>(off, n, blk_counts, ctr);
+  TierBounds tb;
+  for (int t = 0; t < kNumTiers; ++t) tb.b[t] = cfg.bound[t];
+  plan_count<<<(unsigned)nblk, kPlanBlock, 0, s>>>(off, n, blk_counts, ctr, tb);
   plan_scan<<<1, kPlanBlock, 0, s>>>(blk_counts, nblk, ctr);
-  plan_scatter<<<(unsigned)nblk, kPlanBlock, 0, s>>>(off, n, blk_counts, ctr, list);
+  plan_scatter<<<(unsigned)nblk, kPlanBlock, 0, s>>>(off, n, blk_counts, ctr, list, tb);
   return hipGetLastError();
 }
 

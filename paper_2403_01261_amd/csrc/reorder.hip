@@ -292,7 +292,7 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
                           int64_t *off2, int32_t *cols2, uint32_t *w2, int32_t *lab,
                           int64_t *scan_tmp, unsigned long long *first_key,
                           unsigned long long *hub_rowsum, unsigned long long *flags,
-                          unsigned long long *dn0, int apply_first, hipStream_t s) {
+                          unsigned long long *dn0, int apply_first, const TierConfig &cfg, hipStream_t s) {
   const int64_t np = n - tier_count_h[0];
   constexpr int kCap = 256 * 32;
   reorder_invert<<<grid_of(n, 256, kCap), 256, 0, s>>>(list, n, old2new);
@@ -309,22 +309,26 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
   for (int t = 1; t < kNumTiers; ++t) {
     const int64_t cnt = tier_count_h[t], first = tier_start_h[t];
     if (cnt <= 0) continue;
-    if (t == 1)
+    // the copy kernel takes rows up to G * K entries: the smallest that
+    // covers the tier's degree bound
+    const int64_t d = cfg.bound[t];
+    if (t == kNumTiers - 1) {
+      if (hub_chunks > 0) reorder_hub_rows<<<(unsigned)hub_chunks, 256, 0, s>>>(c, hub_chunk_start, cnt);
+    } else if (d <= 8) {
       reorder_rows<1, 256, 8><<<grid_of(cnt, 256, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t == 2)
+    } else if (d <= 16) {
       reorder_rows<8, 256, 2><<<grid_of(cnt, 32, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t == 3)
+    } else if (d <= 32) {
       reorder_rows<16, 256, 2><<<grid_of(cnt, 16, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t == 4)
+    } else if (d <= 64) {
       reorder_rows<32, 256, 2><<<grid_of(cnt, 8, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t == 5)
+    } else if (d <= 128) {
       reorder_rows<64, 256, 2><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t == 6)
+    } else if (d <= 512) {
       reorder_rows<64, 256, 8><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (t == 7)
+    } else {
       reorder_rows<256, 256, 8><<<grid_of(cnt, 1, kCap), 256, 0, s>>>(c, first, cnt);
-    else if (hub_chunks > 0)
-      reorder_hub_rows<<<(unsigned)hub_chunks, 256, 0, s>>>(c, hub_chunk_start, cnt);
+    }
   }
   if (np > 0)
     first_apply<<<grid_of(np, 256, 1024), 256, 0, s>>>(first_key, list, np, hub_rowsum, H, flags, lab, dn0,

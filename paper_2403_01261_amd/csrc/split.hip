@@ -206,12 +206,24 @@ __global__ __launch_bounds__(256) void split_root_min(int32_t *parent, const int
   }
 }
 
+// The root is looked up again here: split_root_min's store of the root into
+// parent[p] can be overwritten by another thread's path halving with an
+// intermediate ancestor, so parent[p] alone need not be the root.
 __global__ void split_out(const int32_t *__restrict__ parent, const int32_t *__restrict__ orig,
                           const int32_t *__restrict__ minorig, int64_t np, int64_t n, int32_t *out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
     const int32_t v = orig[p];
-    out[v] = p < np ? minorig[parent[p]] : v;
+    if (p < np) {
+      int32_t r = (int32_t)p, q = parent[p];
+      while (q != r) {  // read-only walk: no unions or writes happen any more
+        r = q;
+        q = parent[q];
+      }
+      out[v] = minorig[r];
+    } else {
+      out[v] = v;
+    }
   }
 }
 
@@ -300,7 +312,7 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
-                        hipStream_t s) {
+                        const TierConfig &cfg, hipStream_t s) {
   constexpr int kCap = 256 * 16;
   if (n > 0) {
     split_init<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
@@ -311,13 +323,16 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
   for (int t = 1; t < kNumTiers; ++t) {
     const int64_t cnt = tier_count_host[t], first = tier_start_host[t];
     if (cnt <= 0) continue;
-    if (t == 1)
+    // lanes per row follow the tier's degree bound (any kernel is correct
+    // for any degree; this only balances the work)
+    const int64_t d = cfg.bound[t];
+    if (d <= 8)
       split_hook_thread<<<grid_cap(cnt, 256, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
                                                                   dominant);
-    else if (t <= 3)
+    else if (d <= 32)
       split_hook_group<8><<<grid_cap(cnt, 32, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
                                                                    dominant);
-    else if (t <= 6)
+    else if (d <= 512)
       split_hook_group<64><<<grid_cap(cnt, 4, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
                                                                    dominant);
     else

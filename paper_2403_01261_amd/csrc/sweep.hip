@@ -350,22 +350,28 @@ int launch_lds(const SweepArgs &a, const int32_t *list, int64_t first, int64_t c
 
 }  // namespace
 
-hipError_t launch_sweep_tier(int tier, const SweepArgs &a, const int32_t *list, int64_t first,
+hipError_t launch_sweep_tier(int variant, const SweepArgs &a, const int32_t *list, int64_t first,
                              int64_t count, int *grid_out, hipStream_t s) {
   *grid_out = 0;
   if (count <= 0) return hipSuccess;
   int grid = 0;
-  switch (tier) {
-    case 1:
+  switch (variant) {
+    case 0:
       grid = grid_for(count, 256, kMaxTierGrid);
       sweep_thread<8><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
-    case 2: grid = launch_lds<8, 5, 256, 2>(a, list, first, count, s); break;
+    case 1: grid = launch_lds<8, 5, 256, 2>(a, list, first, count, s); break;
+    case 2: grid = launch_lds<4, 5, 256, 4>(a, list, first, count, s); break;
     case 3: grid = launch_lds<16, 6, 256, 2>(a, list, first, count, s); break;
-    case 4: grid = launch_lds<32, 7, 256, 2>(a, list, first, count, s); break;
-    case 5: grid = launch_lds<64, 8, 256, 2>(a, list, first, count, s); break;
-    case 6: grid = launch_lds<64, 10, 256, 8>(a, list, first, count, s); break;
-    case 7: grid = launch_lds<256, 12, 256, 8>(a, list, first, count, s); break;
+    case 4: grid = launch_lds<8, 6, 256, 4>(a, list, first, count, s); break;
+    case 5: grid = launch_lds<32, 7, 256, 2>(a, list, first, count, s); break;
+    case 6: grid = launch_lds<16, 7, 256, 4>(a, list, first, count, s); break;
+    case 7: grid = launch_lds<64, 8, 256, 2>(a, list, first, count, s); break;
+    case 8: grid = launch_lds<32, 8, 256, 4>(a, list, first, count, s); break;
+    case 9: grid = launch_lds<64, 10, 256, 8>(a, list, first, count, s); break;
+    case 10: grid = launch_lds<128, 10, 128, 4>(a, list, first, count, s); break;
+    case 11: grid = launch_lds<256, 12, 256, 8>(a, list, first, count, s); break;
+    case 12: grid = launch_lds<512, 12, 512, 4>(a, list, first, count, s); break;
     default:
       return hipErrorInvalidValue;
   }

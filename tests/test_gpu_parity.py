@@ -257,3 +257,57 @@ def test_disconnected_matches_alg4(gsl):
         g = graphs[0]
         off, cols, _ = to_device(g)
         gsl.gsl_disconnected(off, cols, torch.full((g.n,), g.n, dtype=torch.int32, device="cuda"))
+
+
+def _random_levels(rng, variants):
+    """A random valid tier table: increasing bounds, variants that hold them."""
+    while True:
+        bounds = sorted(int(x) for x in rng.choice([0, 2, 4, 8, 12, 16, 24, 32, 48, 64, 100, 128, 256, 512,
+                                                    1000, 2048], size=7))
+        bounds[0] = min(bounds[0], 8)
+        levels = []
+        for k, b in enumerate(bounds):
+            if k == 0:
+                levels.append((b, 0))
+                continue
+            ok = [v for v in range(1, len(variants)) if variants[v]["capacity"] >= b]
+            levels.append((b, int(rng.choice(ok))))
+        return levels
+
+
+def test_tier_choices_do_not_change_results(gsl):
+    """Permuted autotuner choices (degree bounds, kernel variants) give the
+    same labels, sweep counts and dN (the oracle's)."""
+    rng = np.random.default_rng(21)
+    variants = gsl.gsl_tier_variants()
+    graphs = [_tier_graph(5, True), workloads.make(2, small=True), workloads.make(1)]
+    try:
+        for trial in range(6):
+            levels = _random_levels(rng, variants)
+            gsl.gsl_set_tiers(levels)
+            assert gsl.gsl_get_tiers() == levels
+            for g in graphs:
+                assert_same(gsl, g, tag="tiers %s" % levels)
+    finally:
+        gsl.gsl_set_tiers(None)
+    with pytest.raises(gsl.GslError):
+        gsl.gsl_set_tiers([(8, 0), (40, 1), (64, 5), (128, 7), (256, 9), (512, 9), (2048, 11)])
+
+
+def test_autotuner_runs_and_caches(gsl, tmp_path, monkeypatch):
+    from paper_2403_01261_amd import tune
+    monkeypatch.setenv("GSL_TUNE_CACHE", str(tmp_path / "tiers.json"))
+    g = workloads.make(2, small=True)
+    off, cols, w = to_device(g)
+    probe = [(off, cols, w, torch.empty(g.n, dtype=torch.int32, device="cuda"))]
+    try:
+        res = tune.tune(probe, "test-probe", reps=1, passes=1)
+        assert tune.valid([tuple(x) for x in res["levels"]], gsl.gsl_tier_variants())
+        assert res["ms"] <= res["default_ms"]
+        say("tuned:", res)
+        again = tune.load_or_tune(probe, "test-probe")
+        assert again.get("cached") and again["levels"] == res["levels"]
+        lab, _ = run_gpu(gsl, g)
+        np.testing.assert_array_equal(lab, oracle.lpa(g).labels)
+    finally:
+        gsl.gsl_set_tiers(None)
