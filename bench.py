@@ -19,6 +19,9 @@ Extra objects on the JSON line:
                 bytes per launch from rocprofv3 counters (profiles/traffic.json),
                 null when absent or stale.
   cpu_baseline  the CPU oracle (single thread, untuned) timed on this host.
+  tiers         the degree tiers the timed runs used: by default the tier
+                autotuner (paper_2403_01261_amd/tune.py) runs first on the
+                same workload, outside every timed region.
 
 --workload 5 measures the batch of 4,096 planted graphs instead: graphs/s of
 the plain per-graph loop (one gsl_lpa call per graph), of one gsl_lpa_batched
@@ -51,11 +54,6 @@ WORKLOAD_TEXT = {
     5: "batch of 4,096 planted-partition graphs, N log-uniform in [200, 200,000], 5-500 blocks, "
        "mean degree U[8, 32] with 2 inter-block, unit weights",
 }
-# Kernel launched for each degree tier (as rocprofv3 names it, template
-# arguments in order).
-TIER_KERNEL = {1: "sweep_thread<8>", 2: "sweep_lds<8, 5, 256, 2>", 3: "sweep_lds<16, 6, 256, 2>",
-               4: "sweep_lds<32, 7, 256, 2>", 5: "sweep_lds<64, 8, 256, 2>",
-               6: "sweep_lds<64, 10, 256, 8>", 7: "sweep_lds<256, 12, 256, 8>", 8: "hub_insert"}
 NUM_TIERS = 9
 
 
@@ -199,6 +197,24 @@ def cpu_baseline(g, max_iters, tol):
             "iterations": int(r.iterations)}, r
 
 
+def run_tuner(args, run, probe):
+    """Degree tiers for the timed runs: the autotuner's choice for this
+    workload (tuning time is outside every timed region), or the defaults."""
+    import paper_2403_01261_amd as gsl
+    if args.tiers == "default":
+        gsl.gsl_set_tiers(None)
+        return {"source": "default", "levels": gsl.gsl_get_tiers()}
+    from paper_2403_01261_amd import tune
+    t0 = time.time()
+    res = tune.load_or_tune(run, probe, retune=args.tiers == "tune", reps=3, passes=2, log=log)
+    log("tiers tuned in %.1fs: %.3f ms -> %.3f ms, %s" % (time.time() - t0, res["default_ms"], res["ms"],
+                                                          res["levels"]))
+    return {"source": "autotuner (cached)" if res.get("cached") else "autotuner", "levels": res["levels"],
+            "probe": probe,
+            "probe_ms_default": round(res["default_ms"], 3), "probe_ms_tuned": round(res["ms"], 3),
+            "evaluations": res["evaluations"], "seconds": round(time.time() - t0, 1)}
+
+
 def roofline_from_stats(stats, weighted, steps, wname):
     """Dominant sweep kernel over a list of timing-mode stats dicts."""
     ms_tier = [sum(st["tiers"][t]["ms"] for st in stats) for t in range(NUM_TIERS)]
@@ -211,7 +227,10 @@ def roofline_from_stats(stats, weighted, steps, wname):
     bytes_total = tier_bytes(agg, weighted)
     avg_ms = ms_tier[dom] / max(launches, 1)
     achieved = bytes_total / max(launches, 1) / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
-    kernel = TIER_KERNEL[dom]
+    import paper_2403_01261_amd as gsl
+    variants = gsl.gsl_tier_variants()
+    levels = gsl.gsl_get_tiers()
+    kernel = "hub_insert" if dom == NUM_TIERS - 1 else gsl.variant_kernel_name(variants[levels[dom - 1][1]])
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel),
             "kernel": kernel, "tier": dom, "launches_per_step": launches // max(steps, 1),
@@ -255,6 +274,14 @@ def bench_batched(args):
         for k in range(count):
             gsl.gsl_lpa_ex(loc_off[k], loc_cols[k], None, mi, tol, out=views[k])
 
+    # tiers tuned on the batched call over a prefix of the batch (a prefix of
+    # a concatenated batch is itself one)
+    P = min(G, 512)
+    vb_p, eb_p = vb_d[:P + 1], eb_d[:P + 1]
+    off_p, cols_p = off[:vb[P] + 1], cols[:eb[P]]
+    out_p = out_batch[:vb[P]]
+    tiers = run_tuner(args, lambda: gsl.gsl_lpa_batched(vb_p, eb_p, off_p, cols_p, None, mi, tol, out=out_p),
+                      "%s prefix %d" % (workloads.describe(5, args.small), P))
     for k in range(args.warmup):
         gsl.gsl_lpa_batched(vb_d, eb_d, off, cols, None, mi, tol, out=out_batch)
         plain_loop(min(G, 64))
@@ -277,7 +304,7 @@ def bench_batched(args):
     log("batched: %.3f s/step, %.1f graphs/s" % (batch_s, G / batch_s))
     _, iters_b, st_b = gsl.gsl_lpa_batched(vb_d, eb_d, off, cols, None, mi, tol, out=out_batch, timing=True)
     if args.batched_only:
-        print(json.dumps({"batched_ms": 1000.0 * batch_s, "graphs_per_s": G / batch_s,
+        print(json.dumps({"batched_ms": 1000.0 * batch_s, "graphs_per_s": G / batch_s, "tiers": tiers,
                           "roofline": roofline_from_stats([st_b], False, 1, workloads.NAMES[5]),
                           "ms_sweep": st_b["ms_sweep"], "processed": st_b["processed"],
                           "changed": st_b["changed"], "ms_split": st_b["ms_split"]}), flush=True)
@@ -345,7 +372,7 @@ def bench_batched(args):
                       "ms": round(1000.0 * plain_s, 3)},
             "speedup_batched_vs_plain": round(plain_s / batch_s, 2),
             "served": served, "labels_identical_plain_batched": same_plain_batch,
-            "roofline": roofline_from_stats([st_b], False, 1, wname), "cpu_baseline": cpu}
+            "roofline": roofline_from_stats([st_b], False, 1, wname), "cpu_baseline": cpu, "tiers": tiers}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -359,6 +386,10 @@ def main(argv=None):
                     help="1 planted-10k, 2 rmat-s22, 3 road-24m, 4 rmat-s26, 5 batched-4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="the small variant of the workload (quick checks)")
+    ap.add_argument("--tiers", choices=("tune", "cached", "default"), default="tune",
+                    help="degree tiers of the timed runs: run the tier autotuner first (default), reuse its "
+                         "cached result for this device and workload (tuning only if there is none), or "
+                         "keep the library defaults")
     ap.add_argument("--batched-only", action="store_true",
                     help="workload 5: time only the batched call (profiling runs)")
     ap.add_argument("--pmc-copy", action="store_true",
@@ -405,6 +436,8 @@ def main(argv=None):
     mi, tol = workloads.MAX_ITERS, workloads.TOLERANCE
     torch.cuda.synchronize()
 
+    tiers = run_tuner(args, lambda: gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels),
+                      workloads.describe(args.workload, args.small))
     for k in range(args.warmup):
         gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels)
         log("warmup %d done" % k)
@@ -455,7 +488,7 @@ def main(argv=None):
             "config": {"workload": "%s: %s" % (wname, WORKLOAD_TEXT[args.workload]), "n": g.n,
                        "nnz": g.nnz, "max_iters": mi, "tolerance": tol,
                        "weights": "uint32 array" if weighted else "NULL (unit)"},
-            "roofline": roofline, "cpu_baseline": cpu, "phases": phases,
+            "roofline": roofline, "cpu_baseline": cpu, "phases": phases, "tiers": tiers,
             "context": "paper: 844M edges/s, sk-2005 3.8B edges, 2x Xeon Gold 6226R, 64 threads"}
     print(json.dumps(line), flush=True)
     return 0

@@ -9,8 +9,9 @@ on the result: every configuration gives the same labels.
 tune() runs a coordinate descent over the levels: for each level it tries the
 bounds {b/2, b, 2b} that keep the bounds non-decreasing, with every variant
 that can hold rows of that length, timing the production path (median wall
-time of a few gsl_lpa calls per probe graph) and keeping a change only when it
-is faster by more than the noise margin.  Two passes.  Results are cached as
+time of a few runs of the workload: gsl_lpa calls on probe graphs, or any
+callable, such as a batched call) and keeping a change only when it is faster
+by more than the noise margin.  Two passes.  Results are cached as
 JSON per device (and library version and probe), so later runs just load
 them: load_or_tune().
 """
@@ -112,32 +113,44 @@ def _write_cache(data: dict) -> None:
     os.replace(tmp, path)
 
 
-def time_levels(graphs, levels: Levels, reps: int = 5, max_iters: int = 20, tol: float = 0.05) -> float:
-    """Sum over the probe graphs of the median wall time (ms) of gsl_lpa."""
+def time_levels(run: Callable[[], None], levels: Levels, reps: int = 5) -> float:
+    """Median wall time (ms) of run() under the given tiers, after one
+    untimed run (which also builds the loop graph)."""
     import torch
 
-    from . import gsl_lpa_ex, gsl_set_tiers
+    from . import gsl_set_tiers
     gsl_set_tiers(levels)
-    total = 0.0
-    for off, cols, w, out in graphs:
-        gsl_lpa_ex(off, cols, w, max_iters, tol, out=out)  # builds the loop graph
-        ts = []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
+    run()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return statistics.median(ts)
+
+
+def graphs_runner(graphs, max_iters: int = 20, tol: float = 0.05) -> Callable[[], None]:
+    """run() over probe graphs: list of (offsets, cols, weights, out) tensors,
+    one gsl_lpa call each."""
+    from . import gsl_lpa_ex
+
+    def run():
+        for off, cols, w, out in graphs:
             gsl_lpa_ex(off, cols, w, max_iters, tol, out=out)
-            torch.cuda.synchronize()
-            ts.append((time.perf_counter() - t0) * 1e3)
-        total += statistics.median(ts)
-    return total
+    return run
 
 
-def tune(graphs, probe: str, reps: int = 5, passes: int = 2, log=None) -> dict:
-    """Tunes on `graphs` (list of (offsets, cols, weights, out) device
-    tensors), applies the result and caches it under `probe`."""
+def tune(run, probe: str, reps: int = 5, passes: int = 2, log=None) -> dict:
+    """Tunes the tiers for run() (a callable doing one unit of the workload
+    on the device, or a list of probe graphs, see graphs_runner), applies the
+    result and caches it under `probe`."""
     from . import gsl_set_tiers, gsl_tier_variants
+    if not callable(run):
+        run = graphs_runner(run)
     variants = gsl_tier_variants()
-    res = search(lambda lv: time_levels(graphs, lv, reps), variants, passes=passes, log=log)
+    res = search(lambda lv: time_levels(run, lv, reps), variants, passes=passes, log=log)
     gsl_set_tiers([tuple(x) for x in res["levels"]])
     res["when"] = time.strftime("%Y-%m-%dT%H:%M:%S")
     data = _read_cache()
@@ -146,7 +159,7 @@ def tune(graphs, probe: str, reps: int = 5, passes: int = 2, log=None) -> dict:
     return res
 
 
-def load_or_tune(graphs, probe: str, retune: bool = False, **kw) -> dict:
+def load_or_tune(run, probe: str, retune: bool = False, **kw) -> dict:
     """Applies the cached tiers for this device and probe, tuning first if
     there are none (or retune)."""
     from . import gsl_set_tiers, gsl_tier_variants
@@ -157,4 +170,4 @@ def load_or_tune(graphs, probe: str, retune: bool = False, **kw) -> dict:
             rec = dict(rec)
             rec["cached"] = True
             return rec
-    return tune(graphs, probe, **kw)
+    return tune(run, probe, **kw)
