@@ -117,13 +117,30 @@ def _read_counter_csv(d: str, counter: str):
 
 
 def _kernel_stats(d: str):
+    """Per kernel from a rocprofv3 kernel trace: all dispatches, and those
+    that did work.  A sweep kernel enqueued after its loop has converged
+    returns at once; dispatches shorter than 5% of the kernel's longest are
+    counted as such empty launches."""
     import csv
     import glob
-    paths = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    paths = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
     if not paths:
         return []
+    per = {}
     with open(paths[0]) as f:
-        return list(csv.DictReader(f))
+        for r in csv.DictReader(f):
+            dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            per.setdefault(r["Kernel_Name"], []).append(dt)
+    total = sum(sum(v) for v in per.values()) or 1
+    rows = []
+    for name, ds in per.items():
+        cut = 0.05 * max(ds)
+        work = [x for x in ds if x >= cut]
+        rows.append({"Name": name, "Calls": len(ds), "WorkCalls": len(work),
+                     "WorkAvgNs": sum(work) / len(work), "TotalDurationNs": sum(ds),
+                     "Percentage": 100.0 * sum(ds) / total})
+    rows.sort(key=lambda r: -r["TotalDurationNs"])
+    return rows
 
 
 def _short(name: str) -> str:
@@ -143,10 +160,14 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
         return max(copies) if copies else None
 
     cf, cw = calib(fetch), calib(write)
-    kf = [v for n, v in fetch.values() if kernel in _short(n)]
-    kw = [v for n, v in write.values() if kernel in _short(n)]
+    # only launches that did work: a sweep kernel enqueued after the loop
+    # converged reads next to nothing (cut at 5% of the largest reading)
+    kf = [v for n, v in fetch.values() if _short(n).startswith(kernel)]
+    kw = [v for n, v in write.values() if _short(n).startswith(kernel)]
     if not kf or not kw or not cf or not cw:
         raise SystemExit("counter runs lack the kernel %r or the calibration copy" % kernel)
+    kf = [v for v in kf if v >= 0.05 * max(kf)]
+    kw = [v for v in kw if v >= 0.05 * max(kw)]
     sf = COPY_BYTES / (cf * 1024.0)
     sw = COPY_BYTES / (cw * 1024.0)
     fetch_b = sum(kf) / len(kf) * 1024.0 * sf
@@ -168,7 +189,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
         f.write("\n")
     # Short text summary of the kernel trace next to it.
     stats = _kernel_stats(trace_dir)
-    md = os.path.join(ROOT, "profiles", "%s_%s.md" % (wname, kernel.split("<")[0]))
+    tag = kernel.replace("<", "-").replace(">", "").replace(", ", "-")
+    md = os.path.join(ROOT, "profiles", "%s_%s.md" % (wname, tag))
     with open(md, "w") as f:
         f.write("# %s on %s\n\n" % (kernel, wname))
         f.write("Commands (repository root, MI355X):\n\n")
@@ -178,11 +200,15 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
                 "(FETCH_SIZE / WRITE_SIZE scaled by a %d MiB copy: x%.4f / x%.4f).\n\n"
                 % (kernel, len(kf), fetch_b / 1e9, write_b / 1e9, COPY_BYTES >> 20, sf, sw))
         if stats:
-            f.write("| kernel | calls | avg us | total ms | % |\n|---|---|---|---|---|\n")
-            for r in stats[:20]:
-                f.write("| %s | %s | %.1f | %.2f | %.1f |\n" % (
-                    _short(r["Name"])[:70], r["Calls"], float(r["AverageNs"]) / 1e3,
-                    float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+            f.write("Kernel trace of the first command.  `calls` counts every dispatch; sweep kernels "
+                    "enqueued after the loop converged return at once, so `working calls` and their "
+                    "average count only dispatches of at least 5% of the kernel's longest.\n\n")
+            f.write("| kernel | calls | working calls | avg us (working) | total ms | % |\n"
+                    "|---|---|---|---|---|---|\n")
+            for r in stats[:24]:
+                f.write("| %s | %d | %d | %.1f | %.2f | %.1f |\n" % (
+                    _short(r["Name"])[:72], r["Calls"], r["WorkCalls"], r["WorkAvgNs"] / 1e3,
+                    r["TotalDurationNs"] / 1e6, r["Percentage"]))
     return rec[wname][kernel]
 
 
@@ -206,6 +232,7 @@ def run_tuner(args, run, probe):
         return {"source": "default", "levels": gsl.gsl_get_tiers()}
     from paper_2403_01261_amd import tune
     t0 = time.time()
+    log("tier autotuner: key %r, cache %s" % (tune.device_key(probe), tune.cache_path()))
     res = tune.load_or_tune(run, probe, retune=args.tiers == "tune", reps=3, passes=2, log=log)
     log("tiers tuned in %.1fs: %.3f ms -> %.3f ms, %s" % (time.time() - t0, res["default_ms"], res["ms"],
                                                           res["levels"]))

@@ -661,12 +661,12 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if (renumber) {
     if (o.split)
       HIP_TRY(gsl::launch_split(g_off, g_cols, np, C, s.parent, labels_out, nullptr, plan.tier_count,
-                                plan.tier_start, s.list, s.minorig, n, dominant_ptr(s), cfg, st));
+                                plan.tier_start, s.list, s.minorig, n, dominant_ptr(s), s.sigma, cfg, st));
     else
       HIP_TRY(gsl::launch_reorder_scatter(s.list, C, np, n, labels_out, st));
   } else if (o.split) {
     HIP_TRY(gsl::launch_split(offsets, cols, n, C, s.parent, labels_out, s.list, plan.tier_count,
-                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), cfg, st));
+                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
   }
   if (batch) {
     HIP_TRY(gsl::launch_localize(labels_out, batch->vtx_base, batch->graphs, n, st));
@@ -1130,7 +1130,7 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
   if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list,
-                            plan.tier_count, plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), cfg, st));
+                            plan.tier_count, plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
   HIP_TRY(hipStreamSynchronize(st));
   return GSL_OK;
 }
@@ -1157,7 +1157,7 @@ int gsl_disconnected(const int64_t *offsets, const int32_t *cols, int64_t n, con
   Counters plan = *s.ctr_host;
   // split labels into Cn, then piece counts per community in parent
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels, s.parent, s.Cn, s.list, plan.tier_count, plan.tier_start,
-                            nullptr, nullptr, n, dominant_ptr(s), cfg, st));
+                            nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
   unsigned long long *cnt = reinterpret_cast<unsigned long long *>(&s.ctr->split_changed);
   HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
   HIP_TRY(gsl::launch_disconnected(labels, s.Cn, n, s.parent, flags_out, cnt, st));

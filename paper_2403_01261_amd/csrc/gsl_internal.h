@@ -26,7 +26,7 @@ constexpr int kHubTier = 8;
 struct SweepVariant {
   int group, log2s, block, per_lane;
 };
-constexpr int kNumVariants = 13;
+constexpr int kNumVariants = 15;
 constexpr SweepVariant kVariants[kNumVariants] = {
     {1, 0, 256, 8},     // 0: thread per vertex, row in registers (d <= 8)
     {8, 5, 256, 2},     // 1: d <= 16
@@ -41,6 +41,8 @@ constexpr SweepVariant kVariants[kNumVariants] = {
     {128, 10, 128, 4},  // 10: d <= 512, one 128-thread workgroup per vertex
     {256, 12, 256, 8},  // 11: d <= 2048, one workgroup per vertex
     {512, 12, 512, 4},  // 12: d <= 2048, one 512-thread workgroup per vertex
+    {512, 13, 512, 8},  // 13: d <= 4096 (64 KB table)
+    {1024, 14, 1024, 8},  // 14: d <= 8192 (128 KB table, one workgroup per CU)
 };
 constexpr int64_t variant_capacity(int v) { return (int64_t)kVariants[v].group * kVariants[v].per_lane; }
 
@@ -239,7 +241,7 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
-                        const TierConfig &cfg, hipStream_t s);
+                        unsigned long long *cp, const TierConfig &cfg, hipStream_t s);
 // Alg. 4 from split labels comp (smallest id of each piece): pieces[c] =
 // number of pieces of community c, D[c] = pieces[c] > 1 (D may be NULL),
 // *count += number of such communities.

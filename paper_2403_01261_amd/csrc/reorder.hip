@@ -326,8 +326,10 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
       reorder_rows<64, 256, 2><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
     } else if (d <= 512) {
       reorder_rows<64, 256, 8><<<grid_of(cnt, 4, kCap), 256, 0, s>>>(c, first, cnt);
-    } else {
+    } else if (d <= 2048) {
       reorder_rows<256, 256, 8><<<grid_of(cnt, 1, kCap), 256, 0, s>>>(c, first, cnt);
+    } else {
+      reorder_rows<1024, 1024, 8><<<grid_of(cnt, 1, kCap), 1024, 0, s>>>(c, first, cnt);
     }
   }
   if (np > 0)

@@ -125,11 +125,31 @@ __global__ __launch_bounds__(kSamples) void split_sample(const int32_t *parent, 
   }
 }
 
+// After the flattening every vertex points at its root.  The second pass
+// reads, per row entry, one packed word cp[v] = (C[v] << 32) | root(v) taken
+// then (a single gather instead of two): an entry joins nothing new when v is
+// in another community or was already in u's component at that time
+// (components only grow, so a stale snapshot never skips a needed union).
+__global__ void split_pack(const int32_t *__restrict__ C, const int32_t *__restrict__ parent, int64_t n,
+                           unsigned long long *__restrict__ cp) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    cp[i] = ((unsigned long long)(uint32_t)C[i] << 32) | (uint32_t)parent[i];
+}
+
+__device__ __forceinline__ void hook_entry(int32_t *parent, const unsigned long long *__restrict__ cp,
+                                           int32_t u, uint32_t cu, uint32_t ru, int32_t v) {
+  if (v == u) return;
+  const unsigned long long x = cp[v];
+  if ((uint32_t)(x >> 32) != cu || (uint32_t)x == ru) return;
+  unite(parent, u, v);
+}
+
 // Second pass, one thread per vertex (short rows): entries from position
 // kLinkFirst on, for vertices not under the dominant root.
 __global__ __launch_bounds__(256) void split_hook_thread(const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ cols,
-                                                         const int32_t *__restrict__ C,
+                                                         const unsigned long long *__restrict__ cp,
                                                          int32_t *parent,
                                                          const int32_t *__restrict__ list,
                                                          int64_t first, int64_t count,
@@ -138,12 +158,10 @@ __global__ __launch_bounds__(256) void split_hook_thread(const int64_t *__restri
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
     const int32_t u = list ? list[first + idx] : (int32_t)(first + idx);
-    if (ld_parent(parent, u) == R) continue;
-    const int32_t cu = C[u];
-    for (int64_t p = off[u] + kLinkFirst; p < off[u + 1]; ++p) {
-      const int32_t v = cols[p];
-      if (v != u && C[v] == cu) unite(parent, u, v);
-    }
+    const unsigned long long xu = cp[u];
+    if ((int32_t)(uint32_t)xu == R) continue;
+    for (int64_t p = off[u] + kLinkFirst; p < off[u + 1]; ++p)
+      hook_entry(parent, cp, u, (uint32_t)(xu >> 32), (uint32_t)xu, cols[p]);
   }
 }
 
@@ -151,7 +169,7 @@ __global__ __launch_bounds__(256) void split_hook_thread(const int64_t *__restri
 template <int G>
 __global__ __launch_bounds__(256) void split_hook_group(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
-                                                        const int32_t *__restrict__ C,
+                                                        const unsigned long long *__restrict__ cp,
                                                         int32_t *parent,
                                                         const int32_t *__restrict__ list,
                                                         int64_t first, int64_t count,
@@ -161,13 +179,11 @@ __global__ __launch_bounds__(256) void split_hook_group(const int64_t *__restric
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   for (int64_t idx = (int64_t)blockIdx.x * GPB + g; idx < count; idx += (int64_t)gridDim.x * GPB) {
     const int32_t u = list ? list[first + idx] : (int32_t)(first + idx);
-    if (ld_parent(parent, u) == R) continue;  // uniform over the group
-    const int32_t cu = C[u];
+    const unsigned long long xu = cp[u];
+    if ((int32_t)(uint32_t)xu == R) continue;  // uniform over the group
     const int64_t e = off[u + 1];
-    for (int64_t p = off[u] + kLinkFirst + lane; p < e; p += G) {
-      const int32_t v = cols[p];
-      if (v != u && C[v] == cu) unite(parent, u, v);
-    }
+    for (int64_t p = off[u] + kLinkFirst + lane; p < e; p += G)
+      hook_entry(parent, cp, u, (uint32_t)(xu >> 32), (uint32_t)xu, cols[p]);
   }
 }
 
@@ -312,13 +328,14 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
-                        const TierConfig &cfg, hipStream_t s) {
+                        unsigned long long *cp, const TierConfig &cfg, hipStream_t s) {
   constexpr int kCap = 256 * 16;
   if (n > 0) {
     split_init<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
     split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n);
     split_flatten<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
     split_sample<<<1, kSamples, 0, s>>>(parent, n, dominant);
+    split_pack<<<grid_cap(n, 256, kCap), 256, 0, s>>>(C, parent, n, cp);
   }
   for (int t = 1; t < kNumTiers; ++t) {
     const int64_t cnt = tier_count_host[t], first = tier_start_host[t];
@@ -327,16 +344,16 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
     // for any degree; this only balances the work)
     const int64_t d = cfg.bound[t];
     if (d <= 8)
-      split_hook_thread<<<grid_cap(cnt, 256, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+      split_hook_thread<<<grid_cap(cnt, 256, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
                                                                   dominant);
     else if (d <= 32)
-      split_hook_group<8><<<grid_cap(cnt, 32, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+      split_hook_group<8><<<grid_cap(cnt, 32, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
                                                                    dominant);
     else if (d <= 512)
-      split_hook_group<64><<<grid_cap(cnt, 4, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+      split_hook_group<64><<<grid_cap(cnt, 4, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
                                                                    dominant);
     else
-      split_hook_group<256><<<grid_cap(cnt, 1, kCap), 256, 0, s>>>(off, cols, C, parent, list, first, cnt,
+      split_hook_group<256><<<grid_cap(cnt, 1, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
                                                                     dominant);
   }
   if (!orig) {

@@ -92,8 +92,11 @@ def device_key(probe: str) -> str:
     import torch
 
     from . import gsl_version
+    # architecture, compute units and memory size (the marketing name can be
+    # empty, e.g. under a profiler)
     p = torch.cuda.get_device_properties(0)
-    return "%s|%s|%s|%s" % (p.name, getattr(p, "gcnArchName", ""), gsl_version(), probe)
+    return "%s|%dcu|%dMiB|%s|%s" % (getattr(p, "gcnArchName", "") or p.name, p.multi_processor_count,
+                                     p.total_memory >> 20, gsl_version(), probe)
 
 
 def _read_cache() -> dict:
