@@ -417,6 +417,8 @@ def main(argv=None):
                     help="degree tiers of the timed runs: run the tier autotuner first (default), reuse its "
                          "cached result for this device and workload (tuning only if there is none), or "
                          "keep the library defaults")
+    ap.add_argument("--split-techniques", action="store_true",
+                    help="also time the split techniques (union-find, LP, LP with pruning) on the raw LPA labels")
     ap.add_argument("--batched-only", action="store_true",
                     help="workload 5: time only the batched call (profiling runs)")
     ap.add_argument("--pmc-copy", action="store_true",
@@ -500,6 +502,18 @@ def main(argv=None):
               "ms_per_step_with_events": round(sum(s["ms_total"] for s in stats) / len(stats), 3),
               "iterations": last["iterations"], "changed": last["changed"]}
 
+    split_cmp = None
+    if args.split_techniques:
+        raw, _ = gsl.gsl_lpa_ex(off, cols, w, mi, tol, split=False)
+        split_cmp = {}
+        ref = None
+        for tech in ("union-find", "lp", "lpp"):
+            out, rounds, ms = gsl.gsl_split_ex(off, cols, raw, tech)
+            same = True if ref is None else bool(torch.equal(out, ref))
+            ref = out if ref is None else ref
+            split_cmp[tech] = {"ms": round(ms, 3), "rounds": rounds, "same_labels": same}
+            log("split %s: %.3f ms, %d rounds" % (tech, ms, rounds))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
@@ -516,6 +530,7 @@ def main(argv=None):
                        "nnz": g.nnz, "max_iters": mi, "tolerance": tol,
                        "weights": "uint32 array" if weighted else "NULL (unit)"},
             "roofline": roofline, "cpu_baseline": cpu, "phases": phases, "tiers": tiers,
+            "split_techniques": split_cmp,
             "context": "paper: 844M edges/s, sk-2005 3.8B edges, 2x Xeon Gold 6226R, 64 threads"}
     print(json.dumps(line), flush=True)
     return 0

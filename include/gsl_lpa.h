@@ -63,6 +63,12 @@ typedef struct gsl_options {
                      the labels of high-degree vertices together; 2: never.
                      The copy costs nnz * 4 (+ nnz * 4 with weights) bytes of
                      device memory.  Results are identical either way. */
+  int32_t async_sweeps; /* nonzero: asynchronous sweeps as the paper's lpaMove
+                     runs them (Alg. 3) -- a changed label is written in
+                     place at once, so later vertices of the same sweep may
+                     see it.  Results then depend on scheduling (not bit-exact
+                     run to run); the split still leaves no disconnected
+                     community.  Default 0: synchronous sweeps. */
 } gsl_options;
 
 typedef struct gsl_stats {
@@ -117,7 +123,7 @@ int gsl_lpa(const int64_t *offsets, const int32_t *cols, const uint32_t *weights
             int32_t max_iters, double tolerance, int32_t *labels_out);
 
 /*
- * gsl_lpa_ex -- gsl_lpa with options (NULL: defaults {1, 1, 0, 0}) and optional
+ * gsl_lpa_ex -- gsl_lpa with options (NULL: defaults {1, 1, 0, 0, 0}) and optional
  * statistics (stats may be NULL; per-sweep arrays hold the first
  * GSL_STATS_MAX_ITERS sweeps).
  */
@@ -136,6 +142,28 @@ int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weig
  */
 int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels_in,
               int32_t *labels_out);
+
+/*
+ * gsl_split_ex -- gsl_split with a choice of technique.  All give the same
+ * labels (the smallest vertex id of each connected piece of each community);
+ * they differ in speed:
+ *   GSL_SPLIT_UNION_FIND  lock-free union-find in Afforest edge order (what
+ *                         gsl_split and gsl_lpa use);
+ *   GSL_SPLIT_LP          Alg. 1: min-label propagation over intra-community
+ *                         entries, every vertex every round, until no label
+ *                         changes (rounds grow with the pieces' diameter);
+ *   GSL_SPLIT_LPP         Alg. 1 with pruning: a vertex is processed only if
+ *                         a same-community neighbour changed in the previous
+ *                         round (frontier-driven, the GPU form of Alg. 2's
+ *                         BFS).
+ *   rounds_out : HOST, propagation rounds (1 for union-find); may be NULL
+ *   ms_out     : HOST, device time of the split in ms; may be NULL
+ */
+#define GSL_SPLIT_UNION_FIND 0
+#define GSL_SPLIT_LP 1
+#define GSL_SPLIT_LPP 2
+int gsl_split_ex(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels_in,
+                 int32_t *labels_out, int32_t technique, int32_t *rounds_out, float *ms_out);
 
 /*
  * gsl_disconnected -- the disconnected-community check (Alg. 4): a community

@@ -15,7 +15,8 @@ import os
 import torch
 
 __all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_batched", "gsl_lpa_graphs", "gsl_check_graph", "Context",
-           "gsl_split", "gsl_disconnected", "gsl_set_tiers", "gsl_get_tiers", "gsl_tier_variants",
+           "gsl_split", "gsl_split_ex", "gsl_disconnected", "gsl_set_tiers", "gsl_get_tiers",
+           "gsl_tier_variants",
            "gsl_modularity", "gsl_convergence_limit", "gsl_set_stream", "gsl_release", "gsl_version",
            "GslError", "LIB_PATH", "load"]
 
@@ -34,7 +35,7 @@ class GslError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("prune", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("layout", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("layout", ctypes.c_int32), ("async_sweeps", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -113,6 +114,8 @@ def load(path: str = None):
     lib.gsl_get_tiers.argtypes = [ctypes.POINTER(_Tier)]
     lib.gsl_tier_variant.argtypes = [ctypes.c_int32, ctypes.POINTER(_VariantInfo)]
     lib.gsl_disconnected.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP, ctypes.POINTER(ctypes.c_int64)]
+    lib.gsl_split_ex.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
     lib.gsl_split.argtypes = [_VP, _VP, ctypes.c_int64, _VP, _VP]
     lib.gsl_modularity.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]
     lib.gsl_convergence_limit.argtypes = [ctypes.c_int64, ctypes.c_double]
@@ -124,7 +127,7 @@ def load(path: str = None):
     for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream,
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
               lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected, lib.gsl_set_tiers,
-              lib.gsl_get_tiers, lib.gsl_tier_variant):
+              lib.gsl_get_tiers, lib.gsl_tier_variant, lib.gsl_split_ex):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -176,9 +179,10 @@ LAYOUTS = {"auto": 0, "renumbered": 1, "original": 2}
 
 
 def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=True, split=True,
-               timing=False, layout="auto", out=None):
+               timing=False, layout="auto", out=None, async_sweeps=False):
     """Returns (labels, stats dict).  layout: "auto", "renumbered" or
-    "original" (which vertex order the sweeps run in; results are identical)."""
+    "original" (which vertex order the sweeps run in; results are identical).
+    async_sweeps: the paper's in-place sweeps (results depend on timing)."""
     lib = _bind_stream()
     po, pc, pw, n = _graph_args(offsets, cols, weights)
     if out is None:
@@ -186,7 +190,7 @@ def gsl_lpa_ex(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=
     if out.numel() != n:
         raise ValueError("out must hold n labels")
     pl = _dev(out, (torch.int32,), "out")
-    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), LAYOUTS[layout])
+    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), LAYOUTS[layout], int(bool(async_sweeps)))
     st = _Stats()
     _check(lib.gsl_lpa_ex(po, pc, pw, n, int(max_iters), float(tolerance), ctypes.byref(opt),
                           ctypes.byref(st), pl))
@@ -223,7 +227,7 @@ def gsl_lpa_batched(vtx_base, edge_base, offsets, cols, weights=None, max_iters=
     if out.numel() != n:
         raise ValueError("out must hold N labels")
     iters = torch.zeros(max(G, 0), dtype=torch.int32, device=offsets.device)
-    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), 2)
+    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), 2, 0)
     st = _Stats()
     _check(lib.gsl_lpa_batched_ex(G, _dev(vtx_base, (torch.int64,), "vtx_base"),
                                   _dev(edge_base, (torch.int64,), "edge_base"), po, pc, pw,
@@ -273,7 +277,7 @@ def _run_graphs(lib, handle, graphs, max_iters, tolerance, prune, split, return_
     G = len(graphs)
     iters = (ctypes.c_int32 * max(G, 1))()
     status = (ctypes.c_int32 * max(G, 1))() if return_status else None
-    opt = _Options(int(bool(prune)), int(bool(split)), 0, 2)
+    opt = _Options(int(bool(prune)), int(bool(split)), 0, 2, 0)
     st = _Stats()
     _check(lib.gsl_lpa_graphs(handle, G, tab, int(max_iters), float(tolerance), ctypes.byref(opt),
                               ctypes.byref(st), iters, status))
@@ -337,6 +341,25 @@ def gsl_split(offsets, cols, labels_in, out=None):
         out = torch.empty(n, dtype=torch.int32, device=offsets.device)
     _check(lib.gsl_split(po, pc, n, pin, _dev(out, (torch.int32,), "out")))
     return out
+
+
+SPLIT_TECHNIQUES = {"union-find": 0, "lp": 1, "lpp": 2}
+
+
+def gsl_split_ex(offsets, cols, labels_in, technique="union-find", out=None):
+    """The split with a chosen technique ("union-find", "lp", "lpp"; same
+    labels).  Returns (labels, rounds, device ms)."""
+    lib = _bind_stream()
+    po, pc, _, n = _graph_args(offsets, cols, None)
+    if labels_in.numel() != n:
+        raise ValueError("labels_in must hold n labels")
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    rounds, ms = ctypes.c_int32(0), ctypes.c_float(0.0)
+    _check(lib.gsl_split_ex(po, pc, n, _dev(labels_in, (torch.int32,), "labels_in"),
+                            _dev(out, (torch.int32,), "out"), SPLIT_TECHNIQUES[technique], ctypes.byref(rounds),
+                            ctypes.byref(ms)))
+    return out, rounds.value, ms.value
 
 
 def gsl_disconnected(offsets, cols, labels, flags=True):

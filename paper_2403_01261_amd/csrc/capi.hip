@@ -437,7 +437,7 @@ struct Launch {
 int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *cols, const uint32_t *weights,
              int64_t n, int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
              int32_t *labels_out, const Batch *batch = nullptr) {
-  gsl_options o = {1, 1, 0, 0};
+  gsl_options o = {1, 1, 0, 0, 0};
   if (opt) o = *opt;
   if (stats) memset(stats, 0, sizeof(*stats));
   if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n = %lld out of range", (long long)n);
@@ -535,6 +535,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   a.overflow = reinterpret_cast<unsigned long long *>(&s.ctr->overflow);
   a.gid = batch ? s.gid : nullptr;
   a.gdone = batch ? s.gdone : nullptr;
+  a.inplace = o.async_sweeps ? 1 : 0;
   const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
 
   // Timing records (timing mode only).
@@ -603,7 +604,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     // The whole loop (max_iters sweeps) as one captured graph, reused while
     // every pointer and size it was built from stays the same.
     std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)n_sweep, (uint64_t)nnz, (uint64_t)max_iters,
-                                 (uint64_t)o.prune, (uint64_t)renumber,
+                                 (uint64_t)o.prune, (uint64_t)renumber, (uint64_t)a.inplace,
                                  (uint64_t)(uintptr_t)g_off, (uint64_t)(uintptr_t)g_cols,
                                  (uint64_t)(uintptr_t)g_w, (uint64_t)(uintptr_t)C, (uint64_t)(uintptr_t)g_list,
                                  (uint64_t)(uintptr_t)s.Cn, (uint64_t)(uintptr_t)s.chg,
@@ -875,7 +876,7 @@ int batched_concat(Scratch &s, hipStream_t st, int64_t G, const int64_t *vtx_bas
   if (bad) return fail(GSL_EINVAL, "vtx_base / edge_base must start at 0, end at the totals and not decrease");
   if ((rc = ensure_array(&s.gcols, &s.gcols_cap, nnz, "global cols"))) return rc;
   HIP_TRY(gsl::launch_globalize_cols(cols, edge_base, vtx_base, G, nnz, s.gcols, st));
-  gsl_options o = {1, 1, 0, 0};
+  gsl_options o = {1, 1, 0, 0, 0};
   if (opt) o = *opt;
   o.layout = 2;
   const Batch b{G, vtx_base, iters_out, nullptr, nullptr, nullptr, nullptr};
@@ -926,7 +927,7 @@ int batched_graphs(Scratch &s, hipStream_t st, int64_t G, const gsl_graph *graph
     if ((rc = ensure_array(&s.glab, &s.batch_glab_cap, N, "batch labels"))) return rc;
     HIP_TRY(gsl::launch_gather(s.gdesc, s.gvb, s.geb, G, N, nnz, s.goff, s.gcols, weighted ? s.gw : nullptr,
                                s.gflag, st));
-    gsl_options o = {1, 1, 0, 0};
+    gsl_options o = {1, 1, 0, 0, 0};
     if (opt) o = *opt;
     o.layout = 2;
     const Batch b{G, s.gvb, nullptr, iters_out, s.gdesc, s.gflag, flags.data()};
@@ -1132,6 +1133,60 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list,
                             plan.tier_count, plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return GSL_OK;
+}
+
+int gsl_split_ex(const int64_t *offsets, const int32_t *cols, int64_t n, const int32_t *labels_in,
+                 int32_t *labels_out, int32_t technique, int32_t *rounds_out, float *ms_out) {
+  if (rounds_out) *rounds_out = 0;
+  if (ms_out) *ms_out = 0.f;
+  if (technique < GSL_SPLIT_UNION_FIND || technique > GSL_SPLIT_LPP)
+    return fail(GSL_EINVAL, "unknown split technique %d", technique);
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GSL_EINVAL, "n out of range");
+  if (n == 0) return GSL_OK;
+  if (!offsets || !labels_in || !labels_out) return fail(GSL_EINVAL, "NULL argument");
+  if (labels_in == labels_out) return fail(GSL_EINVAL, "labels_out must not alias labels_in");
+  std::lock_guard<std::mutex> lk(g_mu);
+  const hipStream_t st = g_stream;
+  Scratch *sp = nullptr;
+  int rc = get_scratch(&sp);
+  if (rc) return rc;
+  Scratch &s = *sp;
+  int64_t nnz = 0;
+  if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
+  if ((rc = ensure_scratch(s, n, 1))) return rc;
+  if ((rc = check_labels(s, labels_in, n, st))) return rc;
+  const gsl::TierConfig cfg = current_tiers();
+  if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
+  Counters plan = *s.ctr_host;
+  HIP_TRY(hipEventRecord(s.ev[0], st));
+  int32_t rounds = 0;
+  if (technique == GSL_SPLIT_UNION_FIND) {
+    HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list, plan.tier_count,
+                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
+    rounds = 1;
+  } else {
+    const bool prune = technique == GSL_SPLIT_LPP;
+    uint8_t *f[2] = {prune ? s.act[0] : nullptr, prune ? s.act[1] : nullptr};
+    unsigned long long *chg = reinterpret_cast<unsigned long long *>(&s.ctr->split_changed);
+    HIP_TRY(gsl::launch_split_lp_init(labels_out, f[0], f[1], n, st));
+    for (;;) {
+      HIP_TRY(hipMemsetAsync(chg, 0, sizeof(*chg), st));
+      HIP_TRY(gsl::launch_split_lp_round(offsets, cols, n, labels_in, labels_out, s.list, plan.tier_count,
+                                         plan.tier_start, cfg, f[rounds & 1], f[(rounds + 1) & 1], chg, st));
+      ++rounds;
+      unsigned long long host = 0;
+      HIP_TRY(hipMemcpyAsync(&host, chg, sizeof(host), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (!host) break;
+      if (rounds > n + 1) return fail(GSL_EDEVICE, "label propagation split did not converge");
+    }
+  }
+  HIP_TRY(hipEventRecord(s.ev[1], st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (rounds_out) *rounds_out = rounds;
+  if (ms_out) *ms_out = elapsed(s.ev[0], s.ev[1]);
   return GSL_OK;
 }
 

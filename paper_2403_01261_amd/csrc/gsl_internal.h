@@ -118,6 +118,10 @@ struct SweepArgs {
   // for a single graph).
   const int32_t *gid;
   const uint8_t *gdone;
+  // 1: asynchronous sweeps -- a changed label is written straight into C,
+  // so vertices later in the same sweep may already read it (the paper's
+  // in-place lpaMove); results then depend on timing.
+  int32_t inplace;
 };
 
 // What a sweep kernel needs from the loop state.
@@ -242,6 +246,14 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
                         unsigned long long *cp, const TierConfig &cfg, hipStream_t s);
+// Alg. 1 split (min-label propagation on intra-community entries): labels
+// and flags initialised by launch_split_lp_init (f0 all set, f1 clear; NULL
+// flags for LP without pruning), then rounds until *changed stays 0.
+hipError_t launch_split_lp_init(int32_t *lab, uint8_t *f0, uint8_t *f1, int64_t n, hipStream_t s);
+hipError_t launch_split_lp_round(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
+                                 int32_t *lab, const int32_t *list, const int64_t *tier_count_host,
+                                 const int64_t *tier_start_host, const TierConfig &cfg, uint8_t *fin,
+                                 uint8_t *fout, unsigned long long *changed, hipStream_t s);
 // Alg. 4 from split labels comp (smallest id of each piece): pieces[c] =
 // number of pieces of community c, D[c] = pieces[c] > 1 (D may be NULL),
 // *count += number of such communities.

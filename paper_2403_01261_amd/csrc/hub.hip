@@ -329,7 +329,11 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
       if (best) {
         const uint32_t cstar = key_label(best);
         if (cstar != (uint32_t)a.C[v]) {
-          a.Cn[v] = (int32_t)cstar;
+          if (a.inplace)
+            __hip_atomic_store(const_cast<int32_t *>(a.C) + v, (int32_t)cstar, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          else
+            a.Cn[v] = (int32_t)cstar;
           a.chg[v] = 1;
           lc.dn = 1;
           if (sv.mark) lc.marked = lc.edges;  // hub_mark flags the whole row

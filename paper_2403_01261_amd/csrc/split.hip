@@ -266,14 +266,136 @@ int grid_cap(int64_t items, int per_block, int cap) {
 
 }  // namespace
 
-// Split on a graph whose vertices are grouped by tier (tier t occupies
-// [tier_start[t], tier_start[t] + tier_count[t]) of `list`, or of the ids
-// themselves when list is NULL).
-//  orig == NULL : the graph is in caller ids; out[i] = smallest id of i's piece.
-//  orig != NULL : the graph is the renumbered copy of its n non-isolated
-//                 vertices, orig[p] the caller id of vertex p (orig holds
-//                 n_total entries, isolated vertices last); out is written in
-//                 caller ids with the smallest caller id of each piece.
+namespace {
+
+// ---------------------------------------------------------------------------
+// The paper's other split technique (Alg. 1): min-label propagation restricted
+// to intra-community entries, repeated until no label changes.  Labels start
+// as the vertex ids and only decrease, so the fixed point -- every vertex
+// holds the smallest id of its piece -- is the union-find result; the rounds
+// update labels in place (a stale read only delays convergence).  With
+// pruning (LPP) a vertex is processed only if a neighbour of its community
+// changed in the previous round.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t ld_lab(const int32_t *p, int64_t i) {
+  return __hip_atomic_load(const_cast<int32_t *>(p) + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_lab(int32_t *p, int64_t i, int32_t v) {
+  __hip_atomic_store(p + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void split_lp_round(const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ cols,
+                                                      const int32_t *__restrict__ C, int32_t *lab,
+                                                      const int32_t *__restrict__ list, int64_t first,
+                                                      int64_t count, const uint8_t *__restrict__ fin,
+                                                      uint8_t *fout, unsigned long long *changed) {
+  constexpr int GPB = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  unsigned long long nchg = 0;
+  for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
+    const int64_t idx = base + g;
+    int32_t u = -1;
+    if (idx < count) {
+      u = list ? list[first + idx] : (int32_t)(first + idx);
+      if (fin && !fin[u]) u = -1;
+    }
+    int32_t m = 0x7fffffff, cu = 0;
+    int64_t b = 0, e = 0;
+    if (u >= 0) {
+      cu = C[u];
+      b = off[u];
+      e = off[u + 1];
+      m = ld_lab(lab, u);
+    }
+    const int32_t own = m;
+    for (int64_t p = b + lane; p < e; p += G) {
+      const int32_t v = cols[p];
+      if (C[v] == cu) {
+        const int32_t lv = ld_lab(lab, v);
+        m = lv < m ? lv : m;
+      }
+    }
+    constexpr int W = G < kWave ? G : kWave;
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) {
+      const int32_t y = __shfl_xor(m, o, W);
+      m = y < m ? y : m;
+    }
+    if constexpr (G > kWave) {  // the whole block is one group: combine its waves
+      __shared__ int32_t wmin[256 / kWave];
+      if (threadIdx.x % kWave == 0) wmin[threadIdx.x / kWave] = m;
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < 256 / kWave; ++w) m = wmin[w] < m ? wmin[w] : m;
+      __syncthreads();
+    }
+    if (u >= 0 && m < own) {
+      if (lane == 0) {
+        st_lab(lab, u, m);
+        nchg += 1;
+      }
+      if (fout)
+        for (int64_t p = b + lane; p < e; p += G) {
+          const int32_t v = cols[p];
+          if (C[v] == cu && !fout[v]) fout[v] = 1;
+        }
+    }
+  }
+  if (nchg) atomicAdd(changed, nchg);
+}
+
+__global__ void split_lp_init(int32_t *lab, uint8_t *f0, uint8_t *f1, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    lab[i] = (int32_t)i;
+    if (f0) f0[i] = 1;
+    if (f1) f1[i] = 0;
+  }
+}
+
+__global__ void clear_u8(uint8_t *p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_split_lp_init(int32_t *lab, uint8_t *f0, uint8_t *f1, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  split_lp_init<<<grid_cap(n, 256, 256 * 16), 256, 0, s>>>(lab, f0, f1, n);
+  return hipGetLastError();
+}
+
+// One round over every tier; fin / fout NULL for LP, the flag arrays of this
+// and the next round for LPP (fin is cleared afterwards for reuse).
+hipError_t launch_split_lp_round(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
+                                 int32_t *lab, const int32_t *list, const int64_t *tier_count_host,
+                                 const int64_t *tier_start_host, const TierConfig &cfg, uint8_t *fin,
+                                 uint8_t *fout, unsigned long long *changed, hipStream_t s) {
+  constexpr int kCap = 256 * 16;
+  for (int t = 1; t < kNumTiers; ++t) {
+    const int64_t cnt = tier_count_host[t], first = tier_start_host[t];
+    if (cnt <= 0) continue;
+    const int64_t d = cfg.bound[t];
+    if (d <= 8)
+      split_lp_round<1><<<grid_cap(cnt, 256, kCap), 256, 0, s>>>(off, cols, C, lab, list, first, cnt, fin, fout,
+                                                                  changed);
+    else if (d <= 32)
+      split_lp_round<8><<<grid_cap(cnt, 32, kCap), 256, 0, s>>>(off, cols, C, lab, list, first, cnt, fin, fout,
+                                                                 changed);
+    else if (d <= 512)
+      split_lp_round<64><<<grid_cap(cnt, 4, kCap), 256, 0, s>>>(off, cols, C, lab, list, first, cnt, fin, fout,
+                                                                 changed);
+    else
+      split_lp_round<256><<<grid_cap(cnt, 1, kCap), 256, 0, s>>>(off, cols, C, lab, list, first, cnt, fin,
+                                                                  fout, changed);
+  }
+  if (fin && n > 0) clear_u8<<<grid_cap(n, 256, kCap), 256, 0, s>>>(fin, n);
+  return hipGetLastError();
+}
+
 namespace {
 
 // Alg. 4 on top of the split: a community is disconnected iff it has more
@@ -324,6 +446,14 @@ hipError_t launch_disconnected(const int32_t *labels, const int32_t *comp, int64
   return hipGetLastError();
 }
 
+// Split on a graph whose vertices are grouped by tier (tier t occupies
+// [tier_start[t], tier_start[t] + tier_count[t]) of `list`, or of the ids
+// themselves when list is NULL).
+//  orig == NULL : the graph is in caller ids; out[i] = smallest id of i's piece.
+//  orig != NULL : the graph is the renumbered copy of its n non-isolated
+//                 vertices, orig[p] the caller id of vertex p (orig holds
+//                 n_total entries, isolated vertices last); out is written in
+//                 caller ids with the smallest caller id of each piece.
 hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,

@@ -26,7 +26,11 @@ namespace {
 
 __device__ __forceinline__ void record_change(const SweepArgs &a, int32_t v, uint32_t cstar,
                                               LocalCounts &lc) {
-  a.Cn[v] = (int32_t)cstar;
+  if (a.inplace)
+    __hip_atomic_store(const_cast<int32_t *>(a.C) + v, (int32_t)cstar, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  else
+    a.Cn[v] = (int32_t)cstar;
   a.chg[v] = 1;
   lc.dn += 1;
 }
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(256) void apply_changes(SweepArgs a, int32_t *__res
       for (int k = 0; k < 4; ++k)
         if ((word >> (8 * k)) & 0xffu) {
           const int64_t v = 4 * q + k;
-          C[v] = Cn[v];
+          if (!a.inplace) C[v] = Cn[v];
           if (gdn) {
             const int32_t g = a.gid[v];
             if (gq < 0) gq = g;

@@ -91,6 +91,11 @@ def test_batched_argument_errors_without_device_work():
     assert cnt.value == 0
     assert lib.gsl_disconnected(None, None, -3, None, None, None) == gsl.GSL_EINVAL
     assert lib.gsl_disconnected(None, None, 3, None, None, None) == gsl.GSL_EINVAL
+    r = ctypes.c_int32(9)
+    assert lib.gsl_split_ex(None, None, 0, None, None, 0, ctypes.byref(r), None) == gsl.GSL_OK
+    assert r.value == 0
+    assert lib.gsl_split_ex(None, None, 0, None, None, 7, None, None) == gsl.GSL_EINVAL
+    assert lib.gsl_split_ex(None, None, 4, None, None, 1, None, None) == gsl.GSL_EINVAL
 
 
 def _literal_limit(n, tol):

@@ -313,3 +313,50 @@ def test_autotuner_runs_and_caches(gsl, tmp_path, monkeypatch):
         np.testing.assert_array_equal(lab, oracle.lpa(g).labels)
     finally:
         gsl.gsl_set_tiers(None)
+
+
+def test_split_techniques_agree(gsl):
+    """Union-find, Alg. 1 LP and LP with pruning reach the same labels as the
+    oracle's Alg. 2 BFS; LP needs more rounds on long paths."""
+    rng = np.random.default_rng(31)
+    graphs = [workloads.make(1), workloads.make(2, small=True), workloads.make(3, small=True),
+              graphgen.cliques([3, 4, 5], perm=rng.permutation(12))]
+    for g in graphs:
+        off, cols, _ = to_device(g)
+        for labels in (oracle.lpa(g, split=False).labels,
+                       rng.integers(0, max(1, g.n // 50), size=g.n).astype(np.int32)):
+            expect = oracle.split_bfs(g, labels)
+            lab_d = torch.from_numpy(labels).cuda()
+            rounds = {}
+            for tech in ("union-find", "lp", "lpp"):
+                out, r, ms = gsl.gsl_split_ex(off, cols, lab_d, tech)
+                np.testing.assert_array_equal(out.cpu().numpy(), expect, err_msg="%s %s" % (g.name, tech))
+                rounds[tech] = r
+            say("%s: rounds %s" % (g.name, rounds))
+            assert rounds["union-find"] == 1 and rounds["lpp"] >= 1
+
+
+def test_async_sweeps_keep_the_invariants(gsl):
+    """Asynchronous (in-place) sweeps depend on scheduling, so they are held
+    to invariants: valid labels, no disconnected community after the split,
+    split-stable labels, modularity close to the synchronous result, disjoint
+    cliques recovered exactly."""
+    cl = graphgen.cliques([3, 4, 5, 6], perm=np.random.default_rng(2).permutation(18))
+    for g in (workloads.make(1), workloads.make(2, small=True), workloads.make(3, small=True), cl):
+        off, cols, w = to_device(g)
+        sync, _ = gsl.gsl_lpa_ex(off, cols, w)
+        for layout in ("original", "renumbered"):
+            lab, st = gsl.gsl_lpa_ex(off, cols, w, async_sweeps=True, layout=layout)
+            a = lab.cpu().numpy()
+            assert a.min() >= 0 and a.max() < g.n
+            assert 1 <= st["iterations"] <= 20
+            cnt, _ = gsl.gsl_disconnected(off, cols, lab)
+            assert cnt == 0, (g.name, layout)
+            np.testing.assert_array_equal(gsl.gsl_split(off, cols, lab).cpu().numpy(), a)
+            q_async = gsl.gsl_modularity(off, cols, w, lab)
+            q_sync = gsl.gsl_modularity(off, cols, w, sync)
+            say("%s %s: async %d sweeps Q %.4f, sync Q %.4f" % (g.name, layout, st["iterations"], q_async,
+                                                               q_sync))
+            assert q_async >= q_sync - 0.1, (g.name, layout, q_async, q_sync)
+            if g is cl:
+                np.testing.assert_array_equal(a, oracle.lpa(g).labels)
