@@ -114,6 +114,61 @@ __device__ __forceinline__ void global_table_add(unsigned long long *tab, int lo
   }
 }
 
+// Folds repeated labels of one wavefront before they reach the LDS table
+// (every lane of the wave must work on the same table).  Up to `rounds`
+// times: take the label of the first entry not yet folded, sum the weights of
+// every entry of the wave with that label into that entry and drop the
+// others.  On power-law graphs most entries of a long row carry a few labels
+// after the first sweeps; without this every one of them is an atomic on the
+// same LDS address.  Stops at the first label that occurs only once.
+// Weights of dropped entries stay in the caller's row sum.
+template <int K>
+__device__ __forceinline__ void wave_fold_labels(uint32_t (&lab)[K], uint32_t (&wt)[K], int rounds) {
+  const int wl = threadIdx.x % kWave;
+  bool led[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) led[k] = false;
+  for (int r = 0; r < rounds; ++r) {
+    int kk = -1, leader = -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const unsigned long long b = __ballot(lab[k] != kNoLabel && !led[k]);
+      if (kk < 0 && b) {
+        kk = k;
+        leader = __ffsll((long long)b) - 1;
+      }
+    }
+    if (kk < 0) return;  // uniform: nothing left in the wave
+    uint32_t mine = kNoLabel;
+#pragma unroll
+    for (int k = 0; k < K; ++k) mine = k == kk ? lab[k] : mine;
+    const uint32_t L = (uint32_t)__shfl((int)mine, leader);
+    int count = 0;
+    unsigned long long local = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const bool m = lab[k] == L;
+      count += __popcll(__ballot(m));
+      local += m ? wt[k] : 0u;
+    }
+    if (count < 2) return;  // uniform: the most common labels are gone
+    unsigned long long sum = local;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (lab[k] != L) continue;
+      if (wl == leader && k == kk) {
+        wt[k] = (uint32_t)sum;  // >= 2^32 only when the row sum overflows, which is reported
+        led[k] = true;
+      } else {
+        lab[k] = kNoLabel;
+        wt[k] = 0;
+      }
+    }
+  }
+}
+
 // Max over the G lanes of a group (G a power of two <= 64, groups aligned).
 template <int G>
 __device__ __forceinline__ unsigned long long group_max(unsigned long long x) {

@@ -192,6 +192,7 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
   unsigned long long rs = 0;
 #pragma unroll
   for (int q = 0; q < kHubK; ++q) rs += wt[q];
+  wave_fold_labels<kHubK>(lab, wt, 4);  // the whole chunk belongs to one hub
   __syncthreads();  // table and histogram initialised
   int slot[kHubK];
 #pragma unroll

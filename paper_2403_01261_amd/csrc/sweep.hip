@@ -24,6 +24,9 @@ namespace gsl {
 
 namespace {
 
+// Repeated labels folded per wave before the LDS inserts (wave_fold_labels).
+constexpr int kFoldRounds = 4;
+
 __device__ __forceinline__ void record_change(const SweepArgs &a, int32_t v, uint32_t cstar,
                                               LocalCounts &lc) {
   if (a.inplace)
@@ -189,6 +192,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
       unsigned long long rowsum = 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) rowsum += wt[k];
+      if constexpr (G >= kWave) wave_fold_labels<K>(lab, wt, kFoldRounds);  // one vertex per wave
 #pragma unroll
       for (int k = 0; k < K; ++k) slot[k] = lab[k] != kNoLabel ? lds_insert(T, log2s, lab[k], wt[k]) : -1;
       __syncthreads();
