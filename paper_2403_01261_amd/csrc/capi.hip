@@ -57,6 +57,7 @@ struct Scratch {
   uint8_t *act[2] = {nullptr, nullptr};
   int32_t *list = nullptr;
   int32_t *parent = nullptr;
+  int32_t *rep = nullptr;  // split: representative component per community
   int64_t *blk_counts = nullptr;
   unsigned long long *sigma = nullptr;
   unsigned long long *partials = nullptr;
@@ -141,6 +142,7 @@ void free_scratch(Scratch &s) {
   hipFree(s.act[1]);
   hipFree(s.list);
   hipFree(s.parent);
+  hipFree(s.rep);
   hipFree(s.blk_counts);
   hipFree(s.sigma);
   hipFree(s.partials);
@@ -202,15 +204,17 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
     hipFree(s.act[1]);
     hipFree(s.list);
     hipFree(s.parent);
+    hipFree(s.rep);
     hipFree(s.blk_counts);
     hipFree(s.sigma);
     s.Cn = nullptr; s.chg = nullptr; s.act[0] = s.act[1] = nullptr; s.list = nullptr;
-    s.parent = nullptr; s.blk_counts = nullptr; s.sigma = nullptr;
+    s.parent = nullptr; s.rep = nullptr; s.blk_counts = nullptr; s.sigma = nullptr;
     s.n_cap = -1;
     const int64_t flag_bytes = (cap + 3) / 4 * 4 + 16;
     if (dmalloc(&s.Cn, cap) != hipSuccess || dmalloc(&s.chg, flag_bytes) != hipSuccess ||
         dmalloc(&s.act[0], flag_bytes) != hipSuccess || dmalloc(&s.act[1], flag_bytes) != hipSuccess ||
         dmalloc(&s.list, cap) != hipSuccess || dmalloc(&s.parent, cap) != hipSuccess ||
+        dmalloc(&s.rep, cap) != hipSuccess ||
         dmalloc(&s.blk_counts, gsl::plan_blocks(cap) * gsl::kNumTiers) != hipSuccess ||
         dmalloc(&s.sigma, cap) != hipSuccess) {
       (void)hipGetLastError();
@@ -245,8 +249,6 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
   return GSL_OK;
 }
 
-// Device slot for the split's dominant-root hint (inside the counters block).
-int32_t *dominant_ptr(Scratch &s) { return reinterpret_cast<int32_t *>(&s.ctr->pad[0]); }
 
 unsigned long long *sweep_array(Counters *c, int which, int32_t max_iters) {
   auto *base = reinterpret_cast<unsigned long long *>(c + 1);
@@ -662,12 +664,12 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if (renumber) {
     if (o.split)
       HIP_TRY(gsl::launch_split(g_off, g_cols, np, C, s.parent, labels_out, nullptr, plan.tier_count,
-                                plan.tier_start, s.list, s.minorig, n, dominant_ptr(s), s.sigma, cfg, st));
+                                plan.tier_start, s.list, s.minorig, n, s.rep, s.sigma, cfg, st));
     else
       HIP_TRY(gsl::launch_reorder_scatter(s.list, C, np, n, labels_out, st));
   } else if (o.split) {
     HIP_TRY(gsl::launch_split(offsets, cols, n, C, s.parent, labels_out, s.list, plan.tier_count,
-                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
+                              plan.tier_start, nullptr, nullptr, n, s.rep, s.sigma, cfg, st));
   }
   if (batch) {
     HIP_TRY(gsl::launch_localize(labels_out, batch->vtx_base, batch->graphs, n, st));
@@ -1131,7 +1133,7 @@ int gsl_split(const int64_t *offsets, const int32_t *cols, int64_t n, const int3
   if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list,
-                            plan.tier_count, plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
+                            plan.tier_count, plan.tier_start, nullptr, nullptr, n, s.rep, s.sigma, cfg, st));
   HIP_TRY(hipStreamSynchronize(st));
   return GSL_OK;
 }
@@ -1164,7 +1166,7 @@ int gsl_split_ex(const int64_t *offsets, const int32_t *cols, int64_t n, const i
   int32_t rounds = 0;
   if (technique == GSL_SPLIT_UNION_FIND) {
     HIP_TRY(gsl::launch_split(offsets, cols, n, labels_in, s.parent, labels_out, s.list, plan.tier_count,
-                              plan.tier_start, nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
+                              plan.tier_start, nullptr, nullptr, n, s.rep, s.sigma, cfg, st));
     rounds = 1;
   } else {
     const bool prune = technique == GSL_SPLIT_LPP;
@@ -1212,7 +1214,7 @@ int gsl_disconnected(const int64_t *offsets, const int32_t *cols, int64_t n, con
   Counters plan = *s.ctr_host;
   // split labels into Cn, then piece counts per community in parent
   HIP_TRY(gsl::launch_split(offsets, cols, n, labels, s.parent, s.Cn, s.list, plan.tier_count, plan.tier_start,
-                            nullptr, nullptr, n, dominant_ptr(s), s.sigma, cfg, st));
+                            nullptr, nullptr, n, s.rep, s.sigma, cfg, st));
   unsigned long long *cnt = reinterpret_cast<unsigned long long *>(&s.ctr->split_changed);
   HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
   HIP_TRY(gsl::launch_disconnected(labels, s.Cn, n, s.parent, flags_out, cnt, st));

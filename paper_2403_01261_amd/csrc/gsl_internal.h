@@ -244,7 +244,7 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
 hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
-                        const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
+                        const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *rep,
                         unsigned long long *cp, const TierConfig &cfg, hipStream_t s);
 // Alg. 1 split (min-label propagation on intra-community entries): labels
 // and flags initialised by launch_split_lp_init (f0 all set, f1 clear; NULL

@@ -9,12 +9,16 @@
 // smallest vertex, whatever order the unions happen in.
 //
 // The edges are taken in the order of Afforest (Sutton, Ben-Nun & Barak,
-// IPDPS 2018): first the first two entries of every row, then a compression
-// and a sample of 1024 vertices that names the dominant root R, then the
-// remaining entries of every row whose vertex is not already under R.  A
-// skipped vertex u loses nothing: for an entry (u, v) with v outside R the
-// mirrored entry (v, u) is processed from v's side (the graph is symmetric),
-// either among v's first two entries or in the second pass.
+// IPDPS 2018): first the first two entries of every row (one round each,
+// flattened in between), then a representative component per community --
+// the root some vertex of the community points at after the flattening,
+// nearly always the community's big piece -- and then the remaining entries
+// of every row whose vertex is not in its community's representative.  A
+// skipped vertex u loses nothing: an entry (u, v) with v in another community
+// needs no union; with v skipped too, u and v are already in the same
+// component (a community has one representative); otherwise the mirrored
+// entry (v, u) is processed from v's side (the graph is symmetric), either
+// among v's first two entries or in the second pass.
 #include "device_common.h"
 #include "gsl_internal.h"
 
@@ -56,9 +60,12 @@ __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b) {
       a = b;
       b = t;
     }
-    int32_t expected = a;  // hang root a (larger) below b (smaller)
-    if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    // A fresh read first: when many threads hold the same stale pair of
+    // roots (hubs of a power-law graph), only the first needs the atomic.
+    int32_t expected = __hip_atomic_load(parent + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (expected == a &&  // hang root a (larger) below b (smaller)
+        __hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
       return;
     a = find_root(parent, expected);  // a was hooked meanwhile: continue above it
     b = find_root(parent, b);
@@ -72,23 +79,19 @@ __global__ void split_init(int32_t *parent, int64_t n) {
 }
 
 constexpr int kLinkFirst = 2;  // entries per row linked before the sample
-constexpr int kSamples = 1024;
 
-// First pass: the first kLinkFirst entries of every row.
+// First pass: entry q (< kLinkFirst) of every row, one launch per q with a
+// flattening in between, so the second round starts from flat trees.
 __global__ __launch_bounds__(256) void split_link_first(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
                                                         const int32_t *__restrict__ C,
-                                                        int32_t *parent, int64_t n) {
+                                                        int32_t *parent, int64_t n, int q) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     const int64_t b = off[u], e = off[u + 1];
-    const int32_t cu = C[u];
-#pragma unroll
-    for (int q = 0; q < kLinkFirst; ++q) {
-      if (b + q >= e) break;
-      const int32_t v = cols[b + q];
-      if (v != (int32_t)u && C[v] == cu) unite(parent, (int32_t)u, v);
-    }
+    if (b + q >= e) continue;
+    const int32_t v = cols[b + q];
+    if (v != (int32_t)u && C[v] == C[u]) unite(parent, (int32_t)u, v);
   }
 }
 
@@ -98,31 +101,12 @@ __global__ void split_flatten(int32_t *parent, int64_t n) {
     parent[i] = find_root(parent, (int32_t)i);
 }
 
-// Most frequent root among kSamples pseudo-random vertices (ties: smaller
-// root); one block of kSamples threads.  Only a hint: any value is correct.
-__global__ __launch_bounds__(kSamples) void split_sample(const int32_t *parent, int64_t n,
-                                                         int32_t *dominant) {
-  __shared__ int32_t val[kSamples];
-  __shared__ unsigned long long best[kSamples / kWave];
-  uint64_t z = (uint64_t)threadIdx.x * 0x9e3779b97f4a7c15ull + 0x632be59bd9b4e019ull;
-  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-  z ^= z >> 31;
-  val[threadIdx.x] = parent[(int64_t)(z % (uint64_t)n)];
-  __syncthreads();
-  const int32_t mine = val[threadIdx.x];
-  unsigned cnt = 0;
-  for (int k = 0; k < kSamples; ++k) cnt += val[k] == mine;
-  // key: count high, then the complement of the root (smaller root wins)
-  unsigned long long key = ((unsigned long long)cnt << 32) | (uint32_t)(~(uint32_t)mine);
-  key = group_max<kWave>(key);
-  if (threadIdx.x % kWave == 0) best[threadIdx.x / kWave] = key;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long m = 0;
-    for (int w = 0; w < kSamples / kWave; ++w) m = best[w] > m ? best[w] : m;
-    *dominant = (int32_t)~(uint32_t)m;
-  }
+// Representative component of every community: the root of some vertex of
+// the community (racing plain stores: any of them is a valid choice).
+__global__ void split_rep(const int32_t *__restrict__ C, const int32_t *__restrict__ parent, int64_t n,
+                          int32_t *__restrict__ rep) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) rep[C[i]] = parent[i];
 }
 
 // After the flattening every vertex points at its root.  The second pass
@@ -146,20 +130,19 @@ __device__ __forceinline__ void hook_entry(int32_t *parent, const unsigned long 
 }
 
 // Second pass, one thread per vertex (short rows): entries from position
-// kLinkFirst on, for vertices not under the dominant root.
+// kLinkFirst on, for vertices outside their community's representative.
 __global__ __launch_bounds__(256) void split_hook_thread(const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ cols,
                                                          const unsigned long long *__restrict__ cp,
                                                          int32_t *parent,
                                                          const int32_t *__restrict__ list,
                                                          int64_t first, int64_t count,
-                                                         const int32_t *__restrict__ dominant) {
-  const int32_t R = *dominant;
+                                                         const int32_t *__restrict__ rep) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
     const int32_t u = list ? list[first + idx] : (int32_t)(first + idx);
     const unsigned long long xu = cp[u];
-    if ((int32_t)(uint32_t)xu == R) continue;
+    if (rep[xu >> 32] == (int32_t)(uint32_t)xu) continue;
     for (int64_t p = off[u] + kLinkFirst; p < off[u + 1]; ++p)
       hook_entry(parent, cp, u, (uint32_t)(xu >> 32), (uint32_t)xu, cols[p]);
   }
@@ -173,14 +156,13 @@ __global__ __launch_bounds__(256) void split_hook_group(const int64_t *__restric
                                                         int32_t *parent,
                                                         const int32_t *__restrict__ list,
                                                         int64_t first, int64_t count,
-                                                        const int32_t *__restrict__ dominant) {
+                                                        const int32_t *__restrict__ rep) {
   constexpr int GPB = 256 / G;
-  const int32_t R = *dominant;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   for (int64_t idx = (int64_t)blockIdx.x * GPB + g; idx < count; idx += (int64_t)gridDim.x * GPB) {
     const int32_t u = list ? list[first + idx] : (int32_t)(first + idx);
     const unsigned long long xu = cp[u];
-    if ((int32_t)(uint32_t)xu == R) continue;  // uniform over the group
+    if (rep[xu >> 32] == (int32_t)(uint32_t)xu) continue;  // uniform over the group
     const int64_t e = off[u + 1];
     for (int64_t p = off[u] + kLinkFirst + lane; p < e; p += G)
       hook_entry(parent, cp, u, (uint32_t)(xu >> 32), (uint32_t)xu, cols[p]);
@@ -457,14 +439,16 @@ hipError_t launch_disconnected(const int32_t *labels, const int32_t *comp, int64
 hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
-                        const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *dominant,
+                        const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *rep,
                         unsigned long long *cp, const TierConfig &cfg, hipStream_t s) {
   constexpr int kCap = 256 * 16;
   if (n > 0) {
     split_init<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
-    split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n);
-    split_flatten<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
-    split_sample<<<1, kSamples, 0, s>>>(parent, n, dominant);
+    for (int q = 0; q < kLinkFirst; ++q) {
+      split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n, q);
+      split_flatten<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
+    }
+    split_rep<<<grid_cap(n, 256, kCap), 256, 0, s>>>(C, parent, n, rep);
     split_pack<<<grid_cap(n, 256, kCap), 256, 0, s>>>(C, parent, n, cp);
   }
   for (int t = 1; t < kNumTiers; ++t) {
@@ -475,16 +459,16 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
     const int64_t d = cfg.bound[t];
     if (d <= 8)
       split_hook_thread<<<grid_cap(cnt, 256, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
-                                                                  dominant);
+                                                                  rep);
     else if (d <= 32)
       split_hook_group<8><<<grid_cap(cnt, 32, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
-                                                                   dominant);
+                                                                   rep);
     else if (d <= 512)
       split_hook_group<64><<<grid_cap(cnt, 4, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
-                                                                   dominant);
+                                                                   rep);
     else
       split_hook_group<256><<<grid_cap(cnt, 1, kCap), 256, 0, s>>>(off, cols, cp, parent, list, first, cnt,
-                                                                    dominant);
+                                                                    rep);
   }
   if (!orig) {
     if (n > 0) split_compress<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, out, n);

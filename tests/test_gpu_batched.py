@@ -242,3 +242,24 @@ def test_malformed_graph_fails_alone(gsl):
     with pytest.raises(gsl.GslError):
         gsl.gsl_check_graph(dev[other][0], dev[other][1])
     gsl.gsl_check_graph(*to_device(graphs[big])[:2])
+
+
+def test_full_batch_matches_oracle_hash(gsl):
+    """The whole batch of 4,096 graphs (2.4B entries) in one call against the
+    oracle's per-graph results (hash of the labels in graph order, sweep count
+    of every graph)."""
+    import json
+    import os
+    from tests.gpu_util import graph_hash, labels_hash
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "workloads.json")
+    with open(path) as f:
+        gold = json.load(f).get("5")
+    if gold is None:
+        pytest.skip("batched workload not in the golden file")
+    b = workloads.make(5)
+    assert b.n == gold["n"] and b.nnz == gold["nnz"] and b.num_graphs == gold["graphs"]
+    assert graph_hash(b) == gold["graph_xxh128"]
+    say("batch: %d graphs, N=%d, nnz=%d" % (b.num_graphs, b.n, b.nnz))
+    labels, iters, _ = run_concat(gsl, b, gold["max_iters"], gold["tolerance"])
+    assert iters == gold["iterations"]
+    assert labels_hash(np.concatenate(labels)) == gold["labels_xxh128"]
