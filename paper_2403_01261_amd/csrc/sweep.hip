@@ -142,6 +142,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
   __shared__ unsigned long long red[NW];
   __shared__ unsigned long long red2[NW];
   __shared__ int32_t q[BLOCK];
+  __shared__ int64_t qb[BLOCK], qe[BLOCK];  // row bounds of the packed vertices
   __shared__ int wcnt[NW];
   SweepView sv;
   if (!sweep_view(a, sv)) return;
@@ -151,11 +152,17 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
   unsigned long long *T = tab + g * S;
   LocalCounts lc;
   for (int64_t w0 = (int64_t)blockIdx.x * win; w0 < count; w0 += (int64_t)gridDim.x * win) {
-    // pack the taken vertices of the window
+    // pack the taken vertices of the window with their row bounds (loaded
+    // here, all at once, instead of one dependent load per group round)
     int32_t u = -1;
+    int64_t ub = 0, ue = 0;
     if (threadIdx.x < win && w0 + threadIdx.x < count) {
       u = list ? list[first + w0 + threadIdx.x] : (int32_t)(first + w0 + threadIdx.x);
       if (!sweep_takes(a, sv, u)) u = -1;
+      if (u >= 0) {
+        ub = a.off[u];
+        ue = a.off[u + 1];
+      }
     }
     const unsigned long long m = __ballot(u >= 0);
     if (wl == 0) wcnt[wid] = __popcll(m);
@@ -166,15 +173,19 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
       pos += w < wid ? wcnt[w] : 0;
       total += wcnt[w];
     }
-    if (u >= 0) q[pos] = u;
+    if (u >= 0) {
+      q[pos] = u;
+      qb[pos] = ub;
+      qe[pos] = ue;
+    }
     __syncthreads();
     for (int r0 = 0; r0 < total; r0 += GPB) {
       const int32_t v = r0 + g < total ? q[r0 + g] : -1;
       int64_t b = 0, e = 0;
       int log2s = 1;
       if (v >= 0) {
-        b = a.off[v];
-        e = a.off[v + 1];
+        b = qb[r0 + g];
+        e = qe[r0 + g];
         log2s = table_log2(e - b, 1, LOG2S);
       }
       int32_t j[K];
