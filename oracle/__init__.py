@@ -7,6 +7,7 @@ into ``liboracle.so``); this module only marshals numpy arrays.
 
 Functions follow arXiv:2403.01261:
   lpa           Alg. 3 (synchronous sweeps, pruning, Eq. 2 label rule) + Alg. 2
+  lpa_f32       the same with fp32 weights summed in fp64
   split_bfs     Alg. 2
   split_lp      Alg. 1 (LP / LPP)
   modularity    Eq. 1 (second form)
@@ -42,6 +43,7 @@ _P32 = ctypes.POINTER(ctypes.c_int32)
 _PU32 = ctypes.POINTER(ctypes.c_uint32)
 _PU64 = ctypes.POINTER(ctypes.c_uint64)
 _PU8 = ctypes.POINTER(ctypes.c_uint8)
+_PF32 = ctypes.POINTER(ctypes.c_float)
 
 
 def _load():
@@ -57,6 +59,10 @@ def _load():
         lib.oracle_modularity.argtypes = [ctypes.c_int64, _P64, _P32, _PU32, _P32,
                                           ctypes.POINTER(ctypes.c_double), _PU64]
         lib.oracle_disconnected.argtypes = [ctypes.c_int64, _P64, _P32, _P32, _PU8, _P64]
+        lib.oracle_lpa_f32.argtypes = [ctypes.c_int64, _P64, _P32, _PF32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_int, _P32, ctypes.POINTER(ctypes.c_int32), _P64,
+                                       _P32, _P64]
+        lib.oracle_lpa_f32.restype = ctypes.c_int
         for f in (lib.oracle_lpa, lib.oracle_split_bfs, lib.oracle_split_lp, lib.oracle_modularity,
                   lib.oracle_disconnected):
             f.restype = ctypes.c_int
@@ -108,6 +114,23 @@ def lpa(g, max_iters=20, tolerance=0.05, prune=True, split=True, history=False) 
     it = iters.value
     return LpaResult(labels, it, dn[:it].copy(), None if hist is None else hist[:it].copy(),
                      proc[:it].copy())
+
+
+def lpa_f32(g, weights, max_iters=20, tolerance=0.05, prune=True, split=True) -> LpaResult:
+    """lpa with fp32 weights (float32 array, one per CSR entry; None = unit)
+    summed in fp64 in CSR entry order."""
+    off, cols, _ = _csr(g)
+    n = off.shape[0] - 1
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    labels = np.empty(n, dtype=np.int32)
+    iters = ctypes.c_int32(0)
+    dn = np.zeros(max(max_iters, 1), dtype=np.int64)
+    proc = np.zeros(max(max_iters, 1), dtype=np.int64)
+    _rc(_load().oracle_lpa_f32(n, _ptr(off, _P64), _ptr(cols, _P32), _ptr(w, _PF32), max_iters, float(tolerance),
+                               int(bool(prune)), int(bool(split)), _ptr(labels, _P32), ctypes.byref(iters),
+                               _ptr(dn, _P64), None, _ptr(proc, _P64)), "lpa_f32")
+    it = iters.value
+    return LpaResult(labels, it, dn[:it].copy(), None, proc[:it].copy())
 
 
 def split_bfs(g, labels) -> np.ndarray:

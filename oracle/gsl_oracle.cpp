@@ -10,6 +10,7 @@
 // arXiv:2403.01261):
 //   * oracle_lpa          -- Alg. 3 (lpa / lpaMove / scanCommunities) with the
 //                            label rule of Eq. 2, then the split of Alg. 2.
+//   * oracle_lpa_f32      -- the same with fp32 weights summed in fp64.
 //   * oracle_split_bfs    -- Alg. 2 (split disconnected communities by BFS).
 //   * oracle_split_lp     -- Alg. 1 (min-label LP, with or without pruning).
 //   * oracle_modularity   -- Eq. 1, second form.
@@ -68,20 +69,25 @@ bool valid_labels(int64_t n, const int32_t *lab) {
   return true;
 }
 
+// Weight of entry e: uint32 weights summed in 64-bit integers, or fp32
+// weights summed in fp64 (the paper's precision, Sec. 5.1.2); NULL weights
+// are 1.
 inline uint64_t weight_of(const uint32_t *w, int64_t e) { return w ? (uint64_t)w[e] : 1u; }
+inline double weight_of(const float *w, int64_t e) { return w ? (double)w[e] : 1.0; }
 
 // scanCommunities (Alg. 3): the per-vertex label -> summed weight table,
-// skipping self loops, as a sparse accumulator.  Returns the most weighted
-// label (smallest on ties) or -1 if the table is empty.
+// skipping self loops, as a sparse accumulator (sums in CSR entry order).
+// Returns the most weighted label (smallest on ties) or -1 if the table is
+// empty.
+template <class W, class Acc>
 struct Scanner {
-  std::vector<uint64_t> sum;
+  std::vector<Acc> sum;
   std::vector<int64_t> stamp;
   std::vector<int32_t> touched;
   int64_t epoch = 0;
   explicit Scanner(int64_t n) : sum((size_t)n, 0), stamp((size_t)n, -1) {}
 
-  int32_t best_label(int64_t i, const int64_t *off, const int32_t *cols, const uint32_t *w,
-                     const int32_t *C) {
+  int32_t best_label(int64_t i, const int64_t *off, const int32_t *cols, const W *w, const int32_t *C) {
     ++epoch;
     touched.clear();
     for (int64_t e = off[i]; e < off[i + 1]; ++e) {
@@ -96,9 +102,9 @@ struct Scanner {
       sum[(size_t)c] += weight_of(w, e);
     }
     int32_t best = -1;
-    uint64_t best_w = 0;
+    Acc best_w = 0;
     for (int32_t c : touched) {
-      const uint64_t s = sum[(size_t)c];
+      const Acc s = sum[(size_t)c];
       if (best < 0 || s > best_w || (s == best_w && c < best)) {
         best = c;
         best_w = s;
@@ -157,9 +163,14 @@ extern "C" {
 //   dn_hist         : int64[max_iters], dN of each performed sweep (may be NULL)
 //   history         : int32[max_iters * n], labels after each sweep (may be NULL)
 //   processed_hist  : int64[max_iters], vertices processed per sweep (may be NULL)
-int oracle_lpa(int64_t n, const int64_t *off, const int32_t *cols, const uint32_t *w,
-               int32_t max_iters, double tol, int prune, int split, int32_t *labels_out,
-               int32_t *iters_out, int64_t *dn_hist, int32_t *history, int64_t *processed_hist) {
+}  // extern "C"
+
+namespace {
+
+template <class W, class Acc>
+int lpa_impl(int64_t n, const int64_t *off, const int32_t *cols, const W *w, int32_t max_iters, double tol,
+             int prune, int split, int32_t *labels_out, int32_t *iters_out, int64_t *dn_hist,
+             int32_t *history, int64_t *processed_hist) {
   if (!valid_csr(n, off, cols) || max_iters < 0 || !(tol >= 0.0 && tol <= 1.0)) return -1;
   if (n > 0 && !labels_out) return -1;
   if (iters_out) *iters_out = 0;
@@ -168,7 +179,7 @@ int oracle_lpa(int64_t n, const int64_t *off, const int32_t *cols, const uint32_
   std::vector<int32_t> C((size_t)n), Cn((size_t)n);
   for (int64_t i = 0; i < n; ++i) C[(size_t)i] = (int32_t)i;
   std::vector<uint8_t> unprocessed((size_t)n, 1), next_unprocessed((size_t)n, 0);
-  Scanner scan(n);
+  Scanner<W, Acc> scan(n);
   int32_t l = 0;
   for (; l < max_iters;) {
     // lpaMove: every unprocessed vertex reads C (the previous sweep's labels);
@@ -199,6 +210,29 @@ int oracle_lpa(int64_t n, const int64_t *off, const int32_t *cols, const uint32_
   else
     memcpy(labels_out, C.data(), (size_t)n * sizeof(int32_t));
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_lpa(int64_t n, const int64_t *off, const int32_t *cols, const uint32_t *w, int32_t max_iters,
+               double tol, int prune, int split, int32_t *labels_out, int32_t *iters_out, int64_t *dn_hist,
+               int32_t *history, int64_t *processed_hist) {
+  return lpa_impl<uint32_t, uint64_t>(n, off, cols, w, max_iters, tol, prune, split, labels_out, iters_out,
+                                      dn_hist, history, processed_hist);
+}
+
+// The same with fp32 weights summed in fp64 in CSR entry order (the paper's
+// precision).  Weights must be finite and >= 0.
+int oracle_lpa_f32(int64_t n, const int64_t *off, const int32_t *cols, const float *w, int32_t max_iters,
+                   double tol, int prune, int split, int32_t *labels_out, int32_t *iters_out, int64_t *dn_hist,
+                   int32_t *history, int64_t *processed_hist) {
+  if (w && n > 0 && off)
+    for (int64_t e = 0; e < off[n]; ++e)
+      if (!(w[e] >= 0.0f) || w[e] > 3.4e38f) return -1;
+  return lpa_impl<float, double>(n, off, cols, w, max_iters, tol, prune, split, labels_out, iters_out, dn_hist,
+                                 history, processed_hist);
 }
 
 // Alg. 2 (splitDisconnectedBfs).

@@ -32,9 +32,10 @@ def label_weights(W: np.ndarray, X: np.ndarray, L: np.ndarray):
     entries excluded."""
     B, n, _ = W.shape
     eye = np.eye(n, dtype=bool)[None]
-    Wn = np.where(eye, 0, W).astype(np.int64)
+    dt = np.float64 if np.issubdtype(W.dtype, np.floating) else np.int64  # float weights: fp64 sums
+    Wn = np.where(eye, 0, W).astype(dt)
     Xn = X & ~eye
-    onehot = (L[:, :, None] == np.arange(n)[None, None, :]).astype(np.int64)  # [B, j, c]
+    onehot = (L[:, :, None] == np.arange(n)[None, None, :]).astype(dt)  # [B, j, c]
     S = Wn @ onehot                       # [B, i, c] summed weight per label
     cand = (Xn.astype(np.int64) @ onehot) > 0
     return S, cand

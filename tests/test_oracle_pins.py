@@ -286,3 +286,57 @@ def test_oracle_rejects_bad_input():
     g = graphgen.from_undirected(3, [(0, 1)])
     with pytest.raises(ValueError):
         oracle.split_bfs(g, np.array([0, 1, 3], dtype=np.int32))
+
+
+# ---- fp32 weights summed in fp64 (the paper's precision) ----
+
+def test_f32_integer_weights_reduce_to_the_integer_oracle():
+    rng = np.random.default_rng(41)
+    for trial in range(40):
+        n = int(rng.integers(2, 300))
+        g = graphgen.planted(n, max(1, n // 20), 0.2, n, 100 + trial, wmin=1, wmax=50)
+        a = oracle.lpa(g, 20, 0.05)
+        b = oracle.lpa_f32(g, g.weights.astype(np.float32), 20, 0.05)
+        assert a.iterations == b.iterations
+        np.testing.assert_array_equal(a.labels, b.labels)
+        np.testing.assert_array_equal(a.dn, b.dn)
+
+
+def test_f32_brute_force_dyadic_weights():
+    """Every graph on 5 vertices with random dyadic weights k/64 (every partial
+    sum exact in fp64, so summation order cannot matter) against the dense
+    fp64 brute force, sweep by sweep."""
+    rng = np.random.default_rng(42)
+    A = brute.all_graphs(5)
+    Wd = rng.integers(1, 200, size=A.shape) / 64.0
+    Wd = np.triu(Wd, 1)
+    Wd = Wd + np.transpose(Wd, (0, 2, 1))
+    W = np.where(A, Wd, 0.0)
+    L, iters, dns, _ = brute.lpa(W, A, 20, 0.2)
+    for b in range(A.shape[0]):
+        r, c = np.nonzero(A[b])
+        g = graphgen.from_entries(5, r, c)
+        w = W[b][r, c].astype(np.float32)
+        res = oracle.lpa_f32(g, w, 20, 0.2, split=False)
+        assert res.iterations == iters[b], b
+        np.testing.assert_array_equal(res.labels, L[b], err_msg="graph %d" % b)
+
+
+def test_f32_sums_are_fp64_not_fp32():
+    """Row of vertex 0: label 2 twice (1.0 and 2^-25), label 1 once (1.0).  In
+    fp64 label 2 weighs 1 + 2^-25 and wins; summed in fp32 it would tie at 1.0
+    and the smaller label 1 would win."""
+    g = graphgen.from_entries(3, [0, 0, 0, 1, 2, 2], [2, 2, 1, 0, 0, 0])
+    w = np.array([1.0, 2.0 ** -25, 1.0, 1.0, 1.0, 2.0 ** -25], dtype=np.float32)
+    r = oracle.lpa_f32(g, w, 1, 0.0, split=False)
+    assert r.labels[0] == 2
+    assert np.float32(1.0) + np.float32(2.0 ** -25) == np.float32(1.0)  # the fp32 tie it avoids
+
+
+def test_f32_rejects_negative_and_nan_weights():
+    g = graphgen.from_undirected(3, [(0, 1), (1, 2)])
+    for bad in (-1.0, float("nan"), float("inf")):
+        w = np.ones(g.nnz, dtype=np.float32)
+        w[1] = bad
+        with pytest.raises(ValueError):
+            oracle.lpa_f32(g, w)
