@@ -212,10 +212,10 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
     return rec[wname][kernel]
 
 
-def cpu_baseline(g, max_iters, tol):
+def cpu_baseline(g, max_iters, tol, w32=None):
     import oracle
     t0 = time.perf_counter()
-    r = oracle.lpa(g, max_iters, tol)
+    r = oracle.lpa(g, max_iters, tol) if w32 is None else oracle.lpa_f32(g, w32, max_iters, tol)
     dt = time.perf_counter() - t0
     return {"value": g.nnz / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": "one full oracle GSL-LPA run (sweeps + split) of the whole workload, "
@@ -417,6 +417,8 @@ def main(argv=None):
                     help="degree tiers of the timed runs: run the tier autotuner first (default), reuse its "
                          "cached result for this device and workload (tuning only if there is none), or "
                          "keep the library defaults")
+    ap.add_argument("--weights-f32", action="store_true",
+                    help="pass the workload's weights as fp32 values (summed in fp64, gsl_lpa_f32)")
     ap.add_argument("--split-techniques", action="store_true",
                     help="also time the split techniques (union-find, LP, LP with pruning) on the raw LPA labels")
     ap.add_argument("--batched-only", action="store_true",
@@ -457,23 +459,29 @@ def main(argv=None):
     g = workloads.make(args.workload, small=args.small)
     log("generated %s: n=%d nnz=%d in %.1fs" % (workloads.NAMES[args.workload], g.n, g.nnz,
                                                  time.time() - t0))
-    weighted = g.weights is not None
+    weighted = g.weights is not None or args.weights_f32
     off = torch.from_numpy(g.offsets).to(dev)
     cols = torch.from_numpy(g.cols).to(dev)
-    w = torch.from_numpy(g.weights.view(np.int32)).to(dev) if weighted else None
+    if args.weights_f32:
+        wsrc = g.weights if g.weights is not None else np.ones(g.nnz, dtype=np.uint32)
+        w = torch.from_numpy(wsrc.astype(np.float32)).to(dev)
+    else:
+        w = torch.from_numpy(g.weights.view(np.int32)).to(dev) if g.weights is not None else None
+    lpa_call = gsl.gsl_lpa_f32 if args.weights_f32 else gsl.gsl_lpa_ex
     labels = torch.empty(g.n, dtype=torch.int32, device=dev)
     mi, tol = workloads.MAX_ITERS, workloads.TOLERANCE
     torch.cuda.synchronize()
 
-    tiers = run_tuner(args, lambda: gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels),
-                      workloads.describe(args.workload, args.small))
+    tiers = (run_tuner(args, lambda: lpa_call(off, cols, w, mi, tol, out=labels),
+                       workloads.describe(args.workload, args.small))
+             if not args.weights_f32 else {"source": "default (fp32 weights use the default tiers)"})
     for k in range(args.warmup):
-        gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels)
+        lpa_call(off, cols, w, mi, tol, out=labels)
         log("warmup %d done" % k)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
-        gsl.gsl_lpa_ex(off, cols, w, mi, tol, out=labels)
+        lpa_call(off, cols, w, mi, tol, out=labels)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1000.0 * elapsed / max(args.steps, 1)
@@ -481,7 +489,7 @@ def main(argv=None):
     log("timed %d steps: %.3f ms/step, %.3g edges/s" % (args.steps, ms_per_step, value))
     stats = []
     for k in range(args.steps):
-        _, st = gsl.gsl_lpa_ex(off, cols, w, mi, tol, timing=True, out=labels)
+        _, st = lpa_call(off, cols, w, mi, tol, timing=True, out=labels)
         stats.append(st)
     log("event pass: %.3f ms/step with per-launch events" % (sum(s["ms_total"] for s in stats) / len(stats)))
 
@@ -504,7 +512,7 @@ def main(argv=None):
 
     split_cmp = None
     if args.split_techniques:
-        raw, _ = gsl.gsl_lpa_ex(off, cols, w, mi, tol, split=False)
+        raw, _ = lpa_call(off, cols, w, mi, tol, split=False)
         split_cmp = {}
         ref = None
         for tech in ("union-find", "lp", "lpp"):
@@ -517,7 +525,7 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        cpu, ref = cpu_baseline(g, mi, tol)
+        cpu, ref = cpu_baseline(g, mi, tol, w.cpu().numpy() if args.weights_f32 else None)
         got = labels.cpu().numpy()
         cpu["labels_match_gpu"] = bool(np.array_equal(got, ref.labels))
         log("oracle: %.3g edges/s, labels match: %s" % (cpu["value"], cpu["labels_match_gpu"]))
@@ -525,10 +533,11 @@ def main(argv=None):
     line = {"metric": "edges/s (|E|/time) on 1 MI355X + % HBM peak", "value": value,
             "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "vs_baseline": None, "dtype": "f64" if args.weights_f32 else "u32", "data": "synthetic",
             "config": {"workload": "%s: %s" % (wname, WORKLOAD_TEXT[args.workload]), "n": g.n,
                        "nnz": g.nnz, "max_iters": mi, "tolerance": tol,
-                       "weights": "uint32 array" if weighted else "NULL (unit)"},
+                       "weights": ("fp32 array, fp64 sums" if args.weights_f32 else
+                                   "uint32 array" if weighted else "NULL (unit)")},
             "roofline": roofline, "cpu_baseline": cpu, "phases": phases, "tiers": tiers,
             "split_techniques": split_cmp,
             "context": "paper: 844M edges/s, sk-2005 3.8B edges, 2x Xeon Gold 6226R, 64 threads"}

@@ -132,6 +132,21 @@ int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weig
                int32_t *labels_out);
 
 /*
+ * gsl_lpa_f32 -- gsl_lpa_ex with fp32 weights summed in fp64, the paper's
+ * precision (Sec. 5.1.2).  weights: float[nnz] DEVICE array, every value
+ * finite and >= 0 (else GSL_EINVAL), or NULL (unit weights, identical to
+ * gsl_lpa_ex).  The label rule is unchanged: largest summed weight, smallest
+ * label on ties.  Sums are formed with atomics in an order that varies, so a
+ * sum may differ in its last bits from the entry-order sum when weights span
+ * more than 2^29 in magnitude; only exact ties can then resolve differently
+ * (results are bit-exact whenever every partial sum is exact in fp64, e.g.
+ * weights that are multiples of a common power of two).  The degree tiers are
+ * the defaults (gsl_set_tiers does not apply).
+ */
+int gsl_lpa_f32(const int64_t *offsets, const int32_t *cols, const float *weights, int64_t n, int32_t max_iters,
+                double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *labels_out);
+
+/*
  * gsl_split -- the split pass alone (Alg. 2; Alg. 1 reaches the same fixed
  * point): labels_out[i] = the smallest vertex id v such that v and i are joined
  * by a path whose vertices all carry label labels_in[i].

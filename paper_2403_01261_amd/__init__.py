@@ -14,7 +14,7 @@ import os
 
 import torch
 
-__all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_batched", "gsl_lpa_graphs", "gsl_check_graph", "Context",
+__all__ = ["gsl_lpa", "gsl_lpa_ex", "gsl_lpa_f32", "gsl_lpa_batched", "gsl_lpa_graphs", "gsl_check_graph", "Context",
            "gsl_split", "gsl_split_ex", "gsl_disconnected", "gsl_set_tiers", "gsl_get_tiers",
            "gsl_tier_variants",
            "gsl_modularity", "gsl_convergence_limit", "gsl_set_stream", "gsl_release", "gsl_version",
@@ -110,6 +110,8 @@ def load(path: str = None):
                                    ctypes.c_double, ctypes.POINTER(_Options), ctypes.POINTER(_Stats),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.gsl_check_graph.argtypes = [_VP, _VP, ctypes.c_int64]
+    lib.gsl_lpa_f32.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                ctypes.POINTER(_Options), ctypes.POINTER(_Stats), _VP]
     lib.gsl_set_tiers.argtypes = [ctypes.POINTER(_Tier)]
     lib.gsl_get_tiers.argtypes = [ctypes.POINTER(_Tier)]
     lib.gsl_tier_variant.argtypes = [ctypes.c_int32, ctypes.POINTER(_VariantInfo)]
@@ -127,7 +129,7 @@ def load(path: str = None):
     for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream,
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
               lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected, lib.gsl_set_tiers,
-              lib.gsl_get_tiers, lib.gsl_tier_variant, lib.gsl_split_ex):
+              lib.gsl_get_tiers, lib.gsl_tier_variant, lib.gsl_split_ex, lib.gsl_lpa_f32):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -211,6 +213,23 @@ def _stats_dict(st):
                        "changed": st.tier_changed[t], "marked": st.tier_marked[t],
                        "sparse_launches": st.tier_sparse[t], "ms": st.ms_tier[t]}
                       for t in range(STATS_TIERS)]}
+
+
+def gsl_lpa_f32(offsets, cols, weights=None, max_iters=20, tolerance=0.05, prune=True, split=True, timing=False,
+                layout="auto", out=None, async_sweeps=False):
+    """gsl_lpa_ex with float32 weights summed in fp64.  Returns (labels, stats)."""
+    lib = _bind_stream()
+    po, pc, _, n = _graph_args(offsets, cols, None)
+    pw = _dev(weights, (torch.float32,), "weights", allow_none=True)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    if out.numel() != n:
+        raise ValueError("out must hold n labels")
+    opt = _Options(int(bool(prune)), int(bool(split)), int(bool(timing)), LAYOUTS[layout], int(bool(async_sweeps)))
+    st = _Stats()
+    _check(lib.gsl_lpa_f32(po, pc, pw, n, int(max_iters), float(tolerance), ctypes.byref(opt), ctypes.byref(st),
+                           _dev(out, (torch.int32,), "out")))
+    return out, _stats_dict(st)
 
 
 def gsl_lpa_batched(vtx_base, edge_base, offsets, cols, weights=None, max_iters=20, tolerance=0.05,

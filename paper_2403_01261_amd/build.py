@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgsl_lpa.so")
-SOURCES = ["capi.hip", "plan.hip", "sweep.hip", "hub.hip", "reorder.hip", "split.hip", "modularity.hip", "batch.hip"]
+SOURCES = ["capi.hip", "plan.hip", "sweep.hip", "hub.hip", "reorder.hip", "split.hip", "modularity.hip", "batch.hip", "sweep_f32.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -102,6 +102,10 @@ struct Scratch {
   gsl::GraphDesc *gdesc = nullptr;
   unsigned long long *gbad = nullptr;
   uint32_t *gflag = nullptr;  // per-graph: entry outside the graph's range
+  // fp32 weights: global hub tables (keys, fp64 sums)
+  uint32_t *fkeys = nullptr;
+  double *fsums = nullptr;
+  int64_t fslots_cap = -1;
   int32_t *glab = nullptr;
   int64_t *goff = nullptr;
   int64_t gcols_cap = -1, gw_cap = -1, goff_cap = -1, batch_glab_cap = -1;
@@ -174,6 +178,8 @@ void free_scratch(Scratch &s) {
   hipFree(s.gdesc);
   hipFree(s.gbad);
   hipFree(s.gflag);
+  hipFree(s.fkeys);
+  hipFree(s.fsums);
   hipFree(s.glab);
   hipFree(s.goff);
   hipFree(s.gcols);
@@ -436,9 +442,10 @@ struct Launch {
   size_t ev;
 };
 
+// f32: `weights` holds fp32 values (summed in fp64) instead of uint32.
 int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *cols, const uint32_t *weights,
              int64_t n, int32_t max_iters, double tolerance, const gsl_options *opt, gsl_stats *stats,
-             int32_t *labels_out, const Batch *batch = nullptr) {
+             int32_t *labels_out, const Batch *batch = nullptr, bool f32 = false) {
   gsl_options o = {1, 1, 0, 0, 0};
   if (opt) o = *opt;
   if (stats) memset(stats, 0, sizeof(*stats));
@@ -452,7 +459,9 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
   if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   if ((rc = ensure_scratch(s, n, max_iters))) return rc;
-  const gsl::TierConfig cfg = current_tiers();
+  // fp32 weights run the fixed default tiers (their kernels are instantiated
+  // for those bounds only)
+  const gsl::TierConfig cfg = f32 ? gsl::kDefaultTiers : current_tiers();
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
   if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
@@ -513,7 +522,23 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   HIP_TRY(hipMemcpyAsync(s.ctrl, &hc, sizeof(hc), hipMemcpyHostToDevice, st));
   HIP_TRY(gsl::launch_loop_init(
       s.ctrl, renumber ? reinterpret_cast<const unsigned long long *>(&s.ctr->first_flags) : nullptr, dn_arr,
-      mk_arr, st));
+      mk_arr, f32 ? 0 : 1, st));
+  if (f32 && H > 0) {
+    const int64_t slots = gsl::hub_f32_slots(s.h_chunk[(size_t)H]);
+    if (slots > s.fslots_cap) {
+      hipFree(s.fkeys);
+      hipFree(s.fsums);
+      s.fkeys = nullptr;
+      s.fsums = nullptr;
+      s.fslots_cap = -1;
+      if (dmalloc(&s.fkeys, slots) != hipSuccess || dmalloc(&s.fsums, slots) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GSL_ENOMEM, "hub table allocation (%lld slots) failed", (long long)slots);
+      }
+      s.fslots_cap = slots;
+    }
+    HIP_TRY(gsl::launch_hub_f32_clear(s.fkeys, s.fsums, slots, st));
+  }
   if (batch)
     HIP_TRY(gsl::launch_batch_init(batch->vtx_base, batch->graphs, max_iters, tolerance, s.gid, s.glimit,
                                    s.giters, s.gdone, s.gdn, st));
@@ -571,7 +596,10 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
         launches.push_back({t, k, 0, nev});
         if ((rc = rec(nev++))) return rc;
       }
-      if (t == gsl::kHubTier) {
+      if (t == gsl::kHubTier && f32) {
+        HIP_TRY(gsl::launch_hub_f32(a, g_list, s.hub_chunk_start, cnt, s.h_chunk[(size_t)cnt], s.fkeys, s.fsums,
+                                    cur));
+      } else if (t == gsl::kHubTier) {
         for (size_t bi = 0; bi < s.hub_batches.size(); ++bi) {
           const auto &bt = s.hub_batches[bi];
           for (int stage = 0; stage < 2; ++stage) {
@@ -585,7 +613,10 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
           }
         }
       } else {
-        HIP_TRY(gsl::launch_sweep_tier(cfg.variant[t], a, g_list, plan.tier_start[t], cnt, &grids.g[t], cur));
+        if (f32)
+          HIP_TRY(gsl::launch_sweep_tier_f32(t, a, g_list, plan.tier_start[t], cnt, &grids.g[t], cur));
+        else
+          HIP_TRY(gsl::launch_sweep_tier(cfg.variant[t], a, g_list, plan.tier_start[t], cnt, &grids.g[t], cur));
       }
       if (timed && (rc = rec(nev++))) return rc;
     }
@@ -606,7 +637,8 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     // The whole loop (max_iters sweeps) as one captured graph, reused while
     // every pointer and size it was built from stays the same.
     std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)n_sweep, (uint64_t)nnz, (uint64_t)max_iters,
-                                 (uint64_t)o.prune, (uint64_t)renumber, (uint64_t)a.inplace,
+                                 (uint64_t)o.prune, (uint64_t)renumber, (uint64_t)a.inplace, (uint64_t)f32,
+                                 (uint64_t)(uintptr_t)s.fkeys, (uint64_t)(uintptr_t)s.fsums,
                                  (uint64_t)(uintptr_t)g_off, (uint64_t)(uintptr_t)g_cols,
                                  (uint64_t)(uintptr_t)g_w, (uint64_t)(uintptr_t)C, (uint64_t)(uintptr_t)g_list,
                                  (uint64_t)(uintptr_t)s.Cn, (uint64_t)(uintptr_t)s.chg,
@@ -995,6 +1027,31 @@ int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weig
   Scratch *sp = nullptr;
   if ((rc = get_scratch(&sp))) return rc;
   return lpa_impl(*sp, g_stream, offsets, cols, weights, n, max_iters, tolerance, opt, stats, labels_out);
+}
+
+int gsl_lpa_f32(const int64_t *offsets, const int32_t *cols, const float *weights, int64_t n, int32_t max_iters,
+                double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *labels_out) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  int rc = check_lpa(n, max_iters, tolerance, offsets, labels_out);
+  if (rc) return rc == kNoop ? GSL_OK : rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Scratch *sp = nullptr;
+  if ((rc = get_scratch(&sp))) return rc;
+  Scratch &s = *sp;
+  const hipStream_t st = g_stream;
+  if (weights) {
+    int64_t nnz = 0;
+    if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
+    if ((rc = ensure_batch(s, 1, 1))) return rc;
+    unsigned long long bad = 0;
+    HIP_TRY(hipMemsetAsync(s.gbad, 0, sizeof(unsigned long long), st));
+    HIP_TRY(gsl::launch_check_f32(weights, nnz, s.gbad, st));
+    HIP_TRY(hipMemcpyAsync(&bad, s.gbad, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(GSL_EINVAL, "weights must be finite and >= 0");
+  }
+  return lpa_impl(s, st, offsets, cols, reinterpret_cast<const uint32_t *>(weights), n, max_iters, tolerance, opt,
+                  stats, labels_out, nullptr, weights != nullptr);
 }
 
 int gsl_lpa_batched(int64_t num_graphs, const int64_t *vtx_base, const int64_t *edge_base, const int64_t *offsets,

@@ -195,7 +195,19 @@ hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsig
 // Loop state before the first sweep; first_flags (NULL unless renumbered)
 // tells whether the renumbering copy already ran sweep 0.
 hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_flags, unsigned long long *dn,
-                            unsigned long long *marked_sweeps, hipStream_t s);
+                            unsigned long long *marked_sweeps, int check_overflow, hipStream_t s);
+// ---- fp32 weights summed in fp64 (sweep_f32.hip); SweepArgs::w holds floats ----
+hipError_t launch_sweep_tier_f32(int tier, const SweepArgs &a, const int32_t *list, int64_t first, int64_t count,
+                                 int *grid_out, hipStream_t s);
+// Hub tier: per-chunk LDS sums folded into a global table per hub
+// (hub_f32_slots(chunks) slots in total, empty before the first sweep and
+// left empty by every sweep).
+hipError_t launch_hub_f32(const SweepArgs &a, const int32_t *hubs, const int64_t *chunk_start, int64_t H,
+                          int64_t chunks, uint32_t *gkeys, double *gsums, hipStream_t s);
+int64_t hub_f32_slots(int64_t chunks);
+hipError_t launch_hub_f32_clear(uint32_t *gkeys, double *gsums, int64_t slots, hipStream_t s);
+// *bad |= 1 if a weight is negative, NaN or infinite.
+hipError_t launch_check_f32(const float *w, int64_t nnz, unsigned long long *bad, hipStream_t s);
 // Batches: graph id per vertex, per-graph limits, sweep counts and stop flags.
 hipError_t launch_batch_init(const int64_t *vtx_base, int64_t graphs, int32_t max_iters, double tol,
                              int32_t *gid, int64_t *glimit, int32_t *giters, uint8_t *gdone, int64_t *gdn,

@@ -482,7 +482,7 @@ __global__ void sweep_end(SweepCtrl *c, const unsigned long long *dn, unsigned l
 // already ran sweep 0 (first_flags bit 0 clear: every row strictly
 // increasing), the loop resumes at sweep 1 with that sweep's change count.
 __global__ void loop_init(SweepCtrl *c, const unsigned long long *first_flags, unsigned long long *dn,
-                          unsigned long long *marked_sweeps) {
+                          unsigned long long *marked_sweeps, int check_overflow) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   c->it = 0;
   c->error = 0;
@@ -498,7 +498,7 @@ __global__ void loop_init(SweepCtrl *c, const unsigned long long *first_flags, u
   }
   marked_sweeps[0] = 0;
   c->it = 1;
-  if (ff & 2ull) {
+  if (check_overflow && (ff & 2ull)) {
     c->error = 1;
     c->done = 1;
     return;
@@ -571,8 +571,8 @@ hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsig
 }
 
 hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_flags, unsigned long long *dn,
-                            unsigned long long *marked_sweeps, hipStream_t s) {
-  loop_init<<<1, 64, 0, s>>>(ctrl, first_flags, dn, marked_sweeps);
+                            unsigned long long *marked_sweeps, int check_overflow, hipStream_t s) {
+  loop_init<<<1, 64, 0, s>>>(ctrl, first_flags, dn, marked_sweeps, check_overflow);
   return hipGetLastError();
 }
 

@@ -47,6 +47,9 @@ def test_argument_errors_are_reported_without_device_work():
     assert lib.gsl_lpa(None, None, None, 5, 20, float("nan"), None) == gsl.GSL_EINVAL
     assert lib.gsl_lpa(None, None, None, 1 << 31, 20, 0.05, None) == gsl.GSL_EINVAL
     assert lib.gsl_lpa(None, None, None, 0, 20, 0.05, None) == gsl.GSL_OK  # n = 0: no-op
+    assert lib.gsl_lpa_f32(None, None, None, -1, 20, 0.05, None, None, None) == gsl.GSL_EINVAL
+    assert lib.gsl_lpa_f32(None, None, None, 0, 20, 0.05, None, None, None) == gsl.GSL_OK
+    assert lib.gsl_lpa_f32(None, None, None, 5, 20, 2.0, None, None, None) == gsl.GSL_EINVAL
     assert lib.gsl_split(None, None, 0, None, None) == gsl.GSL_OK
     assert lib.gsl_split(None, None, 3, None, None) == gsl.GSL_EINVAL
     assert lib.gsl_modularity(None, None, None, 0, None, None) == gsl.GSL_EINVAL

@@ -360,3 +360,49 @@ def test_async_sweeps_keep_the_invariants(gsl):
             assert q_async >= q_sync - 0.1, (g.name, layout, q_async, q_sync)
             if g is cl:
                 np.testing.assert_array_equal(a, oracle.lpa(g).labels)
+
+
+def _f32_weights(g, rng, dyadic):
+    """fp32 weights per undirected edge (symmetric): multiples of 1/64 (every
+    fp64 partial sum exact) or uniform in (0, 1]."""
+    rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    lo, hi = np.minimum(rows, g.cols), np.maximum(rows, g.cols)
+    key = lo.astype(np.int64) * g.n + hi
+    uniq, inv = np.unique(key, return_inverse=True)
+    if dyadic:
+        vals = rng.integers(1, 4096, size=uniq.shape[0]) / 64.0
+    else:
+        vals = 1.0 - rng.random(uniq.shape[0])
+    return vals[inv].astype(np.float32)
+
+
+def test_f32_weights_match_the_fp64_oracle(gsl):
+    """fp32 weights summed in fp64: bit-exact with the oracle when every
+    partial sum is exact (dyadic weights); with uniform random weights, where
+    summation order could only matter at exact ties, labels agree."""
+    rng = np.random.default_rng(51)
+    graphs = [workloads.make(1), workloads.make(2, small=True), workloads.make(3, small=True), _tier_graph(6, False)]
+    for g in graphs:
+        off, cols, _ = to_device(g)
+        for dyadic in (True, False):
+            w = _f32_weights(g, rng, dyadic)
+            wd = torch.from_numpy(w).cuda()
+            for split in (False, True):
+                r = oracle.lpa_f32(g, w, 20, 0.05, split=split)
+                for layout in ("original", "renumbered"):
+                    lab, st = gsl.gsl_lpa_f32(off, cols, wd, 20, 0.05, split=split, layout=layout)
+                    tag = "%s dyadic=%s split=%s %s" % (g.name, dyadic, split, layout)
+                    assert st["iterations"] == r.iterations, tag
+                    assert list(st["changed"]) == list(r.dn), tag
+                    np.testing.assert_array_equal(lab.cpu().numpy(), r.labels, err_msg=tag)
+    # integer-valued float weights give the integer path's labels
+    g = workloads.make(2, small=True)
+    off, cols, w = to_device(g)
+    a, _ = gsl.gsl_lpa_ex(off, cols, w)
+    b, _ = gsl.gsl_lpa_f32(off, cols, w.view(torch.int32).to(torch.float32) if w is not None else None)
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    bad = torch.ones(g.nnz, dtype=torch.float32, device="cuda")
+    bad[3] = -1.0
+    with pytest.raises(gsl.GslError) as e:
+        gsl.gsl_lpa_f32(off, cols, bad)
+    assert e.value.code == gsl.GSL_EINVAL
