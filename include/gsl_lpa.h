@@ -324,8 +324,9 @@ int64_t gsl_convergence_limit(int64_t n, double tolerance);
  * degrees (max_degree[l-1], max_degree[l]] and runs the sweep kernel
  * `variant`.  Variants differ in lanes per vertex, entries per lane, LDS
  * table size and workgroup size (gsl_tier_variant); a variant takes rows of
- * up to `capacity` entries.  Variant 0 (a thread per vertex) is level 0's and
- * only level 0's.  The choice changes speed, never results.
+ * up to `capacity` entries.  The thread-per-vertex variants (group 1: 0, 15,
+ * 16) serve level 0 and only level 0.  The choice changes speed, never
+ * results.
  */
 #define GSL_TIER_LEVELS 7
 typedef struct gsl_tier {

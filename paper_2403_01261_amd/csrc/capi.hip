@@ -1319,7 +1319,8 @@ int gsl_set_tiers(const gsl_tier *levels) {
       const int32_t v = levels[l].variant;
       const int64_t b = levels[l].max_degree;
       if (v < 0 || v >= gsl::kNumVariants) return fail(GSL_EINVAL, "level %d: no variant %d", l, v);
-      if ((l == 0) != (v == 0)) return fail(GSL_EINVAL, "variant 0 (a thread per vertex) is level 0's only");
+      if ((l == 0) != gsl::variant_is_thread(v))
+        return fail(GSL_EINVAL, "level 0 takes a thread-per-vertex variant (0, 15, 16), the others a group variant");
       if (b < prev) return fail(GSL_EINVAL, "level %d: degree bounds must not decrease", l);
       if (b > gsl::variant_capacity(v))
         return fail(GSL_EINVAL, "level %d: bound %lld exceeds variant %d's %lld entries", l, (long long)b, v,

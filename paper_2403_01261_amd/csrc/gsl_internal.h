@@ -26,7 +26,7 @@ constexpr int kHubTier = 8;
 struct SweepVariant {
   int group, log2s, block, per_lane;
 };
-constexpr int kNumVariants = 15;
+constexpr int kNumVariants = 17;
 constexpr SweepVariant kVariants[kNumVariants] = {
     {1, 0, 256, 8},     // 0: thread per vertex, row in registers (d <= 8)
     {8, 5, 256, 2},     // 1: d <= 16
@@ -43,7 +43,11 @@ constexpr SweepVariant kVariants[kNumVariants] = {
     {512, 12, 512, 4},  // 12: d <= 2048, one 512-thread workgroup per vertex
     {512, 13, 512, 8},  // 13: d <= 4096 (64 KB table)
     {1024, 14, 1024, 8},  // 14: d <= 8192 (128 KB table, one workgroup per CU)
+    {1, 0, 256, 16},    // 15: thread per vertex, d <= 16
+    {1, 0, 256, 32},    // 16: thread per vertex, d <= 32
 };
+// A thread-per-vertex variant (group 1) may only serve the first level.
+constexpr bool variant_is_thread(int v) { return kVariants[v].group == 1; }
 constexpr int64_t variant_capacity(int v) { return (int64_t)kVariants[v].group * kVariants[v].per_lane; }
 
 // Degree tiers of one call: tier t (1..7) takes degrees (bound[t-1],

@@ -379,6 +379,14 @@ hipError_t launch_sweep_tier(int variant, const SweepArgs &a, const int32_t *lis
       grid = grid_for(count, 256, kMaxTierGrid);
       sweep_thread<8><<<grid, 256, 0, s>>>(a, list, first, count);
       break;
+    case 15:
+      grid = grid_for(count, 256, kMaxTierGrid);
+      sweep_thread<16><<<grid, 256, 0, s>>>(a, list, first, count);
+      break;
+    case 16:
+      grid = grid_for(count, 256, kMaxTierGrid);
+      sweep_thread<32><<<grid, 256, 0, s>>>(a, list, first, count);
+      break;
     case 1: grid = launch_lds<8, 5, 256, 2>(a, list, first, count, s); break;
     case 2: grid = launch_lds<4, 5, 256, 4>(a, list, first, count, s); break;
     case 3: grid = launch_lds<16, 6, 256, 2>(a, list, first, count, s); break;

@@ -36,7 +36,7 @@ def cache_path() -> str:
 def valid(levels: Levels, variants: Sequence[dict]) -> bool:
     prev = 0
     for k, (b, v) in enumerate(levels):
-        if not (0 <= v < len(variants)) or (k == 0) != (v == 0):
+        if not (0 <= v < len(variants)) or (k == 0) != (variants[v]["group"] == 1):
             return False
         if b < prev or b > variants[v]["capacity"]:
             return False
@@ -53,7 +53,7 @@ def options(levels: Levels, k: int, variants: Sequence[dict]) -> List[Tuple[int,
     out = []
     for b in bounds:
         for v, info in enumerate(variants):
-            if (k == 0) != (v == 0) or info["capacity"] < b:
+            if (k == 0) != (info["group"] == 1) or info["capacity"] < b:
                 continue
             out.append((b, v))
     return out

@@ -266,13 +266,14 @@ def _random_levels(rng, variants):
     while True:
         bounds = sorted(int(x) for x in rng.choice([0, 2, 4, 8, 12, 16, 24, 32, 48, 64, 100, 128, 256, 512,
                                                     1000, 2048], size=7))
-        bounds[0] = min(bounds[0], 8)
+        bounds[0] = min(bounds[0], 32)
         levels = []
         for k, b in enumerate(bounds):
             if k == 0:
-                levels.append((b, 0))
+                ok = [v for v in range(len(variants)) if variants[v]["group"] == 1 and variants[v]["capacity"] >= b]
+                levels.append((b, int(rng.choice(ok))))
                 continue
-            ok = [v for v in range(1, len(variants)) if variants[v]["capacity"] >= b]
+            ok = [v for v in range(len(variants)) if variants[v]["group"] > 1 and variants[v]["capacity"] >= b]
             levels.append((b, int(rng.choice(ok))))
         return levels
 

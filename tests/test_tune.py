@@ -9,7 +9,7 @@ from paper_2403_01261_amd import tune
 # The library's variant menu (gsl_tier_variant), as capacities and groups.
 VARIANTS = [{"group": g, "per_lane": k, "capacity": g * k} for g, k in
             [(1, 8), (8, 2), (4, 4), (16, 2), (8, 4), (32, 2), (16, 4), (64, 2), (32, 4), (64, 8), (128, 4),
-             (256, 8), (512, 4), (512, 8), (1024, 8)]]
+             (256, 8), (512, 4), (512, 8), (1024, 8), (1, 16), (1, 32)]]
 
 
 def test_defaults_are_valid_and_options_respect_bounds():
@@ -23,12 +23,18 @@ def test_defaults_are_valid_and_options_respect_bounds():
     bad = list(tune.DEFAULT_LEVELS)
     bad[1] = (8, 0)  # thread variant outside level 0
     assert not tune.valid(bad, VARIANTS)
+    bad[1] = (16, 15)
+    assert not tune.valid(bad, VARIANTS)
+    ok = list(tune.DEFAULT_LEVELS)
+    ok[0] = (32, 16)  # a wider thread variant on level 0
+    ok[1] = (32, 3)
+    assert tune.valid(ok, VARIANTS)
     for k in range(7):
         for b, v in tune.options(tune.DEFAULT_LEVELS, k, VARIANTS):
             trial = list(tune.DEFAULT_LEVELS)
             trial[k] = (b, v)
             assert VARIANTS[v]["capacity"] >= b
-            assert (k == 0) == (v == 0)
+            assert (k == 0) == (VARIANTS[v]["group"] == 1)
 
 
 def test_search_finds_the_cheaper_configuration():
