@@ -212,6 +212,17 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
     return rec[wname][kernel]
 
 
+def calibration_copy():
+    """A plain device copy of COPY_BYTES, the reference the traffic counters
+    are scaled by."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def cpu_baseline(g, max_iters, tol, w32=None):
     import oracle
     t0 = time.perf_counter()
@@ -438,6 +449,8 @@ def main(argv=None):
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
+    if args.pmc_copy:
+        calibration_copy()
     if args.workload == 5:
         return bench_batched(args)
 
@@ -449,12 +462,6 @@ def main(argv=None):
 
     gsl.load()
     dev = torch.device("cuda:0")
-    if args.pmc_copy:
-        src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     t0 = time.time()
     g = workloads.make(args.workload, small=args.small)
     log("generated %s: n=%d nnz=%d in %.1fs" % (workloads.NAMES[args.workload], g.n, g.nnz,

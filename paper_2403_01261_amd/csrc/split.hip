@@ -9,16 +9,16 @@
 // smallest vertex, whatever order the unions happen in.
 //
 // The edges are taken in the order of Afforest (Sutton, Ben-Nun & Barak,
-// IPDPS 2018): first the first two entries of every row (one round each,
-// flattened in between), then a representative component per community --
-// the root some vertex of the community points at after the flattening,
-// nearly always the community's big piece -- and then the remaining entries
+// IPDPS 2018): first the first two intra-community entries of every row,
+// flattened, then a representative component per
+// community -- the root some vertex of the community points at after the
+// flattening, nearly always the community's big piece -- and then every entry
 // of every row whose vertex is not in its community's representative.  A
 // skipped vertex u loses nothing: an entry (u, v) with v in another community
 // needs no union; with v skipped too, u and v are already in the same
 // component (a community has one representative); otherwise the mirrored
-// entry (v, u) is processed from v's side (the graph is symmetric), either
-// among v's first two entries or in the second pass.
+// entry (v, u) is processed from v's side in the second pass (the graph is
+// symmetric).
 #include "device_common.h"
 #include "gsl_internal.h"
 
@@ -78,20 +78,29 @@ __global__ void split_init(int32_t *parent, int64_t n) {
     parent[i] = (int32_t)i;
 }
 
-constexpr int kLinkFirst = 2;  // entries per row linked before the sample
+constexpr int kLinkFirst = 2;  // intra-community entries per row linked before the hooks
 
-// First pass: entry q (< kLinkFirst) of every row, one launch per q with a
-// flattening in between, so the second round starts from flat trees.
+// First pass: the first kLinkFirst intra-community entries of every row
+// (scanning at most kLinkScan entries), then a flattening.  Taking
+// intra-community entries (not simply the first entries, which may all lead
+// to other communities) leaves nearly every community in one piece.
+constexpr int kLinkScan = 16;
 __global__ __launch_bounds__(256) void split_link_first(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
                                                         const int32_t *__restrict__ C,
-                                                        int32_t *parent, int64_t n, int q) {
+                                                        int32_t *parent, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-    const int64_t b = off[u], e = off[u + 1];
-    if (b + q >= e) continue;
-    const int32_t v = cols[b + q];
-    if (v != (int32_t)u && C[v] == C[u]) unite(parent, (int32_t)u, v);
+    const int64_t b = off[u];
+    const int64_t e = off[u + 1] < b + kLinkScan ? off[u + 1] : b + kLinkScan;
+    const int32_t cu = C[u];
+    int seen = 0;
+    for (int64_t p = b; p < e && seen < kLinkFirst; ++p) {
+      const int32_t v = cols[p];
+      if (v == (int32_t)u || C[v] != cu) continue;
+      unite(parent, (int32_t)u, v);
+      ++seen;
+    }
   }
 }
 
@@ -129,8 +138,9 @@ __device__ __forceinline__ void hook_entry(int32_t *parent, const unsigned long 
   unite(parent, u, v);
 }
 
-// Second pass, one thread per vertex (short rows): entries from position
-// kLinkFirst on, for vertices outside their community's representative.
+// Second pass, one thread per vertex (short rows): every entry of the rows of
+// vertices outside their community's representative (entries already linked
+// cost one snapshot compare).
 __global__ __launch_bounds__(256) void split_hook_thread(const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ cols,
                                                          const unsigned long long *__restrict__ cp,
@@ -143,8 +153,16 @@ __global__ __launch_bounds__(256) void split_hook_thread(const int64_t *__restri
     const int32_t u = list ? list[first + idx] : (int32_t)(first + idx);
     const unsigned long long xu = cp[u];
     if (rep[xu >> 32] == (int32_t)(uint32_t)xu) continue;
-    for (int64_t p = off[u] + kLinkFirst; p < off[u + 1]; ++p)
-      hook_entry(parent, cp, u, (uint32_t)(xu >> 32), (uint32_t)xu, cols[p]);
+    const int64_t e = off[u + 1];
+    int64_t p = off[u];
+    // the link rounds joined the first kLinkFirst intra-community entries
+    // found within kLinkScan entries: skip them
+    for (int linked = 0; p < e && p < off[u] + kLinkScan && linked < kLinkFirst; ++p) {
+      const int32_t v = cols[p];
+      if (v != u && (uint32_t)(cp[v] >> 32) == (uint32_t)(xu >> 32))
+        ++linked;
+    }
+    for (; p < e; ++p) hook_entry(parent, cp, u, (uint32_t)(xu >> 32), (uint32_t)xu, cols[p]);
   }
 }
 
@@ -164,7 +182,7 @@ __global__ __launch_bounds__(256) void split_hook_group(const int64_t *__restric
     const unsigned long long xu = cp[u];
     if (rep[xu >> 32] == (int32_t)(uint32_t)xu) continue;  // uniform over the group
     const int64_t e = off[u + 1];
-    for (int64_t p = off[u] + kLinkFirst + lane; p < e; p += G)
+    for (int64_t p = off[u] + lane; p < e; p += G)
       hook_entry(parent, cp, u, (uint32_t)(xu >> 32), (uint32_t)xu, cols[p]);
   }
 }
@@ -444,10 +462,8 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
   constexpr int kCap = 256 * 16;
   if (n > 0) {
     split_init<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
-    for (int q = 0; q < kLinkFirst; ++q) {
-      split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n, q);
-      split_flatten<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
-    }
+    split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n);
+    split_flatten<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
     split_rep<<<grid_cap(n, 256, kCap), 256, 0, s>>>(C, parent, n, rep);
     split_pack<<<grid_cap(n, 256, kCap), 256, 0, s>>>(C, parent, n, cp);
   }
