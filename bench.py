@@ -268,7 +268,7 @@ def roofline_from_stats(stats, weighted, steps, wname):
     import paper_2403_01261_amd as gsl
     variants = gsl.gsl_tier_variants()
     levels = gsl.gsl_get_tiers()
-    kernel = "hub_insert" if dom == NUM_TIERS - 1 else gsl.variant_kernel_name(variants[levels[dom - 1][1]])
+    kernel = "hub_insert" if dom == NUM_TIERS - 1 else gsl.variant_kernel_name(variants[levels[dom - 1][1]], weighted)
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel),
             "kernel": kernel, "tier": dom, "launches_per_step": launches // max(steps, 1),

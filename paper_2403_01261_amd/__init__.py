@@ -437,10 +437,11 @@ def gsl_tier_variants():
                     "per_lane": info.per_lane, "capacity": info.capacity})
 
 
-def variant_kernel_name(v: dict) -> str:
-    """The sweep kernel's name as profilers print it (template arguments)."""
+def variant_kernel_name(v: dict, weighted: bool = False) -> str:
+    """The sweep kernel's name as profilers print it (template arguments;
+    the thread variants have a weighted and a unit-weight kernel)."""
     if v["group"] == 1:
-        return "sweep_thread<%d>" % v["per_lane"]
+        return "sweep_thread<%d, %s>" % (v["per_lane"], "true" if weighted else "false")
     return "sweep_lds<%d, %d, %d, %d>" % (v["group"], v["table_log2"], v["block"], v["per_lane"])
 
 

@@ -563,6 +563,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   a.gid = batch ? s.gid : nullptr;
   a.gdone = batch ? s.gdone : nullptr;
   a.inplace = o.async_sweeps ? 1 : 0;
+  a.n = n;
   const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
 
   // Timing records (timing mode only).

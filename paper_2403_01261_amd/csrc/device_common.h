@@ -209,6 +209,39 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long x,
   return t;
 }
 
+// Batcher's odd-even merge sort of D register values (D a power of two):
+// a sorting network, so the compare-exchange sequence is the same for every
+// input and every index is a compile-time constant once unrolled (19, 63 and
+// 191 compare-exchanges for D = 8, 16, 32).  Labels end up ascending; with
+// W, each weight moves with its label.
+template <int D, bool W>
+__device__ __forceinline__ void sort_by_label(uint32_t (&l)[D], uint32_t (&w)[D]) {
+#pragma unroll
+  for (int p = 1; p < D; p <<= 1)
+#pragma unroll
+    for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+      for (int j = k % p; j + k < D; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k; ++i) {
+          const int x = i + j, y = i + j + k;
+          if (y < D && x / (2 * p) == y / (2 * p)) {
+            if constexpr (W) {
+              const bool s = l[x] > l[y];
+              const uint32_t lx = l[x], wx = w[x];
+              l[x] = s ? l[y] : lx;
+              l[y] = s ? lx : l[y];
+              w[x] = s ? w[y] : wx;
+              w[y] = s ? wx : w[y];
+            } else {
+              const uint32_t lo = l[x] < l[y] ? l[x] : l[y], hi = l[x] < l[y] ? l[y] : l[x];
+              l[x] = lo;
+              l[y] = hi;
+            }
+          }
+        }
+}
+
 // Per-thread sweep counters, reduced once per block at kernel end.
 struct LocalCounts {
   unsigned long long dn = 0, processed = 0, edges = 0, overflow = 0, marked = 0;

@@ -126,6 +126,7 @@ struct SweepArgs {
   // so vertices later in the same sweep may already read it (the paper's
   // in-place lpaMove); results then depend on timing.
   int32_t inplace;
+  int64_t n;  // vertices (labels C[0..n))
 };
 
 // What a sweep kernel needs from the loop state.

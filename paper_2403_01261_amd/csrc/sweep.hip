@@ -57,10 +57,34 @@ __device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCoun
 }
 
 // ---------------------------------------------------------------------------
-// Tier 1: one thread per vertex, degree <= D.  The row's labels and weights
-// stay in registers; the weight of a label is the sum over equal entries.
+// Tier 1: one thread per vertex, degree <= D.  The row's labels (and weights)
+// stay in registers.  A sorting network puts equal labels next to each
+// other, and one pass over the sorted runs keeps the running sum of each run
+// and the largest argmax key seen.  A run's partial sums never exceed its
+// total, so the largest key is that of the label with the largest total (the
+// smallest such label on ties, which the key orders first).  Entries j == i
+// and the padding beyond the row carry the no-label value, which sorts last
+// and never becomes a candidate.  W: weighted rows; without it every entry
+// weighs 1.
+//
+// The sweep is bound by the latency of the label gathers, so registers are
+// kept few (more waves in flight): each label is loaded into the register
+// that held its column, and with O32 (fewer than 2^30 vertices) the gather
+// address is the label array's base plus a 32-bit byte offset, which needs
+// no 64-bit address registers.
 // ---------------------------------------------------------------------------
-template <int D>
+__device__ const int32_t kZeroI32 = 0;
+__device__ const uint8_t kZeroU8 = 0, kOneU8 = 1;
+
+template <bool O32>
+__device__ __forceinline__ uint32_t gather_label(const int32_t *__restrict__ C, int32_t c) {
+  if constexpr (O32)
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(C) + ((uint32_t)c << 2));
+  else
+    return (uint32_t)C[c];
+}
+
+template <int D, bool W, bool O32>
 __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *__restrict__ list,
                                                     int64_t first, int64_t count) {
   __shared__ unsigned long long red[256 / kWave];
@@ -70,29 +94,41 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
     const int32_t v = list ? list[first + idx] : (int32_t)(first + idx);
-    if (!sweep_takes(a, sv, v)) continue;
+    // Everything that depends on v alone is loaded at once (absent arrays
+    // read constants instead of branching: a branch would make the wave wait
+    // for every load issued before it), so a vertex waits for four dependent
+    // loads before its gathers instead of six.
+    const int32_t *gp = a.gid ? a.gid + v : &kZeroI32;
+    const uint8_t *ap = sv.dense ? &kOneU8 : sv.act + v;
     const int64_t b = a.off[v];
     const int d = (int)(a.off[v + 1] - b);
-    int32_t col[D];
+    const int32_t g = *gp;
+    const bool on = *ap != 0;
+    const uint32_t own = (uint32_t)a.C[v];
+    const uint8_t *dp = a.gdone ? a.gdone + g : &kZeroU8;
+    if (!on || *dp) continue;
     uint32_t lab[D], w[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) col[k] = k < d ? a.cols[b + k] : v;
+    for (int k = 0; k < D; ++k) lab[k] = k < d ? (uint32_t)a.cols[b + k] : (uint32_t)v;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      lab[k] = col[k] != v ? (uint32_t)a.C[col[k]] : kNoLabel;
-      w[k] = k < d ? (a.w ? a.w[b + k] : 1u) : 0u;
+    for (int k = 0; k < D; ++k) lab[k] = lab[k] != (uint32_t)v ? gather_label<O32>(a.C, (int32_t)lab[k]) : kNoLabel;
+    unsigned long long rowsum = (unsigned long long)d;
+    if constexpr (W) {
+      rowsum = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        w[k] = k < d ? a.w[b + k] : 0u;
+        rowsum += w[k];
+      }
     }
-    unsigned long long rowsum = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) rowsum += w[k];
+    sort_by_label<D, W>(lab, w);
     unsigned long long best = 0;
+    uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      if (lab[k] == kNoLabel) continue;
-      uint32_t s = 0;
-#pragma unroll
-      for (int m = 0; m < D; ++m) s += lab[m] == lab[k] ? w[m] : 0u;
-      const unsigned long long key = argmax_key(lab[k], s);
+      const uint32_t wk = W ? w[k] : 1u;
+      s = (k > 0 && lab[k] == lab[k - 1]) ? s + wk : wk;
+      const unsigned long long key = lab[k] != kNoLabel ? argmax_key(lab[k], s) : 0ull;
       best = key > best ? key : best;
     }
     lc.processed += 1;
@@ -100,19 +136,37 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
     lc.overflow += rowsum >> 32 ? 1 : 0;
     if (best) {
       const uint32_t cstar = key_label(best);
-      if (cstar != (uint32_t)a.C[v]) {
+      if (cstar != own) {
         record_change(a, v, cstar, lc);
-        if (sv.mark)
-#pragma unroll
-          for (int k = 0; k < D; ++k)
-            if (k < d) {
-              if (!sv.nact[col[k]]) sv.nact[col[k]] = 1;
-              lc.marked += 1;
-            }
+        if (sv.mark) {
+          // the row again (just read, so mostly from cache) for the flags
+          for (int k = 0; k < d; ++k) {
+            const int32_t j = a.cols[b + k];
+            if (!sv.nact[j]) sv.nact[j] = 1;
+          }
+          lc.marked += (unsigned long long)d;
+        }
       }
     }
   }
   flush_counts(a, lc, red);
+}
+
+template <int D>
+void launch_thread(const SweepArgs &a, const int32_t *list, int64_t first, int64_t count, int grid,
+                   hipStream_t s) {
+  const bool o32 = a.n < (int64_t(1) << 30);
+  if (a.w) {
+    if (o32)
+      sweep_thread<D, true, true><<<grid, 256, 0, s>>>(a, list, first, count);
+    else
+      sweep_thread<D, true, false><<<grid, 256, 0, s>>>(a, list, first, count);
+  } else {
+    if (o32)
+      sweep_thread<D, false, true><<<grid, 256, 0, s>>>(a, list, first, count);
+    else
+      sweep_thread<D, false, false><<<grid, 256, 0, s>>>(a, list, first, count);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -377,15 +431,15 @@ hipError_t launch_sweep_tier(int variant, const SweepArgs &a, const int32_t *lis
   switch (variant) {
     case 0:
       grid = grid_for(count, 256, kMaxTierGrid);
-      sweep_thread<8><<<grid, 256, 0, s>>>(a, list, first, count);
+      launch_thread<8>(a, list, first, count, grid, s);
       break;
     case 15:
       grid = grid_for(count, 256, kMaxTierGrid);
-      sweep_thread<16><<<grid, 256, 0, s>>>(a, list, first, count);
+      launch_thread<16>(a, list, first, count, grid, s);
       break;
     case 16:
       grid = grid_for(count, 256, kMaxTierGrid);
-      sweep_thread<32><<<grid, 256, 0, s>>>(a, list, first, count);
+      launch_thread<32>(a, list, first, count, grid, s);
       break;
     case 1: grid = launch_lds<8, 5, 256, 2>(a, list, first, count, s); break;
     case 2: grid = launch_lds<4, 5, 256, 4>(a, list, first, count, s); break;
