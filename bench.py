@@ -253,7 +253,7 @@ def run_tuner(args, run, probe):
             "evaluations": res["evaluations"], "seconds": round(time.time() - t0, 1)}
 
 
-def roofline_from_stats(stats, weighted, steps, wname):
+def roofline_from_stats(stats, weighted, steps, wname, n):
     """Dominant sweep kernel over a list of timing-mode stats dicts."""
     ms_tier = [sum(st["tiers"][t]["ms"] for st in stats) for t in range(NUM_TIERS)]
     dom = max(range(1, NUM_TIERS), key=lambda t: ms_tier[t])
@@ -268,7 +268,7 @@ def roofline_from_stats(stats, weighted, steps, wname):
     import paper_2403_01261_amd as gsl
     variants = gsl.gsl_tier_variants()
     levels = gsl.gsl_get_tiers()
-    kernel = "hub_insert" if dom == NUM_TIERS - 1 else gsl.variant_kernel_name(variants[levels[dom - 1][1]], weighted)
+    kernel = "hub_insert" if dom == NUM_TIERS - 1 else gsl.variant_kernel_name(variants[levels[dom - 1][1]], weighted, n)
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel),
             "kernel": kernel, "tier": dom, "launches_per_step": launches // max(steps, 1),
@@ -343,7 +343,7 @@ def bench_batched(args):
     _, iters_b, st_b = gsl.gsl_lpa_batched(vb_d, eb_d, off, cols, None, mi, tol, out=out_batch, timing=True)
     if args.batched_only:
         print(json.dumps({"batched_ms": 1000.0 * batch_s, "graphs_per_s": G / batch_s, "tiers": tiers,
-                          "roofline": roofline_from_stats([st_b], False, 1, workloads.NAMES[5]),
+                          "roofline": roofline_from_stats([st_b], False, 1, workloads.NAMES[5], N),
                           "ms_sweep": st_b["ms_sweep"], "processed": st_b["processed"],
                           "changed": st_b["changed"], "ms_split": st_b["ms_split"]}), flush=True)
         return 0
@@ -410,7 +410,7 @@ def bench_batched(args):
                       "ms": round(1000.0 * plain_s, 3)},
             "speedup_batched_vs_plain": round(plain_s / batch_s, 2),
             "served": served, "labels_identical_plain_batched": same_plain_batch,
-            "roofline": roofline_from_stats([st_b], False, 1, wname), "cpu_baseline": cpu, "tiers": tiers}
+            "roofline": roofline_from_stats([st_b], False, 1, wname, N), "cpu_baseline": cpu, "tiers": tiers}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -502,7 +502,7 @@ def main(argv=None):
 
     # Dominant sweep kernel over the event pass.
     wname = workloads.NAMES[args.workload]
-    roofline = roofline_from_stats(stats, weighted, args.steps, wname)
+    roofline = roofline_from_stats(stats, weighted, args.steps, wname, g.n)
     # Whole sweep phase (all tier kernels + apply) for context.
     sweep_ms = sum(st["ms_sweeps"] for st in stats) / len(stats)
     sweep_bytes = sum(tier_bytes(dict(st["tiers"][t], vertices=st["tiers"][t]["vertices"]), weighted)

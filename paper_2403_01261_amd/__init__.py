@@ -437,11 +437,13 @@ def gsl_tier_variants():
                     "per_lane": info.per_lane, "capacity": info.capacity})
 
 
-def variant_kernel_name(v: dict, weighted: bool = False) -> str:
+def variant_kernel_name(v: dict, weighted: bool = False, n: int = 0) -> str:
     """The sweep kernel's name as profilers print it (template arguments;
-    the thread variants have a weighted and a unit-weight kernel)."""
+    the thread variants have weighted and unit-weight kernels, each with
+    32-bit gather offsets for fewer than 2^30 vertices or 64-bit ones)."""
     if v["group"] == 1:
-        return "sweep_thread<%d, %s>" % (v["per_lane"], "true" if weighted else "false")
+        return "sweep_thread<%d, %s, %s>" % (v["per_lane"], "true" if weighted else "false",
+                                             "true" if n < (1 << 30) else "false")
     return "sweep_lds<%d, %d, %d, %d>" % (v["group"], v["table_log2"], v["block"], v["per_lane"])
 
 
