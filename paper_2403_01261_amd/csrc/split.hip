@@ -85,6 +85,7 @@ constexpr int kLinkFirst = 2;  // intra-community entries per row linked before 
 // intra-community entries (not simply the first entries, which may all lead
 // to other communities) leaves nearly every community in one piece.
 constexpr int kLinkScan = 16;
+constexpr int kLinkChunk = 8;
 __global__ __launch_bounds__(256) void split_link_first(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
                                                         const int32_t *__restrict__ C,
@@ -95,11 +96,21 @@ __global__ __launch_bounds__(256) void split_link_first(const int64_t *__restric
     const int64_t e = off[u + 1] < b + kLinkScan ? off[u + 1] : b + kLinkScan;
     const int32_t cu = C[u];
     int seen = 0;
-    for (int64_t p = b; p < e && seen < kLinkFirst; ++p) {
-      const int32_t v = cols[p];
-      if (v == (int32_t)u || C[v] != cu) continue;
-      unite(parent, (int32_t)u, v);
-      ++seen;
+    // kLinkChunk entries and their labels are loaded at once (one round trip
+    // instead of one per entry), then linked in row order.
+    for (int64_t p0 = b; p0 < e && seen < kLinkFirst; p0 += kLinkChunk) {
+      int32_t v[kLinkChunk];
+      bool hit[kLinkChunk];
+#pragma unroll
+      for (int k = 0; k < kLinkChunk; ++k) v[k] = p0 + k < e ? cols[p0 + k] : (int32_t)u;
+#pragma unroll
+      for (int k = 0; k < kLinkChunk; ++k) hit[k] = v[k] != (int32_t)u && C[v[k]] == cu;
+#pragma unroll
+      for (int k = 0; k < kLinkChunk; ++k)
+        if (hit[k] && seen < kLinkFirst) {
+          unite(parent, (int32_t)u, v[k]);
+          ++seen;
+        }
     }
   }
 }

@@ -407,3 +407,39 @@ def test_f32_weights_match_the_fp64_oracle(gsl):
     with pytest.raises(gsl.GslError) as e:
         gsl.gsl_lpa_f32(off, cols, bad)
     assert e.value.code == gsl.GSL_EINVAL
+
+
+def test_vertex_ids_above_2_pow_30(gsl):
+    """Edges only among vertex ids >= 2^30 (every id below is an isolated
+    vertex), so label gathers take the 64-bit address path.  Labels start as
+    vertex ids and ties go to the smallest label, so shifting every id by the
+    same amount shifts the result: the top part must equal the oracle's
+    labels of the small graph plus 2^30, and every isolated vertex keeps its
+    own id.  Tolerance 0 stops both runs on the same rule (a sweep with no
+    change) whatever the vertex count."""
+    dev = torch.device("cuda:0")
+    base = 1 << 30
+    tuned = [(32, 16), (32, 4), (64, 6), (64, 5), (128, 7), (512, 9), (2048, 11)]
+    try:
+        for weighted in (False, True):
+            g = graphgen.planted(3000, 12, 0.05, 3000, 77, wmax=16 if weighted else 0)
+            r = oracle.lpa(g, 20, 0.0)
+            n = base + g.n
+            off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+            off[base:] = torch.from_numpy(np.ascontiguousarray(g.offsets, dtype=np.int64)).to(dev)
+            cols = torch.from_numpy(np.ascontiguousarray(g.cols, dtype=np.int32) + base).to(dev)
+            _, _, w = to_device(g)
+            ids = torch.arange(base, dtype=torch.int32, device=dev)
+            for tiers in (None, tuned):
+                for layout in ("original", "renumbered"):
+                    say("ids >= 2^30: weighted=%s tiers=%s layout=%s" % (weighted, tiers, layout))
+                    gsl.gsl_set_tiers(tiers)
+                    lab, st = gsl.gsl_lpa_ex(off, cols, w, 20, 0.0, layout=layout)
+                    assert st["iterations"] == r.iterations
+                    assert torch.equal(lab[:base], ids)
+                    np.testing.assert_array_equal(lab[base:].cpu().numpy(), r.labels + base)
+                    del lab
+            del off, cols, w, ids
+            torch.cuda.empty_cache()
+    finally:
+        gsl.gsl_set_tiers(None)
