@@ -92,6 +92,10 @@ struct Scratch {
   hipGraphExec_t loop_exec = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream the loop graph is captured on
   std::vector<uint64_t> loop_key;
+  // chunked loop launches: the stop flag after each chunk (pinned host
+  // memory) and the events the host waits on
+  int32_t *done_host = nullptr;
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
   // batches: graph of every vertex, per-graph limits / counts / flags, the
   // base arrays and descriptors of separate graphs, and the global copy
   int64_t batch_n_cap = -1, batch_g_cap = -1;
@@ -166,6 +170,9 @@ void free_scratch(Scratch &s) {
   if (s.ev_reorder) hipEventDestroy(s.ev_reorder);
   if (s.loop_exec) hipGraphExecDestroy(s.loop_exec);
   if (s.cap_stream) hipStreamDestroy(s.cap_stream);
+  if (s.done_host) hipHostFree(s.done_host);
+  for (auto &e : s.chunk_ev)
+    if (e) hipEventDestroy(e);
   hipFree(s.ctrl);
   hipFree(s.gid);
   hipFree(s.giters);
@@ -201,6 +208,11 @@ hipError_t dmalloc(T **p, int64_t count) {
 
 // Makes sure per-vertex scratch holds n vertices and the counters block holds
 // max_iters sweeps.
+// Loop graphs of graphs with at least kChunkMinEntries row entries hold
+// kChunkSweeps sweeps and are launched chunk by chunk (see lpa_impl).
+constexpr int64_t kChunkMinEntries = int64_t(1) << 23;
+constexpr int kChunkSweeps = 2;
+
 int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
   if (n > s.n_cap) {
     const int64_t cap = n;
@@ -635,9 +647,18 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     for (int k = 0; k < max_iters; ++k)
       if ((rc = enqueue_sweep(k))) return rc;
   } else {
-    // The whole loop (max_iters sweeps) as one captured graph, reused while
-    // every pointer and size it was built from stays the same.
-    std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)n_sweep, (uint64_t)nnz, (uint64_t)max_iters,
+    // The loop as a captured graph, reused while every pointer and size it
+    // was built from stays the same.  Small graphs: all max_iters sweeps in
+    // one graph (a sweep enqueued after convergence costs only empty
+    // launches, a few microseconds each).  Large graphs: a graph of
+    // kChunkSweeps sweeps launched repeatedly; the host queues chunk c before
+    // it waits for the stop flag after chunk c - 1, so the device never waits
+    // for the host and at most one chunk runs after the loop has stopped
+    // (every sweep kernel reads the same device loop state, so the chunks
+    // are identical).
+    const bool chunked = nnz >= kChunkMinEntries && max_iters > kChunkSweeps;
+    const int len = chunked ? kChunkSweeps : max_iters;
+    std::vector<uint64_t> key = {(uint64_t)len, (uint64_t)n, (uint64_t)n_sweep, (uint64_t)nnz, (uint64_t)max_iters,
                                  (uint64_t)o.prune, (uint64_t)renumber, (uint64_t)a.inplace, (uint64_t)f32,
                                  (uint64_t)(uintptr_t)s.fkeys, (uint64_t)(uintptr_t)s.fsums,
                                  (uint64_t)(uintptr_t)g_off, (uint64_t)(uintptr_t)g_cols,
@@ -674,7 +695,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
       cur = s.cap_stream;
       HIP_TRY(hipStreamBeginCapture(cur, hipStreamCaptureModeThreadLocal));
       int crc = GSL_OK;
-      for (int k = 0; k < max_iters && crc == GSL_OK; ++k) crc = enqueue_sweep(k);
+      for (int k = 0; k < len && crc == GSL_OK; ++k) crc = enqueue_sweep(k);
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(cur, &graph);
       cur = user_st;
@@ -691,7 +712,24 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
       }
       s.loop_key = key;
     }
-    HIP_TRY(hipGraphLaunch(s.loop_exec, st));
+    if (!chunked) {
+      HIP_TRY(hipGraphLaunch(s.loop_exec, st));
+    } else {
+      if (!s.done_host) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&s.done_host), 2 * sizeof(int32_t)));
+        for (auto &e : s.chunk_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      }
+      const int chunks = (max_iters + len - 1) / len;  // sweeps past max_iters are empty
+      for (int c = 0; c < chunks; ++c) {
+        HIP_TRY(hipGraphLaunch(s.loop_exec, st));
+        HIP_TRY(hipMemcpyAsync(&s.done_host[c & 1], &s.ctrl->done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(s.chunk_ev[c & 1], st));
+        if (c > 0) {
+          HIP_TRY(hipEventSynchronize(s.chunk_ev[(c - 1) & 1]));
+          if (s.done_host[(c - 1) & 1]) break;
+        }
+      }
+    }
   }
   if (timed) HIP_TRY(hipEventRecord(s.ev[2], st));
   if (renumber) {
