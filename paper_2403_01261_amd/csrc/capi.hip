@@ -233,7 +233,7 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
         dmalloc(&s.act[0], flag_bytes) != hipSuccess || dmalloc(&s.act[1], flag_bytes) != hipSuccess ||
         dmalloc(&s.list, cap) != hipSuccess || dmalloc(&s.parent, cap) != hipSuccess ||
         dmalloc(&s.rep, cap) != hipSuccess ||
-        dmalloc(&s.blk_counts, gsl::plan_blocks(cap) * gsl::kNumTiers) != hipSuccess ||
+        dmalloc(&s.blk_counts, gsl::plan_scratch(cap)) != hipSuccess ||
         dmalloc(&s.sigma, cap) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSL_ENOMEM, "device allocation of scratch for %lld vertices failed", (long long)n);

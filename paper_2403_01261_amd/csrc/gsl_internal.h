@@ -164,6 +164,8 @@ struct TierGrids {
 hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *blk_counts,
                        Counters *ctr, const TierConfig &cfg, hipStream_t s);
 int64_t plan_blocks(int64_t n);
+// Entries of the plan's scratch array (blk_counts) for n vertices.
+int64_t plan_scratch(int64_t n);
 
 // Sweep kernel of one tier with the given variant (kVariants index).
 hipError_t launch_sweep_tier(int variant, const SweepArgs &a, const int32_t *list, int64_t first,

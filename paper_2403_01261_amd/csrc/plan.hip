@@ -37,20 +37,32 @@ __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restri
   }
   __syncthreads();
   const int64_t v = (int64_t)blockIdx.x * kPlanBlock + threadIdx.x;
+  const int lane = threadIdx.x % kWave;
   int64_t d = 0;
+  int t = -1;
   if (v < n) {
     d = off[v + 1] - off[v];
-    const int t = tier_of(d, tb);
-    atomicAdd(&cnt[t], 1);
-    if (d > 0) atomicAdd(&ecnt[t], (unsigned long long)d);
+    t = tier_of(d, tb);
   }
-  unsigned long long m = (unsigned long long)(d > 0 ? d : 0);
+  // Per wave: one LDS add per tier present (ballot), with the wave's sum of
+  // the degrees of that tier -- not one contended LDS atomic per vertex.
+  for (int k = 0; k < kNumTiers; ++k) {
+    const unsigned long long m = __ballot(t == k);
+    if (!m) continue;
+    unsigned long long e = t == k && d > 0 ? (unsigned long long)d : 0ull;
+    e = wave_sum(e);
+    if (lane == 0) {
+      atomicAdd(&cnt[k], __popcll(m));
+      if (e) atomicAdd(&ecnt[k], e);
+    }
+  }
+  unsigned long long mx = (unsigned long long)(d > 0 ? d : 0);
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {
-    const unsigned long long y = __shfl_xor(m, o, kWave);
-    m = y > m ? y : m;
+    const unsigned long long y = __shfl_xor(mx, o, kWave);
+    mx = y > mx ? y : mx;
   }
-  if (threadIdx.x % kWave == 0) dmax[threadIdx.x / kWave] = m;
+  if (lane == 0) dmax[threadIdx.x / kWave] = mx;
   __syncthreads();
   if (threadIdx.x < kNumTiers) {
     blk_counts[(int64_t)blockIdx.x * kNumTiers + threadIdx.x] = cnt[threadIdx.x];
@@ -64,8 +76,59 @@ __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restri
   }
 }
 
-// One block: exclusive scan of blk_counts over blocks for every tier (in
-// place), tier totals and tier starts (tiers laid out in order 9..0).
+// The scan of blk_counts ([block][tier], exclusive over blocks for every
+// tier) in three steps: plan_scan_sums totals each group of kPlanBlock
+// blocks, plan_scan (one workgroup) scans the group totals and sets the tier
+// totals and starts, plan_scan_add scans inside each group from its base.
+__global__ __launch_bounds__(kPlanBlock) void plan_scan_sums(const int64_t *__restrict__ blk, int64_t nblk,
+                                                             int64_t *__restrict__ grp) {
+  __shared__ int64_t ws[kPlanBlock / kWave][kNumTiers];
+  const int64_t i = (int64_t)blockIdx.x * kPlanBlock + threadIdx.x;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int t = 0; t < kNumTiers; ++t) {
+    unsigned long long x = i < nblk ? (unsigned long long)blk[i * kNumTiers + t] : 0ull;
+    x = wave_sum(x);
+    if (lane == 0) ws[wid][t] = (int64_t)x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumTiers) {
+    int64_t sum = 0;
+    for (int w = 0; w < kPlanBlock / kWave; ++w) sum += ws[w][threadIdx.x];
+    grp[(int64_t)blockIdx.x * kNumTiers + threadIdx.x] = sum;
+  }
+}
+
+__global__ __launch_bounds__(kPlanBlock) void plan_scan_add(int64_t *__restrict__ blk, int64_t nblk,
+                                                            const int64_t *__restrict__ grp) {
+  __shared__ int64_t ws[kPlanBlock / kWave][kNumTiers];
+  const int64_t i = (int64_t)blockIdx.x * kPlanBlock + threadIdx.x;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  int64_t x[kNumTiers], incl[kNumTiers];
+#pragma unroll
+  for (int t = 0; t < kNumTiers; ++t) {
+    x[t] = i < nblk ? blk[i * kNumTiers + t] : 0;
+    incl[t] = x[t];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t y = __shfl_up(incl[t], o, kWave);
+      incl[t] += lane >= o ? y : 0;
+    }
+    if (lane == kWave - 1) ws[wid][t] = incl[t];
+  }
+  __syncthreads();
+  if (i < nblk) {
+#pragma unroll
+    for (int t = 0; t < kNumTiers; ++t) {
+      int64_t base = grp[(int64_t)blockIdx.x * kNumTiers + t];
+      for (int w = 0; w < wid; ++w) base += ws[w][t];
+      blk[i * kNumTiers + t] = base + incl[t] - x[t];
+    }
+  }
+}
+
+// One block: exclusive scan of the group totals over groups for every tier
+// (in place), tier totals and tier starts (tiers laid out in order 9..0).
 __global__ __launch_bounds__(kPlanBlock) void plan_scan(int64_t *__restrict__ blk_counts,
                                                         int64_t nblk, Counters *ctr) {
   __shared__ int64_t part[kPlanBlock];
@@ -134,6 +197,11 @@ __global__ __launch_bounds__(kPlanBlock) void plan_scatter(const int64_t *__rest
 
 int64_t plan_blocks(int64_t n) { return (n + kPlanBlock - 1) / kPlanBlock; }
 
+int64_t plan_scratch(int64_t n) {
+  const int64_t nblk = plan_blocks(n);
+  return (nblk + plan_blocks(nblk)) * kNumTiers;
+}
+
 // list receives every vertex grouped by tier (9 first, 0 last); entry
 // tier_start[t] is the first vertex of tier t.
 hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *blk_counts,
@@ -142,8 +210,12 @@ hipError_t launch_plan(const int64_t *off, int64_t n, int32_t *list, int64_t *bl
   if (nblk <= 0) return hipSuccess;
   TierBounds tb;
   for (int t = 0; t < kNumTiers; ++t) tb.b[t] = cfg.bound[t];
+  const int64_t ngrp = plan_blocks(nblk);
+  int64_t *grp = blk_counts + nblk * kNumTiers;  // group totals (plan_scratch)
   plan_count<<<(unsigned)nblk, kPlanBlock, 0, s>>>(off, n, blk_counts, ctr, tb);
-  plan_scan<<<1, kPlanBlock, 0, s>>>(blk_counts, nblk, ctr);
+  plan_scan_sums<<<(unsigned)ngrp, kPlanBlock, 0, s>>>(blk_counts, nblk, grp);
+  plan_scan<<<1, kPlanBlock, 0, s>>>(grp, ngrp, ctr);
+  plan_scan_add<<<(unsigned)ngrp, kPlanBlock, 0, s>>>(blk_counts, nblk, grp);
   plan_scatter<<<(unsigned)nblk, kPlanBlock, 0, s>>>(off, n, blk_counts, ctr, list, tb);
   return hipGetLastError();
 }
