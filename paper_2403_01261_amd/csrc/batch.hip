@@ -51,6 +51,17 @@ __global__ __launch_bounds__(kBlock) void globalize_cols(const int32_t *__restri
                                                          int64_t nnz, int32_t *__restrict__ out) {
   for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < nnz; t0 += (int64_t)gridDim.x * kTile) {
     int64_t g = tile_graph(edge_base, G, t0);
+    const int64_t tend = t0 + kTile < nnz ? t0 + kTile : nnz;
+    if (edge_base[g + 1] >= tend) {
+      // the whole tile lies in graph g (most tiles): one base, all loads at once
+      const int32_t vb = (int32_t)vtx_base[g];
+#pragma unroll
+      for (int j = 0; j < kPerThread; ++j) {
+        const int64_t e = t0 + (int64_t)j * kBlock + threadIdx.x;
+        if (e < tend) out[e] = cols[e] + vb;
+      }
+      continue;
+    }
 #pragma unroll 4
     for (int j = 0; j < kPerThread; ++j) {
       const int64_t e = t0 + (int64_t)j * kBlock + threadIdx.x;

@@ -443,3 +443,20 @@ def test_vertex_ids_above_2_pow_30(gsl):
             torch.cuda.empty_cache()
     finally:
         gsl.gsl_set_tiers(None)
+
+
+def test_chunked_loop_launches_honour_the_cap(gsl):
+    """Graphs of at least 2^23 entries launch the loop graph two sweeps at a
+    time and stop queuing chunks once the loop has stopped.  Caps of 1, 2, 3
+    and 5 sweeps (odd ones end inside a chunk), convergence inside a chunk
+    (tolerance 0: stop on a sweep without change) and the default tolerance
+    all give the oracle's labels, sweep counts and change counts."""
+    g = graphgen.planted(200000, 200, 0.05, 200000, 5)
+    assert g.nnz >= 1 << 23
+    for mi, tol in ((1, 0.0), (2, 0.0), (3, 0.0), (5, 0.0), (20, 0.0), (20, 0.05)):
+        say("chunked loop: max_iters=%d tol=%g" % (mi, tol))
+        r = oracle.lpa(g, mi, tol)
+        lab, st = run_gpu(gsl, g, mi, tol)
+        assert st["iterations"] == r.iterations, (mi, tol)
+        assert list(st["changed"][:r.iterations]) == list(r.dn[:r.iterations]), (mi, tol)
+        np.testing.assert_array_equal(lab, r.labels, err_msg="max_iters=%d tol=%g" % (mi, tol))
