@@ -324,9 +324,8 @@ int64_t gsl_convergence_limit(int64_t n, double tolerance);
  * degrees (max_degree[l-1], max_degree[l]] and runs the sweep kernel
  * `variant`.  Variants differ in lanes per vertex, entries per lane, LDS
  * table size and workgroup size (gsl_tier_variant); a variant takes rows of
- * up to `capacity` entries.  The thread-per-vertex variants (group 1: 0, 15,
- * 16) serve level 0 and only level 0.  The choice changes speed, never
- * results.
+ * up to `capacity` entries; any variant may serve any level.  The choice
+ * changes speed, never results.
  */
 #define GSL_TIER_LEVELS 7
 typedef struct gsl_tier {
@@ -342,8 +341,10 @@ typedef struct gsl_variant_info {
 } gsl_variant_info;
 
 /* Sets the tiers of all later calls in this process (levels[GSL_TIER_LEVELS];
- * NULL restores the defaults: bounds 8/16/32/64/128/512/2048 with variants
- * 0/1/3/5/7/9/11).  GSL_EINVAL for an invalid table (nothing changes). */
+ * NULL restores the defaults: bounds 32/64/128/512/2048/4096/4096 with
+ * variants 16/6/8/9/11/13/13, the last level empty).  GSL_EINVAL for an
+ * invalid table (nothing changes).  gsl_lpa_f32 always runs the bounds
+ * 8/16/32/64/128/512/2048. */
 int gsl_set_tiers(const gsl_tier *levels);
 /* Current tiers into levels_out[GSL_TIER_LEVELS]. */
 int gsl_get_tiers(gsl_tier *levels_out);

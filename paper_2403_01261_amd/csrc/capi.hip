@@ -471,9 +471,9 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
   if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   if ((rc = ensure_scratch(s, n, max_iters))) return rc;
-  // fp32 weights run the fixed default tiers (their kernels are instantiated
-  // for those bounds only)
-  const gsl::TierConfig cfg = f32 ? gsl::kDefaultTiers : current_tiers();
+  // fp32 weights run fixed tiers (their kernels are instantiated for those
+  // bounds only)
+  const gsl::TierConfig cfg = f32 ? gsl::kF32Tiers : current_tiers();
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
   if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
@@ -484,8 +484,9 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   // Renumbered layout: chosen when vertices of degree > 64 hold most entries
   // (their labels are the usual gather targets).  Batches keep their layout
   // (per-graph vertex ranges).
-  int64_t heavy = 0;
-  for (int t = 5; t < gsl::kNumTiers; ++t) heavy += plan.tier_edges[t];
+  int64_t heavy = 0;  // entries of the tiers whose rows all have degree > 64
+  for (int t = 1; t < gsl::kNumTiers; ++t)
+    if (cfg.bound[t - 1] >= 64) heavy += plan.tier_edges[t];
   const bool renumber = !batch && (o.layout == 1 || (o.layout == 0 && 2 * heavy > nnz));
   const int64_t np = n - plan.tier_count[0];  // non-isolated vertices
   const int64_t *g_off = offsets;
@@ -1358,8 +1359,6 @@ int gsl_set_tiers(const gsl_tier *levels) {
       const int32_t v = levels[l].variant;
       const int64_t b = levels[l].max_degree;
       if (v < 0 || v >= gsl::kNumVariants) return fail(GSL_EINVAL, "level %d: no variant %d", l, v);
-      if ((l == 0) != gsl::variant_is_thread(v))
-        return fail(GSL_EINVAL, "level 0 takes a thread-per-vertex variant (0, 15, 16), the others a group variant");
       if (b < prev) return fail(GSL_EINVAL, "level %d: degree bounds must not decrease", l);
       if (b > gsl::variant_capacity(v))
         return fail(GSL_EINVAL, "level %d: bound %lld exceeds variant %d's %lld entries", l, (long long)b, v,
@@ -1427,6 +1426,6 @@ void gsl_release(void) {
   if (have) (void)hipSetDevice(cur);
 }
 
-const char *gsl_version(void) { return "gsl_lpa 0.1 (gfx950)"; }
+const char *gsl_version(void) { return "gsl_lpa 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -57,8 +57,14 @@ struct TierConfig {
   int64_t bound[kNumTiers];
   int variant[kNumTiers];
 };
-constexpr TierConfig kDefaultTiers = {{0, 8, 16, 32, 64, 128, 512, 2048, (int64_t)0x7fffffffffffffffLL},
-                                      {0, 0, 1, 3, 5, 7, 9, 11, 0}};
+// Default levels: a thread per vertex up to degree 32, then groups of 16,
+// 32 and 64 lanes, a 256-lane workgroup up to 2048 and a 512-lane workgroup
+// up to 4096 (the seventh level is left empty); hubs above.
+constexpr TierConfig kDefaultTiers = {{0, 32, 64, 128, 512, 2048, 4096, 4096, (int64_t)0x7fffffffffffffffLL},
+                                      {0, 16, 6, 8, 9, 11, 13, 13, 0}};
+// The fp32-weight kernels are instantiated for these bounds only.
+constexpr TierConfig kF32Tiers = {{0, 8, 16, 32, 64, 128, 512, 2048, (int64_t)0x7fffffffffffffffLL},
+                                  {0, 0, 1, 3, 5, 7, 9, 11, 0}};
 // Bounds as a kernel argument.
 struct TierBounds {
   int64_t b[kNumTiers];

@@ -8,12 +8,16 @@ on the result: every configuration gives the same labels.
 
 tune() runs a coordinate descent over the levels: for each level it tries the
 bounds {b/2, b, 2b} that keep the bounds non-decreasing, with every variant
-that can hold rows of that length, timing the production path (median wall
-time of a few runs of the workload: gsl_lpa calls on probe graphs, or any
-callable, such as a batched call) and keeping a change only when it is faster
-by more than the noise margin.  Two passes.  Results are cached as
-JSON per device (and library version and probe), so later runs just load
-them: load_or_tune().
+that can hold rows of that length (and holds at most four times as many),
+timing the production path (median wall time of a few runs of the workload:
+gsl_lpa calls on probe graphs, or any callable, such as a batched call) and
+keeping a change only when it is faster by more than the noise margin.  Two
+passes, from each of two starting tables (the defaults, whose first level
+runs a thread per vertex up to degree 32, and a finer one that starts a
+level at degree 8), and the faster result wins: one level moved at a time
+cannot shift every level up or down at once.  Results are cached as JSON per
+device (and library version and probe), so later runs just load them:
+load_or_tune().
 """
 from __future__ import annotations
 
@@ -25,7 +29,9 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 Levels = List[Tuple[int, int]]
 
-DEFAULT_LEVELS: Levels = [(8, 0), (16, 1), (32, 3), (64, 5), (128, 7), (512, 9), (2048, 11)]
+DEFAULT_LEVELS: Levels = [(32, 16), (64, 6), (128, 8), (512, 9), (2048, 11), (4096, 13), (4096, 13)]
+FINE_LEVELS: Levels = [(8, 0), (32, 16), (64, 6), (128, 8), (512, 9), (2048, 11), (4096, 13)]
+STARTS: List[Levels] = [DEFAULT_LEVELS, FINE_LEVELS]
 
 
 def cache_path() -> str:
@@ -36,7 +42,7 @@ def cache_path() -> str:
 def valid(levels: Levels, variants: Sequence[dict]) -> bool:
     prev = 0
     for k, (b, v) in enumerate(levels):
-        if not (0 <= v < len(variants)) or (k == 0) != (variants[v]["group"] == 1):
+        if not (0 <= v < len(variants)):
             return False
         if b < prev or b > variants[v]["capacity"]:
             return False
@@ -53,7 +59,7 @@ def options(levels: Levels, k: int, variants: Sequence[dict]) -> List[Tuple[int,
     out = []
     for b in bounds:
         for v, info in enumerate(variants):
-            if (k == 0) != (info["group"] == 1) or info["capacity"] < b:
+            if info["capacity"] < b or info["capacity"] > 4 * max(b, 8):
                 continue
             out.append((b, v))
     return out
@@ -153,7 +159,16 @@ def tune(run, probe: str, reps: int = 5, passes: int = 2, log=None) -> dict:
     if not callable(run):
         run = graphs_runner(run)
     variants = gsl_tier_variants()
-    res = search(lambda lv: time_levels(run, lv, reps), variants, passes=passes, log=log)
+    res = None
+    evals = 0
+    for start in STARTS:
+        r = search(lambda lv: time_levels(run, lv, reps), variants, start=start, passes=passes, log=log)
+        evals += r["evaluations"]
+        if res is None:
+            res = r
+        elif r["ms"] < res["ms"]:
+            res = dict(r, default_ms=res["default_ms"])
+    res["evaluations"] = evals
     gsl_set_tiers([tuple(x) for x in res["levels"]])
     res["when"] = time.strftime("%Y-%m-%dT%H:%M:%S")
     data = _read_cache()

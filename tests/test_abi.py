@@ -26,7 +26,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(gsl_[a-z_]+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_entry_points():
+def test_header_declares_the_path_entry_points():
     names = declared_functions()
     for required in ("gsl_lpa", "gsl_split", "gsl_modularity"):
         assert required in names
@@ -128,3 +128,20 @@ def test_convergence_limit_large_n_boundaries():
             k = gsl.gsl_convergence_limit(n, tol)
             assert k / n <= tol
             assert k == n or not ((k + 1) / n <= tol)
+
+
+def test_default_tiers_match_the_tuner_and_any_variant_serves_any_level():
+    """gsl_set_tiers / gsl_get_tiers are host-only: the library's default
+    table is the autotuner's first starting point, and a thread-per-vertex
+    variant may serve a later level (bounds only need to fit capacities)."""
+    gsl, _ = _lib()
+    from paper_2403_01261_amd import tune
+    try:
+        gsl.gsl_set_tiers(None)
+        assert gsl.gsl_get_tiers() == tune.DEFAULT_LEVELS
+        gsl.gsl_set_tiers(tune.FINE_LEVELS)
+        assert gsl.gsl_get_tiers() == tune.FINE_LEVELS
+        with pytest.raises(gsl.GslError):
+            gsl.gsl_set_tiers([(8, 0), (64, 16), (128, 8), (512, 9), (2048, 11), (4096, 13), (4096, 13)])
+    finally:
+        gsl.gsl_set_tiers(None)

@@ -268,12 +268,8 @@ def _random_levels(rng, variants):
                                                     1000, 2048], size=7))
         bounds[0] = min(bounds[0], 32)
         levels = []
-        for k, b in enumerate(bounds):
-            if k == 0:
-                ok = [v for v in range(len(variants)) if variants[v]["group"] == 1 and variants[v]["capacity"] >= b]
-                levels.append((b, int(rng.choice(ok))))
-                continue
-            ok = [v for v in range(len(variants)) if variants[v]["group"] > 1 and variants[v]["capacity"] >= b]
+        for b in bounds:
+            ok = [v for v in range(len(variants)) if variants[v]["capacity"] >= b]
             levels.append((b, int(rng.choice(ok))))
         return levels
 

@@ -21,30 +21,31 @@ def test_defaults_are_valid_and_options_respect_bounds():
     bad[3] = (20, 5)  # below level 2's bound
     assert not tune.valid(bad, VARIANTS)
     bad = list(tune.DEFAULT_LEVELS)
-    bad[1] = (8, 0)  # thread variant outside level 0
-    assert not tune.valid(bad, VARIANTS)
-    bad[1] = (16, 15)
+    bad[1] = (64, 99)  # no such variant
     assert not tune.valid(bad, VARIANTS)
     ok = list(tune.DEFAULT_LEVELS)
-    ok[0] = (32, 16)  # a wider thread variant on level 0
-    ok[1] = (32, 3)
+    ok[1] = (64, 6)  # a group variant, and a thread variant on a later level
+    ok[2] = (64, 16)
+    assert not tune.valid(ok, VARIANTS)  # thread<32> cannot hold degree 64
+    ok[2] = (128, 8)
     assert tune.valid(ok, VARIANTS)
-    for k in range(7):
-        for b, v in tune.options(tune.DEFAULT_LEVELS, k, VARIANTS):
-            trial = list(tune.DEFAULT_LEVELS)
-            trial[k] = (b, v)
-            assert VARIANTS[v]["capacity"] >= b
-            assert (k == 0) == (VARIANTS[v]["group"] == 1)
+    assert tune.valid(tune.FINE_LEVELS, VARIANTS)
+    for start in tune.STARTS:
+        for k in range(7):
+            opts = tune.options(start, k, VARIANTS)
+            assert opts
+            for b, v in opts:
+                assert b <= VARIANTS[v]["capacity"] <= 4 * max(b, 8)
 
 
 def test_search_finds_the_cheaper_configuration():
-    # synthetic cost: variant 4 is cheaper than 3 at level 2, and a level-4
-    # bound of 256 with variant 9 beats 128/7; everything else neutral
+    # synthetic cost: variant 7 is cheaper than 8 at level 2, and a level-3
+    # bound of 256 with variant 9 beats 512/9; everything else neutral
     def cost(levels):
         c = 10.0
-        if levels[2][1] == 4:
+        if levels[2][1] == 7:
             c -= 1.0
-        if levels[4] == (256, 9):
+        if tuple(levels[3]) == (256, 9):
             c -= 2.0
         return c
 
@@ -52,7 +53,7 @@ def test_search_finds_the_cheaper_configuration():
     res = tune.search(lambda lv: (seen.append(list(lv)), cost(lv))[1], VARIANTS)
     assert res["default_ms"] == 10.0
     assert res["ms"] == 7.0
-    assert res["levels"][2][1] == 4 and tuple(res["levels"][4]) == (256, 9)
+    assert res["levels"][2][1] == 7 and tuple(res["levels"][3]) == (256, 9)
     assert all(tune.valid(lv, VARIANTS) for lv in seen)
     assert res["evaluations"] == len(seen)
 
