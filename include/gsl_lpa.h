@@ -82,9 +82,10 @@ typedef struct gsl_stats {
   int64_t max_degree;
   float ms_plan, ms_sweeps, ms_split, ms_total;
   float ms_sweep[GSL_STATS_MAX_ITERS];
-  /* Per degree tier (index 0 = isolated vertices, 1..8 = the sweep kernels
-   * in order of increasing degree, 8 = rows longer than 2048; index 9 is
-   * unused), summed over all sweeps of the call. */
+  /* Per degree tier (index 0 = isolated vertices, 1..7 = the levels of the
+   * tier table in order of increasing degree, 8 = hub rows, longer than the
+   * last level's bound; index 9 is unused), summed over all sweeps of the
+   * call. */
   int64_t tier_vertices[GSL_STATS_TIERS];   /* vertices in the tier */
   int64_t tier_launches[GSL_STATS_TIERS];   /* sweep kernel launches */
   int64_t tier_processed[GSL_STATS_TIERS];  /* vertices scanned */
