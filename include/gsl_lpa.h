@@ -342,8 +342,8 @@ typedef struct gsl_variant_info {
 } gsl_variant_info;
 
 /* Sets the tiers of all later calls in this process (levels[GSL_TIER_LEVELS];
- * NULL restores the defaults: bounds 32/64/128/512/2048/4096/4096 with
- * variants 16/6/8/9/11/13/13, the last level empty).  GSL_EINVAL for an
+ * NULL restores the defaults: bounds 32/64/128/512/1024/2048/4096 with
+ * variants 16/6/8/9/17/11/13).  GSL_EINVAL for an
  * invalid table (nothing changes).  gsl_lpa_f32 always runs the bounds
  * 8/16/32/64/128/512/2048. */
 int gsl_set_tiers(const gsl_tier *levels);

@@ -26,7 +26,7 @@ constexpr int kHubTier = 8;
 struct SweepVariant {
   int group, log2s, block, per_lane;
 };
-constexpr int kNumVariants = 17;
+constexpr int kNumVariants = 18;
 constexpr SweepVariant kVariants[kNumVariants] = {
     {1, 0, 256, 8},     // 0: thread per vertex, row in registers (d <= 8)
     {8, 5, 256, 2},     // 1: d <= 16
@@ -45,9 +45,8 @@ constexpr SweepVariant kVariants[kNumVariants] = {
     {1024, 14, 1024, 8},  // 14: d <= 8192 (128 KB table, one workgroup per CU)
     {1, 0, 256, 16},    // 15: thread per vertex, d <= 16
     {1, 0, 256, 32},    // 16: thread per vertex, d <= 32
+    {256, 11, 256, 4},  // 17: d <= 1024, one workgroup per vertex (16 KB table)
 };
-// A thread-per-vertex variant (group 1) may only serve the first level.
-constexpr bool variant_is_thread(int v) { return kVariants[v].group == 1; }
 constexpr int64_t variant_capacity(int v) { return (int64_t)kVariants[v].group * kVariants[v].per_lane; }
 
 // Degree tiers of one call: tier t (1..7) takes degrees (bound[t-1],
@@ -58,10 +57,10 @@ struct TierConfig {
   int variant[kNumTiers];
 };
 // Default levels: a thread per vertex up to degree 32, then groups of 16,
-// 32 and 64 lanes, a 256-lane workgroup up to 2048 and a 512-lane workgroup
-// up to 4096 (the seventh level is left empty); hubs above.
-constexpr TierConfig kDefaultTiers = {{0, 32, 64, 128, 512, 2048, 4096, 4096, (int64_t)0x7fffffffffffffffLL},
-                                      {0, 16, 6, 8, 9, 11, 13, 13, 0}};
+// 32 and 64 lanes, 256-lane workgroups up to 1024 (2,048-slot table) and
+// 2048 (4,096 slots), and a 512-lane workgroup up to 4096; hubs above.
+constexpr TierConfig kDefaultTiers = {{0, 32, 64, 128, 512, 1024, 2048, 4096, (int64_t)0x7fffffffffffffffLL},
+                                      {0, 16, 6, 8, 9, 17, 11, 13, 0}};
 // The fp32-weight kernels are instantiated for these bounds only.
 constexpr TierConfig kF32Tiers = {{0, 8, 16, 32, 64, 128, 512, 2048, (int64_t)0x7fffffffffffffffLL},
                                   {0, 0, 1, 3, 5, 7, 9, 11, 0}};

@@ -29,7 +29,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 Levels = List[Tuple[int, int]]
 
-DEFAULT_LEVELS: Levels = [(32, 16), (64, 6), (128, 8), (512, 9), (2048, 11), (4096, 13), (4096, 13)]
+DEFAULT_LEVELS: Levels = [(32, 16), (64, 6), (128, 8), (512, 9), (1024, 17), (2048, 11), (4096, 13)]
 FINE_LEVELS: Levels = [(8, 0), (32, 16), (64, 6), (128, 8), (512, 9), (2048, 11), (4096, 13)]
 STARTS: List[Levels] = [DEFAULT_LEVELS, FINE_LEVELS]
 

@@ -145,3 +145,14 @@ def test_default_tiers_match_the_tuner_and_any_variant_serves_any_level():
             gsl.gsl_set_tiers([(8, 0), (64, 16), (128, 8), (512, 9), (2048, 11), (4096, 13), (4096, 13)])
     finally:
         gsl.gsl_set_tiers(None)
+
+
+def test_variant_menu_matches_the_tuner_tests():
+    """gsl_tier_variant (host-only) reports the menu the autotuner's CPU tests
+    model: same order, lanes per vertex and capacities."""
+    gsl, _ = _lib()
+    from tests.test_tune import VARIANTS
+    menu = gsl.gsl_tier_variants()
+    assert len(menu) == len(VARIANTS)
+    for a, b in zip(menu, VARIANTS):
+        assert (a["group"], a["capacity"]) == (b["group"], b["capacity"])
