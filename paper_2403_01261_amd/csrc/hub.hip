@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
   __shared__ unsigned long long tab[kTabSlots];
   __shared__ int pre[kChunkGroup + 1];
   __shared__ int scan_part[kMergeBlock];
-  __shared__ int claimed, overflow;
+  __shared__ int claimed, overflow, records;
   __shared__ unsigned long long red[kMergeBlock / kWave];
   SweepView sv;
   if (!sweep_view(a, sv)) return;
@@ -241,6 +241,19 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
   const int64_t c0 = h.L.chunk_start[k], nc = h.L.chunk_start[k + 1] - c0;
   const int32_t *gh = h.hist + (h.L.hist_start[k] - h.L.hist_start[h.k0]);
   const unsigned long long *stage = h.staging + (c0 - h.L.chunk_start[h.k0]) * kHubChunk;
+  // The partition count is sized for rows whose labels are all distinct.
+  // When the hub's (label, sum) records of all partitions fit one table --
+  // usual once the labels have merged -- workgroup 0 merges them all and the
+  // others return.
+  if (threadIdx.x == 0) records = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t i = threadIdx.x; i < nc; i += kMergeBlock) mine += gh[i * (P + 1) + P];
+  if (mine) atomicAdd(&records, mine);
+  __syncthreads();
+  const bool whole = records <= kMergeCap;  // uniform
+  if (whole && p > 0) return;
+  const int p_lo = whole ? 0 : p, p_hi = whole ? P : p + 1;  // partitions merged here
   unsigned long long best = 0;
   for (uint32_t R = 1;; R <<= 1) {
     bool ok = true;
@@ -256,7 +269,7 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
         const int gn = (int)(nc - g0 < kChunkGroup ? nc - g0 : kChunkGroup);
         for (int i = threadIdx.x; i < gn; i += kMergeBlock) {
           const int32_t *hc = gh + (g0 + i) * (P + 1);
-          pre[i] = hc[p + 1] - hc[p];
+          pre[i] = hc[p_hi] - hc[p_lo];
         }
         __syncthreads();
         block_exclusive_scan<kMergeBlock>(pre, gn, scan_part);
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
               hi = mid;
           }
           const int32_t *hc = gh + (g0 + lo) * (P + 1);
-          const unsigned long long xv = stage[(g0 + lo) * kHubChunk + hc[p] + (t - pre[lo])];
+          const unsigned long long xv = stage[(g0 + lo) * kHubChunk + hc[p_lo] + (t - pre[lo])];
           const uint32_t label = (uint32_t)(xv >> 32);
           if (R > 1 && (sub_of(label) & (R - 1)) != r) continue;
           if (__hip_atomic_load(&overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) continue;
