@@ -66,6 +66,11 @@ struct Scratch {
   int64_t ctr_bytes = 0;
   Counters *ctr = nullptr;
   Counters *ctr_host = nullptr;  // pinned mirror (with the per-sweep arrays)
+  // pinned staging for small device-to-host reads (a pageable destination
+  // makes every copy a synchronous round trip): kPinSmall words, then the
+  // hub layout
+  int64_t *pin = nullptr;
+  int64_t pin_cap = 0;
   // hub tier layout (prefix sums over the hubs of the current graph)
   int64_t hub_cap = 0;
   int64_t *hub_chunk_start = nullptr, *hub_part_start = nullptr, *hub_hist_start = nullptr;
@@ -164,6 +169,7 @@ void free_scratch(Scratch &s) {
   hipFree(s.hub_staging);
   hipFree(s.hub_hist);
   if (s.ctr_host) hipHostFree(s.ctr_host);
+  if (s.pin) hipHostFree(s.pin);
   for (auto &e : s.ev)
     if (e) hipEventDestroy(e);
   for (auto &e : s.pool) hipEventDestroy(e);
@@ -282,9 +288,30 @@ int get_scratch(Scratch **out) {
 
 bool bad_tolerance(double t) { return !(t >= 0.0 && t <= 1.0); }
 
+constexpr int64_t kPinSmall = 16;  // words of Scratch::pin before the hub layout
+
+// Pinned host staging of at least `words` int64 words.
+int ensure_pinned(Scratch &s, int64_t words) {
+  if (words <= s.pin_cap) return GSL_OK;
+  if (s.pin) hipHostFree(s.pin);
+  s.pin = nullptr;
+  s.pin_cap = 0;
+  const int64_t cap = words < 4096 ? 4096 : words;
+  if (hipHostMalloc(reinterpret_cast<void **>(&s.pin), (size_t)cap * sizeof(int64_t), hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    s.pin = nullptr;
+    return fail(GSL_ENOMEM, "pinned host allocation failed");
+  }
+  s.pin_cap = cap;
+  return GSL_OK;
+}
+
 // Reads offsets[0] and offsets[n]; checks offsets[0] == 0 and nnz >= 0.
-int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st) {
-  int64_t ends[2] = {0, 0};
+// `pinned` (2 words of pinned host memory, or NULL) makes it one round trip.
+int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st, int64_t *pinned = nullptr) {
+  int64_t local[2] = {0, 0};
+  int64_t *ends = pinned ? pinned : local;
   HIP_TRY(hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(&ends[1], offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -329,13 +356,16 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
   HIP_TRY(hipMemsetAsync(s.hub_rowsum, 0, (size_t)H * sizeof(unsigned long long), st));
   gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
   HIP_TRY(gsl::launch_hub_layout(offsets, hubs, H, L, st));
-  s.h_chunk.resize((size_t)H + 1);
-  s.h_part.resize((size_t)H + 1);
-  s.h_hist.resize((size_t)H + 1);
-  HIP_TRY(hipMemcpyAsync(s.h_chunk.data(), s.hub_chunk_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(s.h_part.data(), s.hub_part_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(s.h_hist.data(), s.hub_hist_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  int rc = ensure_pinned(s, kPinSmall + 3 * (H + 1));
+  if (rc) return rc;
+  int64_t *ph = s.pin + kPinSmall;
+  HIP_TRY(hipMemcpyAsync(ph, s.hub_chunk_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(ph + (H + 1), s.hub_part_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(ph + 2 * (H + 1), s.hub_hist_start, (size_t)(H + 1) * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  s.h_chunk.assign(ph, ph + (H + 1));
+  s.h_part.assign(ph + (H + 1), ph + 2 * (H + 1));
+  s.h_hist.assign(ph + 2 * (H + 1), ph + 3 * (H + 1));
   constexpr int64_t kHubStagingBytes = (int64_t)4 << 30;
   const int64_t chunk_cap = kHubStagingBytes / ((int64_t)gsl::kHubChunk * 8);
   int64_t k0 = 0;
@@ -468,7 +498,8 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if (!offsets || !labels_out) return fail(GSL_EINVAL, "offsets and labels_out must not be NULL");
   int rc = GSL_OK;
   int64_t nnz = 0;
-  if ((rc = read_nnz(offsets, n, &nnz, st))) return rc;
+  if ((rc = ensure_pinned(s, kPinSmall))) return rc;
+  if ((rc = read_nnz(offsets, n, &nnz, st, s.pin))) return rc;
   if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   if ((rc = ensure_scratch(s, n, max_iters))) return rc;
   // fp32 weights run fixed tiers (their kernels are instantiated for those
@@ -759,10 +790,12 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
                              hipMemcpyDeviceToHost, st));
   }
   if (timed) HIP_TRY(hipEventRecord(s.ev[3], st));
-  gsl::SweepCtrl fc;
-  HIP_TRY(hipMemcpyAsync(&fc, s.ctrl, sizeof(fc), hipMemcpyDeviceToHost, st));
+  static_assert(sizeof(gsl::SweepCtrl) <= (kPinSmall - 2) * sizeof(int64_t), "loop state fits the pinned words");
+  gsl::SweepCtrl *pfc = reinterpret_cast<gsl::SweepCtrl *>(s.pin + 2);
+  HIP_TRY(hipMemcpyAsync(pfc, s.ctrl, sizeof(gsl::SweepCtrl), hipMemcpyDeviceToHost, st));
   if (stats) HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, (size_t)s.ctr_bytes, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  const gsl::SweepCtrl fc = *pfc;
   if (fc.error)
     return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; weights are summed in 32 bits");
   const int32_t it = fc.it;
