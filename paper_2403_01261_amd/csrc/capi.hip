@@ -308,10 +308,8 @@ int ensure_pinned(Scratch &s, int64_t words) {
 }
 
 // Reads offsets[0] and offsets[n]; checks offsets[0] == 0 and nnz >= 0.
-// `pinned` (2 words of pinned host memory, or NULL) makes it one round trip.
-int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st, int64_t *pinned = nullptr) {
-  int64_t local[2] = {0, 0};
-  int64_t *ends = pinned ? pinned : local;
+int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st) {
+  int64_t ends[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(&ends[1], offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -321,11 +319,19 @@ int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st, in
   return GSL_OK;
 }
 
-// Runs the degree plan and copies the counters block to the host mirror.
-int run_plan(Scratch &s, const int64_t *offsets, int64_t n, const gsl::TierConfig &cfg, hipStream_t st) {
+// Runs the degree plan and copies the counters block to the host mirror;
+// with `ends` (2 words of pinned host memory) also offsets[0] and offsets[n],
+// in the same round trip.  The plan reads offsets only, so it may run before
+// they are validated.
+int run_plan(Scratch &s, const int64_t *offsets, int64_t n, const gsl::TierConfig &cfg, hipStream_t st,
+             int64_t *ends = nullptr) {
   HIP_TRY(hipMemsetAsync(s.ctr, 0, (size_t)s.ctr_bytes, st));
   HIP_TRY(gsl::launch_plan(offsets, n, s.list, s.blk_counts, s.ctr, cfg, st));
   HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  if (ends) {
+    HIP_TRY(hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&ends[1], offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  }
   HIP_TRY(hipStreamSynchronize(st));
   return GSL_OK;
 }
@@ -497,16 +503,17 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if (n == 0) return GSL_OK;
   if (!offsets || !labels_out) return fail(GSL_EINVAL, "offsets and labels_out must not be NULL");
   int rc = GSL_OK;
-  int64_t nnz = 0;
   if ((rc = ensure_pinned(s, kPinSmall))) return rc;
-  if ((rc = read_nnz(offsets, n, &nnz, st, s.pin))) return rc;
-  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   if ((rc = ensure_scratch(s, n, max_iters))) return rc;
   // fp32 weights run fixed tiers (their kernels are instantiated for those
   // bounds only)
   const gsl::TierConfig cfg = f32 ? gsl::kF32Tiers : current_tiers();
   if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
-  if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
+  if ((rc = run_plan(s, offsets, n, cfg, st, s.pin))) return rc;
+  if (s.pin[0] != 0) return fail(GSL_EINVAL, "offsets[0] must be 0 (got %lld)", (long long)s.pin[0]);
+  if (s.pin[1] < 0) return fail(GSL_EINVAL, "offsets[n] must be >= 0");
+  const int64_t nnz = s.pin[1];
+  if (nnz > 0 && !cols) return fail(GSL_EINVAL, "cols must not be NULL when offsets[n] > 0");
   Counters plan = *s.ctr_host;
   // Tier t is the id range [tier_start[t], +tier_count[t]) of s.list; hubs
   // (tier 8) come first, isolated vertices (tier 0) last.

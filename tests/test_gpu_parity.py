@@ -456,3 +456,22 @@ def test_chunked_loop_launches_honour_the_cap(gsl):
         assert st["iterations"] == r.iterations, (mi, tol)
         assert list(st["changed"][:r.iterations]) == list(r.dn[:r.iterations]), (mi, tol)
         np.testing.assert_array_equal(lab, r.labels, err_msg="max_iters=%d tol=%g" % (mi, tol))
+
+
+def test_lpa_rejects_offsets_not_starting_at_zero(gsl):
+    """offsets[0] != 0 and a negative offsets[n] are reported as GSL_EINVAL
+    (read back with the plan's counters), and the next call runs normally."""
+    g = workloads.make(1)
+    off, cols, w = to_device(g)
+    bad = off.clone()
+    bad[0] = 1
+    with pytest.raises(gsl.GslError) as e:
+        gsl.gsl_lpa_ex(bad, cols, w)
+    assert e.value.code == gsl.GSL_EINVAL
+    bad = torch.zeros_like(off)
+    bad[-1] = -1
+    with pytest.raises(gsl.GslError) as e:
+        gsl.gsl_lpa_ex(bad, cols, w)
+    assert e.value.code == gsl.GSL_EINVAL
+    lab, st = gsl.gsl_lpa_ex(off, cols, w)
+    np.testing.assert_array_equal(lab.cpu().numpy(), oracle.lpa(g).labels)
