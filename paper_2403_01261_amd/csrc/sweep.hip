@@ -74,7 +74,7 @@ __device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCoun
 // no 64-bit address registers.
 // ---------------------------------------------------------------------------
 __device__ const int32_t kZeroI32 = 0;
-__device__ const uint8_t kZeroU8 = 0, kOneU8 = 1;
+__device__ const uint8_t kZeroU8 = 0;
 
 template <bool O32>
 __device__ __forceinline__ uint32_t gather_label(const int32_t *__restrict__ C, int32_t c) {
@@ -94,19 +94,19 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
     const int32_t v = list ? list[first + idx] : (int32_t)(first + idx);
-    // Everything that depends on v alone is loaded at once (absent arrays
-    // read constants instead of branching: a branch would make the wave wait
-    // for every load issued before it), so a vertex waits for four dependent
-    // loads before its gathers instead of six.
+    // A sparse sweep reads the one-byte flag of every listed vertex first.
+    // Then everything that depends on v alone is loaded at once (absent
+    // arrays read constants instead of branching: a branch would make the
+    // wave wait for every load issued before it), so a vertex of a dense
+    // sweep waits for four dependent loads before its gathers instead of six.
+    if (!sv.dense && !sv.act[v]) continue;
     const int32_t *gp = a.gid ? a.gid + v : &kZeroI32;
-    const uint8_t *ap = sv.dense ? &kOneU8 : sv.act + v;
     const int64_t b = a.off[v];
     const int d = (int)(a.off[v + 1] - b);
     const int32_t g = *gp;
-    const bool on = *ap != 0;
     const uint32_t own = (uint32_t)a.C[v];
     const uint8_t *dp = a.gdone ? a.gdone + g : &kZeroU8;
-    if (!on || *dp) continue;
+    if (*dp) continue;
     uint32_t lab[D], w[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) lab[k] = k < d ? (uint32_t)a.cols[b + k] : (uint32_t)v;
