@@ -446,7 +446,7 @@ def main(argv=None):
         print(json.dumps(r))
         return 0
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
     if args.pmc_copy:
