@@ -148,9 +148,10 @@ def _short(name: str) -> str:
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int, kernel: str,
-                  commands: list) -> dict:
+                  commands: list, out_dir: str = None) -> dict:
     """Traffic of `kernel` per launch from FETCH_SIZE / WRITE_SIZE runs, each
-    scaled by the counter's reading for the plain COPY_BYTES copy."""
+    scaled by the counter's reading for the plain COPY_BYTES copy.  Writes
+    traffic.json and the kernel-trace summary into out_dir (profiles/)."""
     from graphgen import workloads
     fetch = _read_counter_csv(fetch_dir, "FETCH_SIZE")
     write = _read_counter_csv(write_dir, "WRITE_SIZE")
@@ -173,7 +174,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
     fetch_b = sum(kf) / len(kf) * 1024.0 * sf
     write_b = sum(kw) / len(kw) * 1024.0 * sw
     wname = workloads.NAMES[workload]
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    path = os.path.join(out_dir, "traffic.json")
     rec = {}
     if os.path.exists(path):
         with open(path) as f:
@@ -190,7 +192,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
     # Short text summary of the kernel trace next to it.
     stats = _kernel_stats(trace_dir)
     tag = kernel.replace("<", "-").replace(">", "").replace(", ", "-")
-    md = os.path.join(ROOT, "profiles", "%s_%s.md" % (wname, tag))
+    md = os.path.join(out_dir, "%s_%s.md" % (wname, tag))
     with open(md, "w") as f:
         f.write("# %s on %s\n\n" % (kernel, wname))
         f.write("Commands (repository root, MI355X):\n\n")

@@ -1,0 +1,72 @@
+"""bench.py's measurement logic on the CPU: the algorithmic bytes of a tier,
+the working-launch cut of a kernel trace, and the traffic summary scaled by
+the calibration copy (synthetic rocprofv3 CSV files)."""
+import csv
+import json
+import os
+
+import bench
+
+
+def test_tier_bytes_per_unit():
+    zero = {"vertices": 0, "launches": 0, "sparse_launches": 0, "processed": 0, "edges": 0, "changed": 0,
+            "marked": 0}
+
+    def one(**kw):
+        t = dict(zero)
+        t.update(kw)
+        return t
+
+    assert bench.tier_bytes(one(vertices=1, launches=1), False) == 4          # list entry
+    assert bench.tier_bytes(one(vertices=1, sparse_launches=1), False) == 1   # active flag
+    assert bench.tier_bytes(one(processed=1), False) == 20                    # two offsets + own label
+    assert bench.tier_bytes(one(edges=1), False) == 8                         # column + gathered label
+    assert bench.tier_bytes(one(edges=1), True) == 12                         # + weight
+    assert bench.tier_bytes(one(changed=1), False) == 5                       # new label + change flag
+    assert bench.tier_bytes(one(marked=1), False) == 1                        # neighbour flag
+    # a tier listed in 3 launches, one of them sparse
+    t = one(vertices=10, launches=3, sparse_launches=1, processed=25, edges=100, changed=7, marked=40)
+    assert bench.tier_bytes(t, True) == 10 * 3 * 4 + 10 + 25 * 20 + 100 * 12 + 7 * 5 + 40
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_kernel_stats_counts_working_launches(tmp_path):
+    rows = [["k<1>(args)", 0, 100_000], ["k<1>(args)", 200_000, 300_000], ["k<1>(args)", 400_000, 402_000],
+            ["other()", 500_000, 501_000]]
+    _write(str(tmp_path / "t" / "x_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    stats = {r["Name"]: r for r in bench._kernel_stats(str(tmp_path / "t"))}
+    k = stats["k<1>(args)"]
+    assert k["Calls"] == 3 and k["WorkCalls"] == 2 and k["WorkAvgNs"] == 100_000
+    assert abs(sum(r["Percentage"] for r in stats.values()) - 100.0) < 1e-9
+
+
+def test_summarize_pmc_scales_by_the_copy(tmp_path):
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    copy = "__amd_rocclr_copyBuffer"
+    kern = "void gsl::(anonymous namespace)::sweep_lds<8, 5, 256, 2>(gsl::SweepArgs)"
+    # the copy of 1 GiB reads as 0.5 GiB in FETCH_SIZE (scale 2) and 1 GiB in
+    # WRITE_SIZE (scale 1); a near-empty launch falls under the 5 % cut
+    _write(str(tmp_path / "f" / "f_counter_collection.csv"), hdr,
+           [[1, copy, "FETCH_SIZE", 524288.0], [2, kern, "FETCH_SIZE", 1000.0], [3, kern, "FETCH_SIZE", 3000.0],
+            [4, kern, "FETCH_SIZE", 10.0]])
+    _write(str(tmp_path / "w" / "w_counter_collection.csv"), hdr,
+           [[1, copy, "WRITE_SIZE", 1048576.0], [2, kern, "WRITE_SIZE", 100.0], [3, kern, "WRITE_SIZE", 300.0],
+            [4, kern, "WRITE_SIZE", 1.0]])
+    out = tmp_path / "profiles"
+    rec = bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "t"), 2,
+                              "sweep_lds<8, 5, 256, 2>", ["cmd"], out_dir=str(out))
+    assert rec["launches_counted"] == 2
+    assert rec["scale_fetch"] == 2.0 and rec["scale_write"] == 1.0
+    assert rec["fetch_bytes_per_launch"] == 2000 * 1024 * 2
+    assert rec["write_bytes_per_launch"] == 200 * 1024
+    assert rec["bytes_per_launch"] == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    saved = json.load(open(out / "traffic.json"))
+    assert saved["rmat-s22"]["sweep_lds<8, 5, 256, 2>"]["source_hash"] == bench.source_hash()
+    assert (out / "rmat-s22_sweep_lds-8-5-256-2.md").exists()
