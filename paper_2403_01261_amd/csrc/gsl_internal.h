@@ -26,7 +26,7 @@ constexpr int kHubTier = 8;
 struct SweepVariant {
   int group, log2s, block, per_lane;
 };
-constexpr int kNumVariants = 18;
+constexpr int kNumVariants = 19;
 constexpr SweepVariant kVariants[kNumVariants] = {
     {1, 0, 256, 8},     // 0: thread per vertex, row in registers (d <= 8)
     {8, 5, 256, 2},     // 1: d <= 16
@@ -46,6 +46,7 @@ constexpr SweepVariant kVariants[kNumVariants] = {
     {1, 0, 256, 16},    // 15: thread per vertex, d <= 16
     {1, 0, 256, 32},    // 16: thread per vertex, d <= 32
     {256, 11, 256, 4},  // 17: d <= 1024, one workgroup per vertex (16 KB table)
+    {1, 0, 256, 64},    // 18: thread per vertex, d <= 64
 };
 constexpr int64_t variant_capacity(int v) { return (int64_t)kVariants[v].group * kVariants[v].per_lane; }
 

@@ -456,6 +456,10 @@ hipError_t launch_sweep_tier(int variant, const SweepArgs &a, const int32_t *lis
     case 13: grid = launch_lds<512, 13, 512, 8>(a, list, first, count, s); break;
     case 14: grid = launch_lds<1024, 14, 1024, 8>(a, list, first, count, s); break;
     case 17: grid = launch_lds<256, 11, 256, 4>(a, list, first, count, s); break;
+    case 18:
+      grid = grid_for(count, 256, kMaxTierGrid);
+      launch_thread<64>(a, list, first, count, grid, s);
+      break;
     default:
       return hipErrorInvalidValue;
   }

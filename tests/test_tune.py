@@ -9,7 +9,7 @@ from paper_2403_01261_amd import tune
 # The library's variant menu (gsl_tier_variant), as capacities and groups.
 VARIANTS = [{"group": g, "per_lane": k, "capacity": g * k} for g, k in
             [(1, 8), (8, 2), (4, 4), (16, 2), (8, 4), (32, 2), (16, 4), (64, 2), (32, 4), (64, 8), (128, 4),
-             (256, 8), (512, 4), (512, 8), (1024, 8), (1, 16), (1, 32), (256, 4)]]
+             (256, 8), (512, 4), (512, 8), (1024, 8), (1, 16), (1, 32), (256, 4), (1, 64)]]
 
 
 def test_defaults_are_valid_and_options_respect_bounds():
