@@ -225,6 +225,28 @@ def calibration_copy():
     del src, dst
 
 
+def gather_reference(cols, n, reps=5):
+    """Random 4-byte gathers as a plain PyTorch kernel does them: an int32
+    array of n labels indexed by the workload's own column array (original
+    vertex order), timed with events on torch's stream.  The sweeps are bound
+    by such gathers (one per row entry), not by streaming bandwidth."""
+    import torch
+    lab = torch.arange(n, dtype=torch.int32, device=cols.device)
+    out = torch.empty_like(cols)
+    torch.index_select(lab, 0, cols, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.index_select(lab, 0, cols, out=out)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del lab, out
+    return {"gathers_per_s": cols.numel() / (ms / 1000.0), "ms": round(ms, 3),
+            "method": "torch.index_select of an int32 array of n labels by the column array "
+                      "(original vertex order), %d runs" % reps}
+
+
 def cpu_baseline(g, max_iters, tol, w32=None):
     import oracle
     t0 = time.perf_counter()
@@ -510,10 +532,12 @@ def main(argv=None):
     sweep_bytes = sum(tier_bytes(dict(st["tiers"][t], vertices=st["tiers"][t]["vertices"]), weighted)
                       for st in stats for t in range(1, NUM_TIERS)) / len(stats)
     last = stats[-1]
+    sweep_entries = sum(st["tiers"][t]["edges"] for st in stats for t in range(1, NUM_TIERS)) / len(stats)
     phases = {"ms_plan": round(sum(s["ms_plan"] for s in stats) / len(stats), 3),
               "ms_sweeps": round(sweep_ms, 3),
               "ms_split": round(sum(s["ms_split"] for s in stats) / len(stats), 3),
               "sweep_phase_GBps": round(sweep_bytes / (sweep_ms / 1000.0) / 1e9, 1) if sweep_ms else None,
+              "sweep_entries_per_s": sweep_entries / (sweep_ms / 1000.0) if sweep_ms else None,
               "ms_reorder": round(sum(s["ms_reorder"] for s in stats) / len(stats), 3),
               "renumbered": last["renumbered"],
               "ms_per_step_with_events": round(sum(s["ms_total"] for s in stats) / len(stats), 3),
@@ -531,6 +555,10 @@ def main(argv=None):
             split_cmp[tech] = {"ms": round(ms, 3), "rounds": rounds, "same_labels": same}
             log("split %s: %.3f ms, %d rounds" % (tech, ms, rounds))
 
+    gref = gather_reference(cols, g.n)
+    log("gather reference: %.3g gathers/s (sweep phase: %.3g row entries/s)" % (gref["gathers_per_s"],
+                                                                           phases["sweep_entries_per_s"] or 0))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
@@ -547,7 +575,7 @@ def main(argv=None):
                        "nnz": g.nnz, "max_iters": mi, "tolerance": tol,
                        "weights": ("fp32 array, fp64 sums" if args.weights_f32 else
                                    "uint32 array" if weighted else "NULL (unit)")},
-            "roofline": roofline, "cpu_baseline": cpu, "phases": phases, "tiers": tiers,
+            "roofline": roofline, "cpu_baseline": cpu, "phases": phases, "gather_reference": gref, "tiers": tiers,
             "split_techniques": split_cmp,
             "context": "paper: 844M edges/s, sk-2005 3.8B edges, 2x Xeon Gold 6226R, 64 threads"}
     print(json.dumps(line), flush=True)
