@@ -74,13 +74,24 @@ def tier_bytes(t: dict, weighted: bool) -> int:
             + t["changed"] * 5 + t["marked"] * 1)
 
 
-def source_hash() -> str:
+def _code_only(text: str) -> str:
+    """C++/HIP source without comments and with whitespace runs collapsed, so
+    that editing a comment does not count as a change of the kernels."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def source_hash(csrc: str = None) -> str:
+    """Hash of the kernel sources' code (the measured traffic in
+    profiles/traffic.json is reported only while it matches)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2403_01261_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2403_01261_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -10,12 +10,15 @@ namespace gsl {
 // ----------------------------------------------------------------------------
 // Degree tiers.  Every vertex with degree d > 0 is processed by the kernel of
 // the smallest tier whose bound is >= d; tier 0 holds isolated vertices, which
-// never change label.
-//   tier 1        : one thread per vertex, labels held in registers
-//   tiers 2 - 6   : a group of G lanes per vertex, LDS hash table per group
-//   tier 7        : one workgroup per vertex, LDS hash table per workgroup
-//   tier 8 (hub)  : rows cut into chunks, one workgroup per chunk, partial
-//                   sums merged per hash partition (hub.hip)
+// never change label.  Tiers 1 - 7 (the seven levels of the tier table) each
+// run one sweep variant of the menu below:
+//   thread per vertex : labels held in registers and sorted (variants 0, 15,
+//                       16, 18)
+//   G lanes per vertex: an LDS hash table per group, or per workgroup when
+//                       the group is the whole workgroup
+//   tier 8 (hub)      : rows above the last level's bound, cut into chunks,
+//                       one workgroup per chunk, partial sums merged per hash
+//                       partition (hub.hip)
 // ----------------------------------------------------------------------------
 constexpr int kNumTiers = 9;
 constexpr int kHubTier = 8;

@@ -1,5 +1,6 @@
-// Hub tier of the sweep: vertices of degree > 2048, too long for one
-// workgroup's LDS table at good occupancy.
+// Hub tier of the sweep: vertices of degree above the last level of the tier
+// table (4096 by default), too long for one workgroup's LDS table at good
+// occupancy.
 //
 // A hub row is cut into chunks of kHubChunk entries and every chunk gets its
 // own workgroup, so one hub keeps many compute units busy.  Partial sums meet

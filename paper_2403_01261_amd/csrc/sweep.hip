@@ -57,7 +57,8 @@ __device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCoun
 }
 
 // ---------------------------------------------------------------------------
-// Tier 1: one thread per vertex, degree <= D.  The row's labels (and weights)
+// Thread-per-vertex variants: one thread per vertex, degree <= D (the first
+// level by default, any level that fits).  The row's labels (and weights)
 // stay in registers.  A sorting network puts equal labels next to each
 // other, and one pass over the sorted runs keeps the running sum of each run
 // and the largest argmax key seen.  A run's partial sums never exceed its
