@@ -6,7 +6,7 @@ A step is one full gsl_lpa call (degree plan, synchronous sweeps with pruning
 until dN/N <= 0.05 or 20 sweeps, split) on a graph already resident in HBM.
 value = |E| / time per step, |E| = directed CSR entries (every undirected edge
 twice, as the paper counts edges after adding reverse edges).  The timed steps
-run the production path (the sweep loop as one captured graph, no per-launch
+run the production path (the sweep loop as captured graphs, no per-launch
 events).
 
 Extra objects on the JSON line:
@@ -19,6 +19,10 @@ Extra objects on the JSON line:
                 bytes per launch from rocprofv3 counters (profiles/traffic.json),
                 null when absent or stale.
   cpu_baseline  the CPU oracle (single thread, untuned) timed on this host.
+  gather_reference
+                a plain PyTorch gather of an int32 label array by the
+                workload's column array (the sweeps' bound), beside the
+                sweep phase's row entries per second (phases).
   tiers         the degree tiers the timed runs used: by default the tier
                 autotuner (paper_2403_01261_amd/tune.py) runs first on the
                 same workload, outside every timed region.
