@@ -260,6 +260,14 @@ def test_full_batch_matches_oracle_hash(gsl):
     assert b.n == gold["n"] and b.nnz == gold["nnz"] and b.num_graphs == gold["graphs"]
     assert graph_hash(b) == gold["graph_xxh128"]
     say("batch: %d graphs, N=%d, nnz=%d" % (b.num_graphs, b.n, b.nnz))
-    labels, iters, _ = run_concat(gsl, b, gold["max_iters"], gold["tolerance"])
-    assert iters == gold["iterations"]
-    assert labels_hash(np.concatenate(labels)) == gold["labels_xxh128"]
+    # the default tiers, and the table the autotuner picks for this batch
+    # (a thread per vertex up to degree 64: the benchmark's tiers)
+    tuned = [(32, 16), (64, 18), (128, 8), (512, 9), (1024, 17), (2048, 11), (4096, 13)]
+    try:
+        for tiers in (None, tuned):
+            gsl.gsl_set_tiers(tiers)
+            labels, iters, _ = run_concat(gsl, b, gold["max_iters"], gold["tolerance"])
+            assert iters == gold["iterations"], tiers
+            assert labels_hash(np.concatenate(labels)) == gold["labels_xxh128"], tiers
+    finally:
+        gsl.gsl_set_tiers(None)
