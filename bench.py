@@ -99,16 +99,24 @@ def source_hash(csrc: str = None) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kernel: str):
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+def measured_traffic(workload: str, kernel: str, levels, launches_per_step: int, path: str = None):
+    """Measured HBM bytes per launch of `kernel`: the profiled bytes per
+    gsl_lpa call (all dispatches of the kernel in a run of known call count)
+    over the launches one call makes.  None unless the record was taken with
+    the same kernel code and the same tier table as the timed run."""
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or launches_per_step <= 0:
         return None
     with open(path) as f:
         rec = json.load(f)
     entry = rec.get(workload, {}).get(kernel)
     if not entry or entry.get("source_hash") != source_hash():
         return None
-    return entry.get("bytes_per_launch")
+    if [list(x) for x in entry.get("levels", [])] != [list(x) for x in levels]:
+        return None
+    if "bytes_per_step" not in entry:
+        return None
+    return int(round(entry["bytes_per_step"] / launches_per_step))
 
 
 COPY_BYTES = 1 << 30  # plain device-to-device copy used to calibrate the PMC counters
@@ -163,10 +171,17 @@ def _short(name: str) -> str:
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int, kernel: str,
-                  commands: list, out_dir: str = None) -> dict:
-    """Traffic of `kernel` per launch from FETCH_SIZE / WRITE_SIZE runs, each
-    scaled by the counter's reading for the plain COPY_BYTES copy.  Writes
-    traffic.json and the kernel-trace summary into out_dir (profiles/)."""
+                  commands: list, calls: int, levels, launches_per_call: int, out_dir: str = None) -> dict:
+    """Traffic of `kernel` from FETCH_SIZE / WRITE_SIZE runs, each scaled by
+    the counter's reading for the plain COPY_BYTES copy: the sum over every
+    dispatch of the kernel divided by the number of gsl_lpa calls the run
+    made (`calls`, each with `launches_per_call` working launches of the
+    kernel under the tier table `levels`).  Launches enqueued after a loop
+    converged return at once and add next to nothing, so bytes per call over
+    working launches per call is the traffic of one working launch -- the
+    same launch set the benchmark's per-launch durations average over.
+    Writes traffic.json and the kernel-trace summary into out_dir
+    (profiles/)."""
     from graphgen import workloads
     fetch = _read_counter_csv(fetch_dir, "FETCH_SIZE")
     write = _read_counter_csv(write_dir, "WRITE_SIZE")
@@ -176,18 +191,16 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
         return max(copies) if copies else None
 
     cf, cw = calib(fetch), calib(write)
-    # only launches that did work: a sweep kernel enqueued after the loop
-    # converged reads next to nothing (cut at 5% of the largest reading)
     kf = [v for n, v in fetch.values() if _short(n).startswith(kernel)]
     kw = [v for n, v in write.values() if _short(n).startswith(kernel)]
     if not kf or not kw or not cf or not cw:
         raise SystemExit("counter runs lack the kernel %r or the calibration copy" % kernel)
-    kf = [v for v in kf if v >= 0.05 * max(kf)]
-    kw = [v for v in kw if v >= 0.05 * max(kw)]
     sf = COPY_BYTES / (cf * 1024.0)
     sw = COPY_BYTES / (cw * 1024.0)
-    fetch_b = sum(kf) / len(kf) * 1024.0 * sf
-    write_b = sum(kw) / len(kw) * 1024.0 * sw
+    fetch_step = sum(kf) * 1024.0 * sf / calls
+    write_step = sum(kw) * 1024.0 * sw / calls
+    fetch_b = fetch_step / launches_per_call
+    write_b = write_step / launches_per_call
     wname = workloads.NAMES[workload]
     out_dir = out_dir or os.path.join(ROOT, "profiles")
     path = os.path.join(out_dir, "traffic.json")
@@ -196,8 +209,10 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
         with open(path) as f:
             rec = json.load(f)
     rec.setdefault(wname, {})[kernel] = {
+        "bytes_per_step": int(round(fetch_step + write_step)), "calls": calls,
+        "launches_per_call": launches_per_call, "levels": [list(x) for x in levels],
         "bytes_per_launch": int(round(fetch_b + write_b)), "fetch_bytes_per_launch": int(round(fetch_b)),
-        "write_bytes_per_launch": int(round(write_b)), "launches_counted": len(kf),
+        "write_bytes_per_launch": int(round(write_b)), "dispatches": len(kf),
         "copy_fetch_kib": cf, "copy_write_kib": cw, "scale_fetch": sf, "scale_write": sw,
         "source_hash": source_hash(), "commands": commands}
     os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -213,9 +228,12 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
         f.write("Commands (repository root, MI355X):\n\n")
         for c in commands:
             f.write("    %s\n" % c)
-        f.write("\nHBM traffic of `%s` per launch (%d launches): fetch %.3f GB, write %.3f GB "
-                "(FETCH_SIZE / WRITE_SIZE scaled by a %d MiB copy: x%.4f / x%.4f).\n\n"
-                % (kernel, len(kf), fetch_b / 1e9, write_b / 1e9, COPY_BYTES >> 20, sf, sw))
+        f.write("\nTier table (max degree, variant) of the runs: %s.\n\n" % json.dumps([list(x) for x in levels]))
+        f.write("HBM traffic of `%s`: %d dispatches over %d gsl_lpa calls of %d working launches each; "
+                "per working launch fetch %.3f GB, write %.3f GB (FETCH_SIZE / WRITE_SIZE summed over the "
+                "dispatches, scaled by a %d MiB copy: x%.4f / x%.4f).\n\n"
+                % (kernel, len(kf), calls, launches_per_call, fetch_b / 1e9, write_b / 1e9, COPY_BYTES >> 20,
+                   sf, sw))
         if stats:
             f.write("Kernel trace of the first command.  `calls` counts every dispatch; sweep kernels "
                     "enqueued after the loop converged return at once, so `working calls` and their "
@@ -262,15 +280,73 @@ def gather_reference(cols, n, reps=5):
                       "(original vertex order), %d runs" % reps}
 
 
-def cpu_baseline(g, max_iters, tol, w32=None):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def pinned_runs(fn, budget_s: float, max_runs: int):
+    """Runs fn() on one core (the calling thread pinned, as taskset does)
+    until max_runs runs or the time budget is spent (at least one run).
+    Returns (list of seconds, last result, core)."""
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    times, res = [], None
+    try:
+        t_all = time.perf_counter()
+        while len(times) < max_runs and (not times or time.perf_counter() - t_all + times[-1] <= budget_s):
+            t0 = time.perf_counter()
+            res = fn()
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, old)
+    return times, res, core
+
+
+def cpu_baseline(g, max_iters, tol, w32=None, what="the whole workload", budget_s=25.0, max_runs=5):
+    """The oracle (single thread, untuned, pinned to one core), as many full
+    GSL-LPA runs (sweeps + split) of graph g as fit the budget, at most
+    max_runs; median and mean."""
+    import statistics
+
     import oracle
-    t0 = time.perf_counter()
-    r = oracle.lpa(g, max_iters, tol) if w32 is None else oracle.lpa_f32(g, w32, max_iters, tol)
-    dt = time.perf_counter() - t0
-    return {"value": g.nnz / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "one full oracle GSL-LPA run (sweeps + split) of the whole workload, "
-                      "single thread, %.1f s; host has %d CPUs" % (dt, os.cpu_count()),
-            "iterations": int(r.iterations)}, r
+    fn = (lambda: oracle.lpa(g, max_iters, tol)) if w32 is None else (lambda: oracle.lpa_f32(g, w32, max_iters, tol))
+    times, r, core = pinned_runs(fn, budget_s, max_runs)
+    med, mean = statistics.median(times), statistics.mean(times)
+    return {"value": g.nnz / med, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full oracle GSL-LPA run(s) (sweeps + split) of %s, single thread pinned to core %d; "
+                      "median %.2f s, mean %.2f s" % (len(times), what, core, med, mean),
+            "runs": len(times), "seconds_median": round(med, 3), "seconds_mean": round(mean, 3),
+            "value_mean": g.nnz / mean, "iterations": int(r.iterations),
+            "host": {"nproc": os.cpu_count(), "cpu": cpu_model()}}, r
+
+
+def golden_record(idx: int):
+    """Expected values the oracle wrote for workload idx (tests/golden)."""
+    path = os.path.join(ROOT, "tests", "golden", "workloads.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(str(idx))
+
+
+def labels_hash(t) -> str:
+    import numpy as np
+    import xxhash
+    return xxhash.xxh3_128(np.ascontiguousarray(t.cpu().numpy(), dtype=np.int32).view(np.uint8)).hexdigest()
+
+
+# Workloads too large for a bounded oracle run: the oracle runs on a smaller
+# graph of the same recipe instead (name, generator arguments).
+CPU_SAMPLE = {4: ("R-MAT scale 21, edge factor 32, same a/b/c/d, relabelling and seed as rmat-s26, unit weights",
+                  dict(scale=21, edge_factor=32))}
 
 
 def run_tuner(args, run, probe):
@@ -308,8 +384,9 @@ def roofline_from_stats(stats, weighted, steps, wname, n):
     variants = gsl.gsl_tier_variants()
     levels = gsl.gsl_get_tiers()
     kernel = "hub_insert" if dom == NUM_TIERS - 1 else gsl.variant_kernel_name(variants[levels[dom - 1][1]], weighted, n)
+    lps = launches // max(steps, 1)
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wname, kernel, levels, lps),
             "kernel": kernel, "tier": dom, "launches_per_step": launches // max(steps, 1),
             "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": bytes_total // max(launches, 1)}
@@ -459,14 +536,19 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOAD_TEXT),
-                    help="1 planted-10k, 2 rmat-s22, 3 road-24m, 4 rmat-s26, 5 batched-4096")
+    ap.add_argument("--workload", type=int, default=4, choices=sorted(WORKLOAD_TEXT),
+                    help="1 planted-10k, 2 rmat-s22, 3 road-24m, 4 rmat-s26 (default: the largest graph), "
+                         "5 batched-4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="the small variant of the workload (quick checks)")
-    ap.add_argument("--tiers", choices=("tune", "cached", "default"), default="tune",
-                    help="degree tiers of the timed runs: run the tier autotuner first (default), reuse its "
+    ap.add_argument("--tiers", choices=("tune", "cached", "default"), default=None,
+                    help="degree tiers of the timed runs: run the tier autotuner first, reuse its "
                          "cached result for this device and workload (tuning only if there is none), or "
-                         "keep the library defaults")
+                         "keep the library defaults (the default for rmat-s26, whose tuning takes minutes; "
+                         "the others tune)")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run exactly this many production gsl_lpa calls after generation and exit "
+                         "(for rocprofv3 counter and trace runs; prints the tier table and launches per call)")
     ap.add_argument("--weights-f32", action="store_true",
                     help="pass the workload's weights as fp32 values (summed in fp64, gsl_lpa_f32)")
     ap.add_argument("--split-techniques", action="store_true",
@@ -479,9 +561,16 @@ def main(argv=None):
                     help="write profiles/traffic.json from rocprofv3 counter runs and exit")
     ap.add_argument("--kernel", default=None, help="kernel for --summarize-pmc")
     ap.add_argument("--commands", nargs="*", default=[], help="commands recorded by --summarize-pmc")
+    ap.add_argument("--calls", type=int, default=0, help="gsl_lpa calls of the profiled runs (--summarize-pmc)")
+    ap.add_argument("--levels", default=None, help="tier table of the profiled runs, JSON (--summarize-pmc)")
+    ap.add_argument("--launches-per-call", type=int, default=0,
+                    help="working launches of the kernel per call (--summarize-pmc)")
     args = ap.parse_args(argv)
+    if args.tiers is None:
+        args.tiers = "default" if args.workload == 4 else "tune"
     if args.summarize_pmc:
-        r = summarize_pmc(*args.summarize_pmc, args.workload, args.kernel, args.commands)
+        r = summarize_pmc(*args.summarize_pmc, args.workload, args.kernel, args.commands, args.calls,
+                          json.loads(args.levels), args.launches_per_call)
         print(json.dumps(r))
         return 0
     if args.gpus != 1:
@@ -496,6 +585,7 @@ def main(argv=None):
     import numpy as np
     import torch
 
+    import graphgen
     import paper_2403_01261_amd as gsl
     from graphgen import workloads
 
@@ -521,6 +611,19 @@ def main(argv=None):
     tiers = (run_tuner(args, lambda: lpa_call(off, cols, w, mi, tol, out=labels),
                        workloads.describe(args.workload, args.small))
              if not args.weights_f32 else {"source": "default (fp32 weights use the default tiers)"})
+    if args.profile_steps:
+        # exactly profile_steps production calls, then the launch counts the
+        # traffic summary needs (from one more call in timing mode, after the
+        # profiled ones: rocprofv3 sees profile_steps + 1 calls)
+        for k in range(args.profile_steps):
+            lpa_call(off, cols, w, mi, tol, out=labels)
+        torch.cuda.synchronize()
+        _, st = lpa_call(off, cols, w, mi, tol, timing=True, out=labels)
+        print(json.dumps({"profile_calls": args.profile_steps + 1, "levels": gsl.gsl_get_tiers(),
+                          "tier_launches": [t["launches"] for t in st["tiers"]],
+                          "ms_tier": [round(t["ms"], 4) for t in st["tiers"]],
+                          "iterations": st["iterations"]}), flush=True)
+        return 0
     for k in range(args.warmup):
         lpa_call(off, cols, w, mi, tol, out=labels)
         log("warmup %d done" % k)
@@ -574,12 +677,42 @@ def main(argv=None):
     log("gather reference: %.3g gathers/s (sweep phase: %.3g row entries/s)" % (gref["gathers_per_s"],
                                                                            phases["sweep_entries_per_s"] or 0))
 
+    # the timed labels against the oracle's expected values (tests/golden)
+    gold = golden_record(args.workload) if not (args.small or args.weights_f32) else None
+    parity = None
+    if gold is not None and gold.get("nnz") == g.nnz:
+        h = labels_hash(labels)
+        parity = {"labels_xxh128": h, "labels_match_oracle_golden": h == gold["labels_xxh128"],
+                  "iterations_match": last["iterations"] == gold["iterations"],
+                  "dn_match": list(last["changed"]) == list(gold["dn"])}
+        log("labels vs the oracle's golden hash: %s" % parity)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        cpu, ref = cpu_baseline(g, mi, tol, w.cpu().numpy() if args.weights_f32 else None)
-        got = labels.cpu().numpy()
-        cpu["labels_match_gpu"] = bool(np.array_equal(got, ref.labels))
+        if args.workload in CPU_SAMPLE and not args.small:
+            # a smaller graph of the same recipe; the GPU labels of that
+            # graph are checked against the oracle's as well
+            what, kw = CPU_SAMPLE[args.workload]
+            sg = graphgen.rmat(kw["scale"], kw["edge_factor"], workloads.SEED_BASE + args.workload)
+            cpu, ref = cpu_baseline(sg, mi, tol, None, what="a %d-entry sample graph (%s)" % (sg.nnz, what))
+            so = torch.from_numpy(sg.offsets).to(dev)
+            sc = torch.from_numpy(sg.cols).to(dev)
+            slab, _ = lpa_call(so, sc, None, mi, tol)
+            cpu["labels_match_gpu"] = bool(np.array_equal(slab.cpu().numpy(), ref.labels))
+            cpu["sample_graph"] = {"n": sg.n, "nnz": sg.nnz}
+            if gold is not None and "oracle_seconds" in gold:
+                osec = gold["oracle_seconds"]
+                cpu["full_workload_reference"] = {
+                    "edges_per_s": g.nnz / (osec["sweeps"] + osec["split"]),
+                    "note": "one unpinned single-thread oracle run of the whole workload when the golden file "
+                            "was written (another host: context only)"}
+            del so, sc, slab
+        else:
+            cpu, ref = cpu_baseline(g, mi, tol, w.cpu().numpy() if args.weights_f32 else None,
+                                    max_runs=1 if args.workload == 3 else 5)
+            got = labels.cpu().numpy()
+            cpu["labels_match_gpu"] = bool(np.array_equal(got, ref.labels))
         log("oracle: %.3g edges/s, labels match: %s" % (cpu["value"], cpu["labels_match_gpu"]))
 
     line = {"metric": "edges/s (|E|/time) on 1 MI355X + % HBM peak", "value": value,
@@ -590,7 +723,8 @@ def main(argv=None):
                        "nnz": g.nnz, "max_iters": mi, "tolerance": tol,
                        "weights": ("fp32 array, fp64 sums" if args.weights_f32 else
                                    "uint32 array" if weighted else "NULL (unit)")},
-            "roofline": roofline, "cpu_baseline": cpu, "phases": phases, "gather_reference": gref, "tiers": tiers,
+            "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "phases": phases,
+            "gather_reference": gref, "tiers": tiers,
             "split_techniques": split_cmp,
             "context": "paper: 844M edges/s, sk-2005 3.8B edges, 2x Xeon Gold 6226R, 64 threads"}
     print(json.dumps(line), flush=True)

@@ -21,7 +21,11 @@ where a test must finish in seconds.
 """
 from __future__ import annotations
 
-from . import batched_planted, planted, rmat, road_knn
+import os
+
+import numpy as np
+
+from . import Graph, batched_planted, planted, rmat, road_knn
 
 SEED_BASE = 240301261
 
@@ -33,6 +37,33 @@ TOLERANCE = 0.05
 
 
 def make(idx: int, small: bool = False):
+    """Workload idx.  With GSL_GRAPH_CACHE set to a directory, the arrays are
+    kept there as .npy files after the first generation and loaded by later
+    calls (several processes of one session then generate a large graph once)."""
+    cache = os.environ.get("GSL_GRAPH_CACHE")
+    if not cache:
+        return _generate(idx, small)
+    stem = os.path.join(cache, describe(idx, small))
+    parts = ("offsets", "cols", "weights", "vtx_base", "edge_base")
+    if os.path.exists(stem + ".done"):
+        arrs = {k: (np.load(stem + "." + k + ".npy") if os.path.exists(stem + "." + k + ".npy") else None)
+                for k in parts}
+        return Graph(arrs["offsets"], arrs["cols"], arrs["weights"], arrs["vtx_base"], arrs["edge_base"],
+                     name=describe(idx, small))
+    g = _generate(idx, small)
+    try:
+        os.makedirs(cache, exist_ok=True)
+        for k in parts:
+            a = getattr(g, k)
+            if a is not None:
+                np.save(stem + "." + k + ".npy", a)
+        open(stem + ".done", "w").close()
+    except OSError:
+        pass  # no room: later calls generate again
+    return g
+
+
+def _generate(idx: int, small: bool):
     seed = SEED_BASE + idx
     if idx == 1:
         return planted(10_000, 100, 0.1, 10_000, seed)

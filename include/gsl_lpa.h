@@ -352,6 +352,24 @@ int gsl_get_tiers(gsl_tier *levels_out);
 /* Shape of sweep variant `variant` (0 .. until GSL_EINVAL). */
 int gsl_tier_variant(int32_t variant, gsl_variant_info *info);
 
+/*
+ * gsl_set_hub_limits -- limits of the hub tier (rows longer than the last
+ * level's bound) for all later calls in this process.  Hub rows are summed
+ * chunk by chunk into a staging area of (label, sum) records, one batch of
+ * hubs at a time, and the records of each hash partition of a hub are then
+ * merged in a 4,096-slot table; a partition with more distinct labels than
+ * the table takes is merged again in 2, 4, ... hashed sub-passes.  Neither
+ * limit changes results, only memory use and speed.
+ *   staging_bytes : device bytes of staging per hub batch (a hub batch always
+ *                   holds at least one hub); 0 restores the default 4 GiB,
+ *                   else at least 16,384
+ *   merge_claims  : distinct labels one merge pass accepts before the
+ *                   partition is split into sub-passes, in [1, 3839];
+ *                   0 restores the default 3839
+ * GSL_EINVAL outside these ranges (nothing changes).
+ */
+int gsl_set_hub_limits(int64_t staging_bytes, int32_t merge_claims);
+
 /* Stream for all subsequent calls of this process (a hipStream_t; NULL = the
  * null stream). */
 int gsl_set_stream(void *hip_stream);

@@ -122,6 +122,7 @@ def load(path: str = None):
     lib.gsl_modularity.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]
     lib.gsl_convergence_limit.argtypes = [ctypes.c_int64, ctypes.c_double]
     lib.gsl_convergence_limit.restype = ctypes.c_int64
+    lib.gsl_set_hub_limits.argtypes = [ctypes.c_int64, ctypes.c_int32]
     lib.gsl_set_stream.argtypes = [_VP]
     lib.gsl_last_error.restype = ctypes.c_char_p
     lib.gsl_version.restype = ctypes.c_char_p
@@ -129,7 +130,8 @@ def load(path: str = None):
     for f in (lib.gsl_lpa, lib.gsl_lpa_ex, lib.gsl_split, lib.gsl_modularity, lib.gsl_set_stream,
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
               lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected, lib.gsl_set_tiers,
-              lib.gsl_get_tiers, lib.gsl_tier_variant, lib.gsl_split_ex, lib.gsl_lpa_f32):
+              lib.gsl_get_tiers, lib.gsl_tier_variant, lib.gsl_split_ex, lib.gsl_lpa_f32,
+              lib.gsl_set_hub_limits):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -445,6 +447,13 @@ def variant_kernel_name(v: dict, weighted: bool = False, n: int = 0) -> str:
         return "sweep_thread<%d, %s, %s>" % (v["per_lane"], "true" if weighted else "false",
                                              "true" if n < (1 << 30) else "false")
     return "sweep_lds<%d, %d, %d, %d>" % (v["group"], v["table_log2"], v["block"], v["per_lane"])
+
+
+def gsl_set_hub_limits(staging_bytes: int = 0, merge_claims: int = 0) -> None:
+    """Hub tier limits of later calls: staging bytes per hub batch and the
+    distinct labels one merge pass accepts (0: the defaults).  Changes memory
+    use and speed, not results."""
+    _check(load().gsl_set_hub_limits(int(staging_bytes), int(merge_claims)))
 
 
 def gsl_convergence_limit(n: int, tolerance: float) -> int:

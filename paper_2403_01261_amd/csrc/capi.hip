@@ -2,6 +2,7 @@
 // per-device scratch cache and the host loop that enqueues the kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -10,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gsl_lpa.h"
@@ -26,9 +28,23 @@ std::mutex g_mu;
 std::mutex g_tier_mu;
 gsl::TierConfig g_tiers = gsl::kDefaultTiers;
 
+// Hub tier limits (gsl_set_hub_limits): staging bytes per hub batch and
+// merge-table claims before a partition is re-merged in sub-passes.
+constexpr int64_t kDefaultHubStagingBytes = (int64_t)4 << 30;
+struct HubLimits {
+  int64_t staging_bytes = kDefaultHubStagingBytes;
+  int32_t merge_cap = gsl::kHubMergeCapMax;
+};
+HubLimits g_hub_limits;
+
 gsl::TierConfig current_tiers() {
   std::lock_guard<std::mutex> lk(g_tier_mu);
   return g_tiers;
+}
+
+HubLimits current_hub_limits() {
+  std::lock_guard<std::mutex> lk(g_tier_mu);
+  return g_hub_limits;
 }
 
 int fail(int code, const char *fmt, ...) {
@@ -220,6 +236,7 @@ constexpr int64_t kChunkMinEntries = int64_t(1) << 23;
 constexpr int kChunkSweeps = 2;
 
 int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
+  const int64_t need = (int64_t)sizeof(Counters) + 4 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
   if (n > s.n_cap) {
     const int64_t cap = n;
     hipFree(s.Cn);
@@ -253,7 +270,6 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
       return fail(GSL_ENOMEM, "device allocation failed");
   }
   if (!s.ctrl && dmalloc(&s.ctrl, 1) != hipSuccess) return fail(GSL_ENOMEM, "device allocation failed");
-  const int64_t need = (int64_t)sizeof(Counters) + 4 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
   if (need > s.ctr_bytes) {
     hipFree(s.ctr);
     if (s.ctr_host) hipHostFree(s.ctr_host);
@@ -267,6 +283,11 @@ int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
     }
     s.ctr_bytes = need;
   }
+  return GSL_OK;
+}
+
+// The phase events (timing mode, split timing).
+int ensure_events(Scratch &s) {
   if (!s.ev[0])
     for (auto &e : s.ev)
       if (hipEventCreate(&e) != hipSuccess) return fail(GSL_EDEVICE, "hipEventCreate failed");
@@ -325,7 +346,7 @@ int read_nnz(const int64_t *offsets, int64_t n, int64_t *nnz, hipStream_t st) {
 // they are validated.
 int run_plan(Scratch &s, const int64_t *offsets, int64_t n, const gsl::TierConfig &cfg, hipStream_t st,
              int64_t *ends = nullptr) {
-  HIP_TRY(hipMemsetAsync(s.ctr, 0, (size_t)s.ctr_bytes, st));
+  HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.ctr), 0, s.ctr_bytes / 8, st));
   HIP_TRY(gsl::launch_plan(offsets, n, s.list, s.blk_counts, s.ctr, cfg, st));
   HIP_TRY(hipMemcpyAsync(s.ctr_host, s.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   if (ends) {
@@ -338,7 +359,8 @@ int run_plan(Scratch &s, const int64_t *offsets, int64_t n, const gsl::TierConfi
 
 // Builds the hub layout of the current graph and splits the hubs into
 // batches whose staging area fits kHubStagingBytes (at least one hub each).
-int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_t H, hipStream_t st) {
+int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_t H, int64_t staging_bytes,
+                 hipStream_t st) {
   s.hub_batches.clear();
   if (H <= 0) return GSL_OK;
   if (H > s.hub_cap) {
@@ -358,8 +380,8 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
     }
     s.hub_cap = H;
   }
-  HIP_TRY(hipMemsetAsync(s.hub_best, 0, (size_t)H * sizeof(unsigned long long), st));
-  HIP_TRY(hipMemsetAsync(s.hub_rowsum, 0, (size_t)H * sizeof(unsigned long long), st));
+  HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_best), 0, H, st));
+  HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_rowsum), 0, H, st));
   gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
   HIP_TRY(gsl::launch_hub_layout(offsets, hubs, H, L, st));
   int rc = ensure_pinned(s, kPinSmall + 3 * (H + 1));
@@ -372,8 +394,7 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
   s.h_chunk.assign(ph, ph + (H + 1));
   s.h_part.assign(ph + (H + 1), ph + 2 * (H + 1));
   s.h_hist.assign(ph + 2 * (H + 1), ph + 3 * (H + 1));
-  constexpr int64_t kHubStagingBytes = (int64_t)4 << 30;
-  const int64_t chunk_cap = kHubStagingBytes / ((int64_t)gsl::kHubChunk * 8);
+  const int64_t chunk_cap = staging_bytes / ((int64_t)gsl::kHubChunk * 8);
   int64_t k0 = 0;
   for (int64_t k = 0; k < H; ++k) {
     if (k > k0 && s.h_chunk[(size_t)k + 1] - s.h_chunk[(size_t)k0] > chunk_cap) {
@@ -508,7 +529,11 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   // fp32 weights run fixed tiers (their kernels are instantiated for those
   // bounds only)
   const gsl::TierConfig cfg = f32 ? gsl::kF32Tiers : current_tiers();
-  if (o.timing) HIP_TRY(hipEventRecord(s.ev[0], st));
+  const HubLimits hub_lim = current_hub_limits();
+  if (o.timing) {
+    if ((rc = ensure_events(s))) return rc;
+    HIP_TRY(hipEventRecord(s.ev[0], st));
+  }
   if ((rc = run_plan(s, offsets, n, cfg, st, s.pin))) return rc;
   if (s.pin[0] != 0) return fail(GSL_EINVAL, "offsets[0] must be 0 (got %lld)", (long long)s.pin[0]);
   if (s.pin[1] < 0) return fail(GSL_EINVAL, "offsets[n] must be >= 0");
@@ -518,7 +543,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   // Tier t is the id range [tier_start[t], +tier_count[t]) of s.list; hubs
   // (tier 8) come first, isolated vertices (tier 0) last.
   const int64_t H = plan.tier_count[gsl::kHubTier];
-  if ((rc = prepare_hubs(s, offsets, s.list, H, st))) return rc;
+  if ((rc = prepare_hubs(s, offsets, s.list, H, hub_lim.staging_bytes, st))) return rc;
   // Renumbered layout: chosen when vertices of degree > 64 hold most entries
   // (their labels are the usual gather targets).  Batches keep their layout
   // (per-graph vertex ranges).
@@ -661,7 +686,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
             }
             HIP_TRY(gsl::launch_hub_sweep(a, g_list, L, s.h_chunk.data(), s.h_part.data(), s.hub_staging,
                                           s.hub_hist, s.hub_best, s.hub_rowsum, bt.first, bt.second,
-                                          s.hub_max_parts[bi], stage, cur));
+                                          s.hub_max_parts[bi], hub_lim.merge_cap, stage, cur));
           }
         }
       } else {
@@ -718,13 +743,27 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
       key.push_back((uint64_t)plan.tier_start[t]);
       key.push_back((uint64_t)cfg.variant[t]);
     }
+    // Hub launches bake in their grid sizes (chunks and partitions of each
+    // batch, all chunks for fp32 weights) and dynamic LDS (largest partition
+    // count), so those totals belong to the key as well.
+    key.push_back((uint64_t)hub_lim.merge_cap);
+    key.push_back((uint64_t)(H > 0 ? s.h_chunk[(size_t)H] : 0));
     for (size_t bi = 0; bi < s.hub_batches.size(); ++bi) {
-      key.push_back((uint64_t)s.hub_batches[bi].first);
-      key.push_back((uint64_t)s.hub_batches[bi].second);
+      const auto &bt = s.hub_batches[bi];
+      key.push_back((uint64_t)bt.first);
+      key.push_back((uint64_t)bt.second);
       key.push_back((uint64_t)s.hub_max_parts[bi]);
+      key.push_back((uint64_t)(s.h_chunk[(size_t)bt.second] - s.h_chunk[(size_t)bt.first]));
+      key.push_back((uint64_t)(s.h_part[(size_t)bt.second] - s.h_part[(size_t)bt.first]));
     }
     if (!s.loop_exec || key != s.loop_key) {
-      if (s.loop_exec) hipGraphExecDestroy(s.loop_exec);
+      // The previous graph's launches have finished: every call ends with a
+      // stream synchronisation, except one that failed while launching;
+      // synchronise here so that an exec is never destroyed in flight.
+      if (s.loop_exec) {
+        HIP_TRY(hipStreamSynchronize(st));
+        hipGraphExecDestroy(s.loop_exec);
+      }
       s.loop_exec = nullptr;
       s.loop_key.clear();
       // Captured on a private stream (the caller's may be the null stream,
@@ -1299,6 +1338,7 @@ int gsl_split_ex(const int64_t *offsets, const int32_t *cols, int64_t n, const i
   const gsl::TierConfig cfg = current_tiers();
   if ((rc = run_plan(s, offsets, n, cfg, st))) return rc;
   Counters plan = *s.ctr_host;
+  if ((rc = ensure_events(s))) return rc;
   HIP_TRY(hipEventRecord(s.ev[0], st));
   int32_t rounds = 0;
   if (technique == GSL_SPLIT_UNION_FIND) {
@@ -1410,6 +1450,18 @@ int gsl_set_tiers(const gsl_tier *levels) {
   }
   std::lock_guard<std::mutex> lk(g_tier_mu);
   g_tiers = c;
+  return GSL_OK;
+}
+
+int gsl_set_hub_limits(int64_t staging_bytes, int32_t merge_claims) {
+  if (staging_bytes < 0 || (staging_bytes > 0 && staging_bytes < (int64_t)gsl::kHubChunk * 8))
+    return fail(GSL_EINVAL, "staging_bytes must be 0 (default) or at least %lld",
+                (long long)gsl::kHubChunk * 8);
+  if (merge_claims < 0 || merge_claims > gsl::kHubMergeCapMax)
+    return fail(GSL_EINVAL, "merge_claims must be in [0, %d]", gsl::kHubMergeCapMax);
+  std::lock_guard<std::mutex> lk(g_tier_mu);
+  g_hub_limits.staging_bytes = staging_bytes ? staging_bytes : kDefaultHubStagingBytes;
+  g_hub_limits.merge_cap = merge_claims ? merge_claims : gsl::kHubMergeCapMax;
   return GSL_OK;
 }
 

@@ -189,6 +189,9 @@ hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
 // over the hubs (H + 1 entries each) of their chunks, hash partitions and
 // partition-boundary records (chunks * (partitions + 1)).
 constexpr int kHubChunk = 2048;
+// Merge table claims before a hub partition is re-merged in hashed
+// sub-passes (the largest value; see hub.hip).
+constexpr int kHubMergeCapMax = 4096 - 256 - 1;
 struct HubLayout {
   int64_t *chunk_start;
   int64_t *part_start;
@@ -200,7 +203,7 @@ hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L
                             const int64_t *chunk_start_h, const int64_t *part_start_h,
                             unsigned long long *staging, int32_t *hist, unsigned long long *best,
                             unsigned long long *rowsum, int64_t k0, int64_t k1, int max_parts,
-                            int stage, hipStream_t s);
+                            int merge_cap, int stage, hipStream_t s);
 // Copies changed labels into C and clears the consumed flags (this sweep's
 // active flags when it was sparse).  Batches (gdn != NULL): also adds each
 // graph's changes to gdn[graph].

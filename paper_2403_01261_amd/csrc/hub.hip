@@ -35,13 +35,10 @@ constexpr int kMaxParts = 8192;
 constexpr int kPartSize = 2048;               // expected distinct labels per partition
 constexpr int kMergeBlock = 256;
 // Claims before a merge pass gives up and the partition is split into
-// sub-passes (a build may lower it with -DGSL_HUB_MERGE_CAP=... to exercise
-// that path).
-#ifndef GSL_HUB_MERGE_CAP
-#define GSL_HUB_MERGE_CAP (4096 - 256 - 1)
-#endif
-constexpr int kMergeCap = GSL_HUB_MERGE_CAP;
-static_assert(kMergeCap > 0 && kMergeCap + kMergeBlock < kTabSlots, "a free slot must always remain");
+// sub-passes: at most kHubMergeCapMax, so that a free slot always remains
+// (up to kMergeBlock threads may pass the check at once); a smaller cap can
+// be set at run time to exercise the sub-pass path on small graphs.
+static_assert(kHubMergeCapMax + kMergeBlock < kTabSlots, "a free slot must always remain");
 constexpr int kChunkGroup = 1024;                       // chunks whose slices one merge step indexes
 
 static_assert(kHubChunk % kHubBlock == 0, "chunk must split evenly over the block");
@@ -131,6 +128,7 @@ struct HubArgs {
   unsigned long long *best;      // [H] packed argmax keys
   unsigned long long *rowsum;    // [H] summed row weights
   int64_t k0, k1;                // hubs of this batch
+  int merge_cap;                 // claims before a merge pass splits (1 .. kHubMergeCapMax)
 };
 
 // Exclusive scan of a[0..n) (n <= kMaxParts) in LDS by the whole block;
@@ -252,7 +250,7 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
   for (int64_t i = threadIdx.x; i < nc; i += kMergeBlock) mine += gh[i * (P + 1) + P];
   if (mine) atomicAdd(&records, mine);
   __syncthreads();
-  const bool whole = records <= kMergeCap;  // uniform
+  const bool whole = records <= h.merge_cap;  // uniform
   if (whole && p > 0) return;
   const int p_lo = whole ? 0 : p, p_hi = whole ? P : p + 1;  // partitions merged here
   unsigned long long best = 0;
@@ -289,7 +287,7 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
           const uint32_t label = (uint32_t)(xv >> 32);
           if (R > 1 && (sub_of(label) & (R - 1)) != r) continue;
           if (__hip_atomic_load(&overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) continue;
-          if (__hip_atomic_load(&claimed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= kMergeCap) {
+          if (__hip_atomic_load(&claimed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= h.merge_cap) {
             overflow = 1;
             continue;
           }
@@ -341,7 +339,10 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
       lc.processed = 1;
       lc.edges = (unsigned long long)(a.off[v + 1] - a.off[v]);
       lc.overflow = rs >> 32 ? 1 : 0;
-      if (best) {
+      // A row whose weights sum to 2^32 or more may have carried a sum into
+      // the label half of a packed table slot: no change is recorded (the
+      // call fails with the overflow).
+      if (best && !(rs >> 32)) {
         const uint32_t cstar = key_label(best);
         if (cstar != (uint32_t)a.C[v]) {
           if (a.inplace)
@@ -413,9 +414,10 @@ hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L
                             const int64_t *chunk_start_h, const int64_t *part_start_h,
                             unsigned long long *staging, int32_t *hist, unsigned long long *best,
                             unsigned long long *rowsum, int64_t k0, int64_t k1, int max_parts,
-                            int stage, hipStream_t s) {
+                            int merge_cap, int stage, hipStream_t s) {
   if (k1 <= k0) return hipSuccess;
-  HubArgs h{hubs, L, staging, hist, best, rowsum, k0, k1};
+  if (merge_cap < 1 || merge_cap > kHubMergeCapMax) return hipErrorInvalidValue;
+  HubArgs h{hubs, L, staging, hist, best, rowsum, k0, k1, merge_cap};
   const int64_t chunks = chunk_start_h[k1] - chunk_start_h[k0];
   const int64_t parts = part_start_h[k1] - part_start_h[k0];
   if (stage == 0) {

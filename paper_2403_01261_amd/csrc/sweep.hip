@@ -16,7 +16,8 @@
 // neighbourhood), so the host may run a sweep dense instead of marking.
 //
 // Weights are summed exactly in 32-bit integers; every sweep checks that no
-// row's total weight reaches 2^32 and raises `overflow` otherwise.
+// row's total weight reaches 2^32 and raises `overflow` otherwise (such a
+// row records no change, so no label outside [0, n) ever reaches C).
 #include "device_common.h"
 #include "gsl_internal.h"
 
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
     lc.processed += 1;
     lc.edges += (unsigned long long)d;
     lc.overflow += rowsum >> 32 ? 1 : 0;
-    if (best) {
+    if (best && !(rowsum >> 32)) {
       const uint32_t cstar = key_label(best);
       if (cstar != own) {
         record_change(a, v, cstar, lc);
@@ -297,7 +298,10 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
           lc.edges += (unsigned long long)(e - b);
           lc.overflow += rowsum >> 32 ? 1 : 0;
         }
-        if (best) {
+        // A row whose weights sum to 2^32 or more may have carried a sum
+        // into the label half of a packed slot: nothing is recorded for it
+        // (the call fails with the overflow).
+        if (best && !(rowsum >> 32)) {
           const uint32_t cstar = key_label(best);
           if (cstar != (uint32_t)a.C[v]) {
             if (lane == 0) record_change(a, v, cstar, lc);

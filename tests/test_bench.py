@@ -52,21 +52,33 @@ def test_summarize_pmc_scales_by_the_copy(tmp_path):
     copy = "__amd_rocclr_copyBuffer"
     kern = "void gsl::(anonymous namespace)::sweep_lds<8, 5, 256, 2>(gsl::SweepArgs)"
     # the copy of 1 GiB reads as 0.5 GiB in FETCH_SIZE (scale 2) and 1 GiB in
-    # WRITE_SIZE (scale 1); a near-empty launch falls under the 5 % cut
+    # WRITE_SIZE (scale 1); two calls of two working launches each, plus an
+    # empty launch after convergence
     _write(str(tmp_path / "f" / "f_counter_collection.csv"), hdr,
            [[1, copy, "FETCH_SIZE", 524288.0], [2, kern, "FETCH_SIZE", 1000.0], [3, kern, "FETCH_SIZE", 3000.0],
-            [4, kern, "FETCH_SIZE", 10.0]])
+            [4, kern, "FETCH_SIZE", 10.0], [5, kern, "FETCH_SIZE", 1000.0], [6, kern, "FETCH_SIZE", 3000.0]])
     _write(str(tmp_path / "w" / "w_counter_collection.csv"), hdr,
            [[1, copy, "WRITE_SIZE", 1048576.0], [2, kern, "WRITE_SIZE", 100.0], [3, kern, "WRITE_SIZE", 300.0],
-            [4, kern, "WRITE_SIZE", 1.0]])
+            [4, kern, "WRITE_SIZE", 0.0], [5, kern, "WRITE_SIZE", 100.0], [6, kern, "WRITE_SIZE", 300.0]])
     out = tmp_path / "profiles"
+    levels = [[32, 16], [64, 6], [128, 8], [512, 9], [1024, 17], [2048, 11], [4096, 13]]
     rec = bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "t"), 2,
-                              "sweep_lds<8, 5, 256, 2>", ["cmd"], out_dir=str(out))
-    assert rec["launches_counted"] == 2
+                              "sweep_lds<8, 5, 256, 2>", ["cmd"], 2, levels, 2, out_dir=str(out))
+    assert rec["dispatches"] == 5 and rec["calls"] == 2 and rec["launches_per_call"] == 2
     assert rec["scale_fetch"] == 2.0 and rec["scale_write"] == 1.0
-    assert rec["fetch_bytes_per_launch"] == 2000 * 1024 * 2
-    assert rec["write_bytes_per_launch"] == 200 * 1024
-    assert rec["bytes_per_launch"] == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    assert rec["fetch_bytes_per_launch"] == round(8010 * 1024 * 2 / 4)
+    assert rec["write_bytes_per_launch"] == 800 * 1024 // 4
+    assert rec["bytes_per_step"] == (8010 * 2 + 800) * 1024 // 2
     saved = json.load(open(out / "traffic.json"))
-    assert saved["rmat-s22"]["sweep_lds<8, 5, 256, 2>"]["source_hash"] == bench.source_hash()
+    entry = saved["rmat-s22"]["sweep_lds<8, 5, 256, 2>"]
+    assert entry["source_hash"] == bench.source_hash() and entry["levels"] == levels
     assert (out / "rmat-s22_sweep_lds-8-5-256-2.md").exists()
+    # the benchmark reports the traffic only for the same tier table
+    path = str(out / "traffic.json")
+    got = bench.measured_traffic("rmat-s22", "sweep_lds<8, 5, 256, 2>", levels, 2, path=path)
+    assert got == round(entry["bytes_per_step"] / 2)
+    other = [list(x) for x in levels]
+    other[0][0] = 8
+    assert bench.measured_traffic("rmat-s22", "sweep_lds<8, 5, 256, 2>", other, 2, path=path) is None
+    assert bench.measured_traffic("rmat-s22", "sweep_lds<8, 5, 256, 2>", levels, 0, path=path) is None
+    assert bench.measured_traffic("rmat-s26", "sweep_lds<8, 5, 256, 2>", levels, 2, path=path) is None

@@ -218,8 +218,6 @@ def _golden():
 
 @pytest.mark.parametrize("idx", [1, 2, 3, 4])
 def test_full_workload_matches_oracle_hash(gsl, idx):
-    if idx == 4 and os.environ.get("GSL_TEST_LARGE") != "1":
-        pytest.skip("rmat-s26 (4.16B entries, ~2 min to generate): set GSL_TEST_LARGE=1")
     gold = _golden().get(str(idx))
     if gold is None:
         pytest.skip("workload %d not in golden file" % idx)
