@@ -133,6 +133,33 @@ int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weig
                int32_t *labels_out);
 
 /*
+ * gsl_lpa_noalloc -- gsl_lpa for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and the same labels as gsl_lpa, computed by
+ * the same kernels (pruning on, split on, the graph's own vertex order), with
+ * every scratch buffer carved from one static device array of
+ * GSL_NOALLOC_SCRATCH_BYTES per device (its address is looked up once per
+ * device, on the first call there; the array is held until the process ends).
+ * The call allocates nothing: no hipMalloc, hipFree, host pinning, events or
+ * graphs; it reads small results back through pageable host memory.
+ *
+ * Limits (GSL_EINVAL beyond them, before any device work): n at most
+ * GSL_NOALLOC_MAX_VERTICES, max_iters at most GSL_NOALLOC_MAX_ITERS, at most
+ * GSL_NOALLOC_MAX_HUBS rows above the last tier bound, and no such row longer
+ * than 2^20 entries.  Every call on a device shares that device's array, and
+ * each call leaves its contents behind (every buffer is re-initialised before
+ * use).  Calls that overlapped on one device would race on it; the library
+ * lock serialises the calls of one process and each process has its own
+ * array.  gsl_set_tiers and gsl_set_hub_limits apply as for gsl_lpa.
+ */
+#define GSL_NOALLOC_MAX_VERTICES (1 << 20)
+#define GSL_NOALLOC_MAX_ITERS 256
+#define GSL_NOALLOC_MAX_HUBS 16384
+#define GSL_NOALLOC_SCRATCH_BYTES (48 << 20)
+int gsl_lpa_noalloc(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+                    int32_t max_iters, double tolerance, int32_t *labels_out);
+
+/*
  * gsl_lpa_f32 -- gsl_lpa_ex with fp32 weights summed in fp64, the paper's
  * precision (Sec. 5.1.2).  weights: float[nnz] DEVICE array, every value
  * finite and >= 0 (else GSL_EINVAL), or NULL (unit weights, identical to

@@ -123,6 +123,7 @@ def load(path: str = None):
     lib.gsl_convergence_limit.argtypes = [ctypes.c_int64, ctypes.c_double]
     lib.gsl_convergence_limit.restype = ctypes.c_int64
     lib.gsl_set_hub_limits.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.gsl_lpa_noalloc.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _VP]
     lib.gsl_set_stream.argtypes = [_VP]
     lib.gsl_last_error.restype = ctypes.c_char_p
     lib.gsl_version.restype = ctypes.c_char_p
@@ -131,7 +132,7 @@ def load(path: str = None):
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
               lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected, lib.gsl_set_tiers,
               lib.gsl_get_tiers, lib.gsl_tier_variant, lib.gsl_split_ex, lib.gsl_lpa_f32,
-              lib.gsl_set_hub_limits):
+              lib.gsl_set_hub_limits, lib.gsl_lpa_noalloc):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -177,6 +178,20 @@ def gsl_lpa(offsets, cols, weights=None, max_iters=20, tolerance=0.05, out=None)
     """GSL-LPA labels (int32 tensor).  See include/gsl_lpa.h."""
     labels, _ = gsl_lpa_ex(offsets, cols, weights, max_iters, tolerance, out=out)
     return labels
+
+
+def gsl_lpa_noalloc(offsets, cols, weights=None, max_iters=20, tolerance=0.05, out=None):
+    """gsl_lpa without any device allocation by the library (its scratch is a
+    static device array; see include/gsl_lpa.h for the size limits).  `out`
+    should be preallocated by callers that must not allocate."""
+    lib = _bind_stream()
+    po, pc, pw, n = _graph_args(offsets, cols, weights)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    if out.numel() != n:
+        raise ValueError("out must hold n labels")
+    _check(lib.gsl_lpa_noalloc(po, pc, pw, n, int(max_iters), float(tolerance), _dev(out, (torch.int32,), "out")))
+    return out
 
 
 LAYOUTS = {"auto": 0, "renumbered": 1, "original": 2}

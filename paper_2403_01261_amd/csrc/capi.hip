@@ -17,6 +17,12 @@
 #include "../../include/gsl_lpa.h"
 #include "gsl_internal.h"
 
+// Scratch of gsl_lpa_noalloc: one array per device, loaded with the code
+// object and held until the process ends.  Host code never uses this name as
+// an address (it is a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, once per device, in noalloc_setup.
+static __device__ __align__(256) unsigned char scratch[GSL_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 using gsl::Counters;
@@ -67,6 +73,10 @@ int fail(int code, const char *fmt, ...) {
 
 // Scratch cached per device; grown on demand, freed by gsl_release().
 struct Scratch {
+  // Carved once from the no-alloc region (gsl_lpa_noalloc): every buffer is
+  // preset at its largest size, so a call that needs more fails instead of
+  // allocating.
+  bool fixed = false;
   int64_t n_cap = -1;
   int32_t *Cn = nullptr;
   uint8_t *chg = nullptr;
@@ -237,6 +247,11 @@ constexpr int kChunkSweeps = 2;
 
 int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
   const int64_t need = (int64_t)sizeof(Counters) + 4 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
+  if (s.fixed) {
+    if (n > s.n_cap || need > s.ctr_bytes)
+      return fail(GSL_EINVAL, "%lld vertices / %d sweeps exceed the no-alloc scratch", (long long)n, max_iters);
+    return GSL_OK;
+  }
   if (n > s.n_cap) {
     const int64_t cap = n;
     hipFree(s.Cn);
@@ -314,6 +329,7 @@ constexpr int64_t kPinSmall = 16;  // words of Scratch::pin before the hub layou
 // Pinned host staging of at least `words` int64 words.
 int ensure_pinned(Scratch &s, int64_t words) {
   if (words <= s.pin_cap) return GSL_OK;
+  if (s.fixed) return fail(GSL_EINVAL, "the graph has more hub rows than the no-alloc scratch holds");
   if (s.pin) hipHostFree(s.pin);
   s.pin = nullptr;
   s.pin_cap = 0;
@@ -364,6 +380,7 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
   s.hub_batches.clear();
   if (H <= 0) return GSL_OK;
   if (H > s.hub_cap) {
+    if (s.fixed) return fail(GSL_EINVAL, "%lld hub rows exceed the no-alloc scratch", (long long)H);
     hipFree(s.hub_chunk_start);
     hipFree(s.hub_part_start);
     hipFree(s.hub_hist_start);
@@ -420,6 +437,8 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
     need_hist = h > need_hist ? h : need_hist;
   }
   const int64_t need_staging = need_chunks * gsl::kHubChunk;
+  if (s.fixed && (need_staging > s.hub_staging_cap || need_hist > s.hub_hist_cap))
+    return fail(GSL_EINVAL, "a hub row of %lld chunks exceeds the no-alloc staging area", (long long)need_chunks);
   if (need_staging > s.hub_staging_cap) {
     hipFree(s.hub_staging);
     s.hub_staging = nullptr;
@@ -531,6 +550,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   const gsl::TierConfig cfg = f32 ? gsl::kF32Tiers : current_tiers();
   const HubLimits hub_lim = current_hub_limits();
   if (o.timing) {
+    if (s.fixed) return fail(GSL_EINVAL, "timing is not available without allocation");
     if ((rc = ensure_events(s))) return rc;
     HIP_TRY(hipEventRecord(s.ev[0], st));
   }
@@ -543,7 +563,10 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   // Tier t is the id range [tier_start[t], +tier_count[t]) of s.list; hubs
   // (tier 8) come first, isolated vertices (tier 0) last.
   const int64_t H = plan.tier_count[gsl::kHubTier];
-  if ((rc = prepare_hubs(s, offsets, s.list, H, hub_lim.staging_bytes, st))) return rc;
+  // the fixed scratch keeps every staging batch within its staging area
+  const int64_t staging_bytes = s.fixed ? std::min<int64_t>(hub_lim.staging_bytes, s.hub_staging_cap * 8)
+                                        : hub_lim.staging_bytes;
+  if ((rc = prepare_hubs(s, offsets, s.list, H, staging_bytes, st))) return rc;
   // Renumbered layout: chosen when vertices of degree > 64 hold most entries
   // (their labels are the usual gather targets).  Batches keep their layout
   // (per-graph vertex ranges).
@@ -710,6 +733,19 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   if (timed || max_iters == 0) {
     for (int k = 0; k < max_iters; ++k)
       if ((rc = enqueue_sweep(k))) return rc;
+  } else if (s.fixed) {
+    // Without allocation there is no loop graph (instantiating one
+    // allocates): the sweeps are enqueued directly, and the loop state is
+    // read back after every kChunkSweeps sweeps to stop early.
+    for (int k = 0; k < max_iters; ++k) {
+      if ((rc = enqueue_sweep(k))) return rc;
+      if ((k + 1) % kChunkSweeps == 0 && k + 1 < max_iters) {
+        int32_t done = 0;
+        HIP_TRY(hipMemcpyAsync(&done, &s.ctrl->done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (done) break;
+      }
+    }
   } else {
     // The loop as a captured graph, reused while every pointer and size it
     // was built from stays the same.  Small graphs: all max_iters sweeps in
@@ -913,6 +949,93 @@ int check_labels(Scratch &s, const int32_t *labels, int64_t n, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(&bad, &s.ctr->bad_label, sizeof(bad), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (bad) return fail(GSL_EINVAL, "a label is outside [0, n)");
+  return GSL_OK;
+}
+
+// ---- gsl_lpa_noalloc: every buffer carved from the static scratch ----
+constexpr int64_t kNoAllocPlanEntries =
+    ((GSL_NOALLOC_MAX_VERTICES + 1023) / 1024 + ((GSL_NOALLOC_MAX_VERTICES + 1023) / 1024 + 1023) / 1024) *
+    gsl::kNumTiers;
+constexpr int64_t kNoAllocStagingPairs = (int64_t)1 << 20;  // 512 chunks: hub rows up to 2^20 entries
+constexpr int64_t kNoAllocStagingChunks = kNoAllocStagingPairs / gsl::kHubChunk;
+// Partition records of one staging batch: sum over its hubs of chunks * (partitions + 1), partitions == chunks.
+constexpr int64_t kNoAllocHistEntries = kNoAllocStagingChunks * (kNoAllocStagingChunks + 1);
+constexpr int64_t kNoAllocCtrBytes =
+    (int64_t)sizeof(Counters) + 4 * (int64_t)sizeof(uint64_t) * GSL_NOALLOC_MAX_ITERS;
+
+// Bytes of every buffer, each rounded up to 256: the carve order of
+// noalloc_setup.
+constexpr int64_t al256(int64_t b) { return (b + 255) / 256 * 256; }
+constexpr int64_t kNoAllocFlagBytes = (GSL_NOALLOC_MAX_VERTICES + 3) / 4 * 4 + 16;
+constexpr int64_t kNoAllocLayoutBytes =
+    al256(sizeof(gsl::SweepCtrl)) + al256(kNoAllocCtrBytes) +
+    al256((int64_t)gsl::kNumTiers * gsl::kMaxTierGrid * gsl::kCountFields * 8) +
+    al256(4LL * GSL_NOALLOC_MAX_VERTICES) + 3 * al256(kNoAllocFlagBytes) +   // Cn, chg, act[2]
+    3 * al256(4LL * GSL_NOALLOC_MAX_VERTICES) +                              // list, parent, rep
+    al256(8LL * GSL_NOALLOC_MAX_VERTICES) + al256(8 * kNoAllocPlanEntries) +  // sigma, plan counts
+    3 * al256(8LL * (GSL_NOALLOC_MAX_HUBS + 1)) + 2 * al256(8LL * GSL_NOALLOC_MAX_HUBS) +
+    al256(8 * kNoAllocStagingPairs) + al256(4 * kNoAllocHistEntries);
+static_assert(kNoAllocLayoutBytes <= GSL_NOALLOC_SCRATCH_BYTES, "the no-alloc buffers fit the static scratch");
+
+struct NoAlloc {
+  bool ready = false;
+  Scratch s;
+  std::vector<int64_t> pin;      // host words for small reads (pageable: nothing is allocated per call)
+  std::vector<uint64_t> ctr_host;  // host mirror of the counters
+};
+std::map<int, NoAlloc> g_noalloc;
+
+// Once per device, with that device current: the array's device address,
+// every buffer carved from it at its largest size, host mirrors sized.
+int noalloc_setup(NoAlloc &na) {
+  unsigned char *base = nullptr;
+  const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&base), HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !base)
+    return fail(GSL_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  int64_t used = 0;
+  auto carve = [&](auto **p, int64_t bytes) {
+    *p = reinterpret_cast<std::remove_pointer_t<decltype(p)>>(base + used);
+    used += al256(bytes);
+  };
+  Scratch &s = na.s;
+  s.fixed = true;
+  carve(&s.ctrl, sizeof(gsl::SweepCtrl));
+  carve(&s.ctr, kNoAllocCtrBytes);
+  s.ctr_bytes = kNoAllocCtrBytes;
+  carve(&s.tier_part, (int64_t)gsl::kNumTiers * gsl::kMaxTierGrid * gsl::kCountFields * 8);
+  carve(&s.Cn, 4LL * GSL_NOALLOC_MAX_VERTICES);
+  carve(&s.chg, kNoAllocFlagBytes);
+  carve(&s.act[0], kNoAllocFlagBytes);
+  carve(&s.act[1], kNoAllocFlagBytes);
+  carve(&s.list, 4LL * GSL_NOALLOC_MAX_VERTICES);
+  carve(&s.parent, 4LL * GSL_NOALLOC_MAX_VERTICES);
+  carve(&s.rep, 4LL * GSL_NOALLOC_MAX_VERTICES);
+  carve(&s.sigma, 8LL * GSL_NOALLOC_MAX_VERTICES);
+  carve(&s.blk_counts, 8 * kNoAllocPlanEntries);
+  s.n_cap = GSL_NOALLOC_MAX_VERTICES;
+  carve(&s.hub_chunk_start, 8LL * (GSL_NOALLOC_MAX_HUBS + 1));
+  carve(&s.hub_part_start, 8LL * (GSL_NOALLOC_MAX_HUBS + 1));
+  carve(&s.hub_hist_start, 8LL * (GSL_NOALLOC_MAX_HUBS + 1));
+  carve(&s.hub_best, 8LL * GSL_NOALLOC_MAX_HUBS);
+  carve(&s.hub_rowsum, 8LL * GSL_NOALLOC_MAX_HUBS);
+  s.hub_cap = GSL_NOALLOC_MAX_HUBS;
+  carve(&s.hub_staging, 8 * kNoAllocStagingPairs);
+  s.hub_staging_cap = kNoAllocStagingPairs;
+  carve(&s.hub_hist, 4 * kNoAllocHistEntries);
+  s.hub_hist_cap = kNoAllocHistEntries;
+  if (used != kNoAllocLayoutBytes) return fail(GSL_EDEVICE, "no-alloc layout mismatch");
+  // host side: pageable mirrors, and room for the hub layout vectors
+  na.pin.assign((size_t)(kPinSmall + 3 * (GSL_NOALLOC_MAX_HUBS + 1)), 0);
+  s.pin = na.pin.data();
+  s.pin_cap = (int64_t)na.pin.size();
+  na.ctr_host.assign((size_t)(kNoAllocCtrBytes / 8), 0);
+  s.ctr_host = reinterpret_cast<Counters *>(na.ctr_host.data());
+  s.h_chunk.reserve(GSL_NOALLOC_MAX_HUBS + 1);
+  s.h_part.reserve(GSL_NOALLOC_MAX_HUBS + 1);
+  s.h_hist.reserve(GSL_NOALLOC_MAX_HUBS + 1);
+  s.hub_max_parts.reserve(GSL_NOALLOC_MAX_HUBS);
+  s.hub_batches.reserve(GSL_NOALLOC_MAX_HUBS);
+  na.ready = true;
   return GSL_OK;
 }
 
@@ -1146,6 +1269,25 @@ int gsl_lpa_ex(const int64_t *offsets, const int32_t *cols, const uint32_t *weig
   Scratch *sp = nullptr;
   if ((rc = get_scratch(&sp))) return rc;
   return lpa_impl(*sp, g_stream, offsets, cols, weights, n, max_iters, tolerance, opt, stats, labels_out);
+}
+
+int gsl_lpa_noalloc(const int64_t *offsets, const int32_t *cols, const uint32_t *weights, int64_t n,
+                    int32_t max_iters, double tolerance, int32_t *labels_out) {
+  int rc = check_lpa(n, max_iters, tolerance, offsets, labels_out);
+  if (rc) return rc == kNoop ? GSL_OK : rc;
+  if (n > GSL_NOALLOC_MAX_VERTICES)
+    return fail(GSL_EINVAL, "n = %lld exceeds the %d vertices of gsl_lpa_noalloc", (long long)n,
+                GSL_NOALLOC_MAX_VERTICES);
+  if (max_iters > GSL_NOALLOC_MAX_ITERS)
+    return fail(GSL_EINVAL, "max_iters = %d exceeds the %d sweeps of gsl_lpa_noalloc", max_iters,
+                GSL_NOALLOC_MAX_ITERS);
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  NoAlloc &na = g_noalloc[dev];
+  if (!na.ready && (rc = noalloc_setup(na))) return rc;
+  const gsl_options o = {1, 1, 0, 2, 0};  // pruning, split, no timing, original layout, synchronous
+  return lpa_impl(na.s, g_stream, offsets, cols, weights, n, max_iters, tolerance, &o, nullptr, labels_out);
 }
 
 int gsl_lpa_f32(const int64_t *offsets, const int32_t *cols, const float *weights, int64_t n, int32_t max_iters,
