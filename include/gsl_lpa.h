@@ -44,7 +44,8 @@ typedef enum gsl_status {
   GSL_EINVAL = -1,    /* bad argument (size, range, NULL where not allowed) */
   GSL_ENOMEM = -2,    /* device allocation of scratch failed */
   GSL_EDEVICE = -3,   /* a HIP runtime call failed; see gsl_last_error() */
-  GSL_EOVERFLOW = -4  /* a row's summed weight reaches 2^32 (see gsl_lpa) */
+  GSL_EOVERFLOW = -4, /* a row's summed weight reaches 2^32 (see gsl_lpa) */
+  GSL_EAGAIN = -5     /* no room in a session right now (see gsl_session_add) */
 } gsl_status;
 
 #define GSL_STATS_MAX_ITERS 64
@@ -325,6 +326,81 @@ void *gsl_context_stream(gsl_context *ctx);
 int gsl_lpa_graphs(gsl_context *ctx, int64_t num_graphs, const gsl_graph *graphs, int32_t max_iters,
                    double tolerance, const gsl_options *opt, gsl_stats *stats, int32_t *iterations_out,
                    int32_t *status_out);
+
+/*
+ * Sessions: continuous batching.  A session keeps a batch of graphs resident
+ * on the device and runs their sweeps; graphs join it and leave it between
+ * sweeps, so a graph submitted while others are running starts with the very
+ * next sweep instead of waiting for a whole batch to drain.  Every graph gets
+ * exactly what gsl_lpa would give it alone (its own sweeps, its own
+ * convergence test dN_g / n_g <= tolerance and sweep count, then the split of
+ * Alg. 2), whatever else shares the session and whenever it joined.
+ *
+ * A session owns a stream (non-blocking, default priority) and device memory
+ * for at most max_vertices vertices and max_entries CSR entries of graphs
+ * running at once (held twice, so that the graphs still running can be moved
+ * together when finished graphs leave gaps) and max_graphs graphs.  Calls on
+ * one session are serialised; calls on different sessions may overlap on the
+ * device.
+ */
+typedef struct gsl_session gsl_session;
+
+/* Device bytes a session of this capacity holds (an upper bound for the hub
+ * tier's buffers, which grow with the hub rows present); -1 for a bad
+ * capacity.  Host-only. */
+int64_t gsl_session_bytes(int64_t max_vertices, int64_t max_entries, int32_t max_graphs, int32_t weighted);
+
+/* New session on the current device.  weighted: graphs may carry uint32
+ * weights (else every graph must pass NULL weights).  max_iters and
+ * tolerance apply to every graph, as in gsl_lpa. */
+int gsl_session_create(int64_t max_vertices, int64_t max_entries, int32_t max_graphs, int32_t max_iters,
+                       double tolerance, int32_t weighted, gsl_session **out);
+/* Waits for the session's stream and frees everything; unfinished graphs'
+ * outputs are left untouched. */
+void gsl_session_destroy(gsl_session *s);
+/* The session's stream (hipStream_t). */
+void *gsl_session_stream(gsl_session *s);
+
+/*
+ * gsl_session_add -- admits graphs (host array graphs[num_graphs] of device
+ * descriptors, local ids, as for gsl_lpa_graphs) in order.  For each graph:
+ *   status_out[g] = GSL_OK     admitted; tickets_out[g] names it in the
+ *                              results of gsl_session_step (an empty graph
+ *                              needs no sweep: ticket -1, nothing to write)
+ *                   GSL_EAGAIN no room right now (vertices, entries or graph
+ *                              slots of the session are taken): submit again
+ *                              after a step has finished some graphs; every
+ *                              later graph of the call gets GSL_EAGAIN too
+ *                   GSL_EINVAL decreasing offsets, an entry outside [0, n),
+ *                              weights in an unweighted session, or a graph
+ *                              larger than the session could ever hold
+ * The graph's arrays are copied into the session before the call returns;
+ * the caller may reuse them at once, but labels_out must stay valid until
+ * the graph's ticket has come back from gsl_session_step.
+ */
+int gsl_session_add(gsl_session *s, int64_t num_graphs, const gsl_graph *graphs, int64_t *tickets_out,
+                    int32_t *status_out);
+
+/*
+ * gsl_session_step -- runs up to `sweeps` (1 .. 64) synchronous sweeps of
+ * every graph in the session (Alg. 3, each graph on its own, as in
+ * gsl_lpa_batched), then the split of every graph that has stopped, whose
+ * labels (local ids) go to its labels_out.  Returns when that is done.
+ *   done_tickets     : HOST int64[capacity], tickets of the graphs finished
+ *                      by this call (at most capacity; others finish in a
+ *                      later call)
+ *   done_iterations  : HOST int32[capacity] (may be NULL), their sweep counts
+ *   done_count       : HOST, how many were written
+ * GSL_EOVERFLOW when a row's summed weight reaches 2^32; the session's
+ * running graphs are then lost (destroy it).
+ */
+int gsl_session_step(gsl_session *s, int32_t sweeps, int64_t capacity, int64_t *done_tickets,
+                     int32_t *done_iterations, int64_t *done_count);
+
+/* Graphs running, their vertices and entries, free capacity, device bytes
+ * held (any pointer may be NULL). */
+int gsl_session_info(gsl_session *s, int64_t *live_graphs, int64_t *live_vertices, int64_t *live_entries,
+                     int64_t *free_vertices, int64_t *free_entries, int64_t *device_bytes);
 
 /*
  * gsl_check_graph -- checks a CSR on the device: offsets[0] == 0, offsets

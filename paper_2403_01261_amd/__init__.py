@@ -124,6 +124,19 @@ def load(path: str = None):
     lib.gsl_convergence_limit.restype = ctypes.c_int64
     lib.gsl_set_hub_limits.argtypes = [ctypes.c_int64, ctypes.c_int32]
     lib.gsl_lpa_noalloc.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _VP]
+    lib.gsl_session_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+    lib.gsl_session_bytes.restype = ctypes.c_int64
+    lib.gsl_session_create.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_VP)]
+    lib.gsl_session_destroy.argtypes = [_VP]
+    lib.gsl_session_destroy.restype = None
+    lib.gsl_session_stream.argtypes = [_VP]
+    lib.gsl_session_stream.restype = _VP
+    lib.gsl_session_add.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(_Graph), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.gsl_session_step.argtypes = [_VP, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.gsl_session_info.argtypes = [_VP] + [ctypes.POINTER(ctypes.c_int64)] * 6
     lib.gsl_set_stream.argtypes = [_VP]
     lib.gsl_last_error.restype = ctypes.c_char_p
     lib.gsl_version.restype = ctypes.c_char_p
@@ -132,7 +145,8 @@ def load(path: str = None):
               lib.gsl_lpa_batched, lib.gsl_lpa_batched_ex, lib.gsl_context_create, lib.gsl_context_set_stream,
               lib.gsl_lpa_graphs, lib.gsl_check_graph, lib.gsl_disconnected, lib.gsl_set_tiers,
               lib.gsl_get_tiers, lib.gsl_tier_variant, lib.gsl_split_ex, lib.gsl_lpa_f32,
-              lib.gsl_set_hub_limits, lib.gsl_lpa_noalloc):
+              lib.gsl_set_hub_limits, lib.gsl_lpa_noalloc, lib.gsl_session_create, lib.gsl_session_add,
+              lib.gsl_session_step, lib.gsl_session_info):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -353,6 +367,89 @@ class Context:
         if self._h is not None:
             self._lib.gsl_context_destroy(self._h)
             self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+GSL_EAGAIN = -5
+
+
+class Session:
+    """Continuous batching (gsl_session): a resident batch that graphs join
+    and leave between sweeps.  add() admits graphs (lists of (offsets, cols[,
+    weights[, out]]) tensors) and returns (ticket, status, out) per graph;
+    step(sweeps) runs that many sweeps of every resident graph and returns
+    [(ticket, sweeps_run)] of the graphs that finished, whose labels are then
+    in their out tensors.  Each result equals gsl_lpa on the graph alone."""
+
+    def __init__(self, max_vertices, max_entries, max_graphs=1024, max_iters=20, tolerance=0.05,
+                 weighted=False):
+        self._lib = load()
+        h = _VP()
+        _check(self._lib.gsl_session_create(int(max_vertices), int(max_entries), int(max_graphs), int(max_iters),
+                                            float(tolerance), int(bool(weighted)), ctypes.byref(h)))
+        self._h = h
+        self.max_graphs = int(max_graphs)
+        self.stream = torch.cuda.ExternalStream(self._lib.gsl_session_stream(h))
+        # output tensors of the running graphs, held until their graph
+        # finishes (the session writes them at the end of a later step)
+        self._outs = {}
+
+    @staticmethod
+    def device_bytes(max_vertices, max_entries, max_graphs=1024, weighted=False) -> int:
+        """Device bytes a session of this capacity holds (library query)."""
+        return int(load().gsl_session_bytes(int(max_vertices), int(max_entries), int(max_graphs),
+                                            int(bool(weighted))))
+
+    def add(self, graphs):
+        if self._h is None:
+            raise RuntimeError("session closed")
+        G = len(graphs)
+        if G == 0:
+            return []
+        tab, outs = _graph_table(graphs)
+        tickets = (ctypes.c_int64 * G)()
+        status = (ctypes.c_int32 * G)()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        _check(self._lib.gsl_session_add(self._h, G, tab, tickets, status))
+        for k in range(G):
+            if tickets[k] >= 0:
+                self._outs[tickets[k]] = outs[k]
+        return [(tickets[k], status[k], outs[k]) for k in range(G)]
+
+    def step(self, sweeps=1, capacity=None):
+        if self._h is None:
+            raise RuntimeError("session closed")
+        cap = int(capacity if capacity is not None else self.max_graphs)
+        t = (ctypes.c_int64 * max(cap, 1))()
+        it = (ctypes.c_int32 * max(cap, 1))()
+        cnt = ctypes.c_int64(0)
+        _check(self._lib.gsl_session_step(self._h, int(sweeps), cap, t, it, ctypes.byref(cnt)))
+        for k in range(cnt.value):
+            self._outs.pop(t[k], None)
+        return [(t[k], it[k]) for k in range(cnt.value)]
+
+    def info(self):
+        vals = [ctypes.c_int64(0) for _ in range(6)]
+        _check(self._lib.gsl_session_info(self._h, *[ctypes.byref(v) for v in vals]))
+        keys = ("live_graphs", "live_vertices", "live_entries", "free_vertices", "free_entries", "device_bytes")
+        return {k: v.value for k, v in zip(keys, vals)}
+
+    def close(self):
+        if self._h is not None:
+            self._lib.gsl_session_destroy(self._h)
+            self._h = None
+            self._outs.clear()
 
     def __enter__(self):
         return self

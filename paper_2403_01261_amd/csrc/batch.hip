@@ -91,8 +91,8 @@ __global__ __launch_bounds__(kBlock) void graph_entries(const GraphDesc *__restr
 __global__ __launch_bounds__(kBlock) void gather_offsets(const GraphDesc *__restrict__ d,
                                                          const int64_t *__restrict__ vtx_base,
                                                          const int64_t *__restrict__ edge_base, int64_t G,
-                                                         int64_t N, int64_t *__restrict__ off) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) off[N] = edge_base[G];
+                                                         int64_t N, int64_t eshift, int64_t *__restrict__ off) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) off[N] = eshift + edge_base[G];
   for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < N; t0 += (int64_t)gridDim.x * kTile) {
     int64_t g = tile_graph(vtx_base, G, t0);
 #pragma unroll 4
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void gather_offsets(const GraphDesc *__rest
       if (v >= N) break;
       while (vtx_base[g + 1] <= v) ++g;
       const int64_t *o = d[g].offsets;
-      off[v] = edge_base[g] + (o[v - vtx_base[g]] - o[0]);
+      off[v] = eshift + edge_base[g] + (o[v - vtx_base[g]] - o[0]);
     }
   }
 }
@@ -121,7 +121,7 @@ __global__ void check_bases(const int64_t *__restrict__ vtx_base, const int64_t 
 __global__ __launch_bounds__(kBlock) void gather_entries(const GraphDesc *__restrict__ d,
                                                          const int64_t *__restrict__ vtx_base,
                                                          const int64_t *__restrict__ edge_base, int64_t G,
-                                                         int64_t nnz, int32_t *__restrict__ cols,
+                                                         int64_t nnz, int64_t vshift, int32_t *__restrict__ cols,
                                                          uint32_t *__restrict__ w, uint32_t *__restrict__ bad) {
   for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < nnz; t0 += (int64_t)gridDim.x * kTile) {
     int64_t g = tile_graph(edge_base, G, t0);
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void gather_entries(const GraphDesc *__rest
         atomicOr(&bad[g], 1u);
         c = 0;
       }
-      cols[e] = c + (int32_t)vtx_base[g];
+      cols[e] = c + (int32_t)(vshift + vtx_base[g]);
       if (w) w[e] = x.weights ? x.weights[src] : 1u;
     }
   }
@@ -190,6 +190,94 @@ __global__ __launch_bounds__(kBlock) void check_graph(const int64_t *__restrict_
   if (b) atomicOr(bad, (unsigned long long)b);
 }
 
+// ---- sessions (continuous batching) ----
+// Block per range (grid-stride): the vertices of a newly admitted graph get
+// its slot, their own global id as label and the active flag of both sweeps
+// parities (its first sweep processes every vertex, whatever the pruning
+// state of the others).
+__global__ __launch_bounds__(kBlock) void session_admit(const SessionRange *__restrict__ r, int64_t count,
+                                                        int32_t *__restrict__ gid, int32_t *__restrict__ lab,
+                                                        uint8_t *__restrict__ act0, uint8_t *__restrict__ act1) {
+  for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const SessionRange x = r[i];
+    for (int64_t v = x.vb + threadIdx.x; v < x.vb + x.n; v += kBlock) {
+      gid[v] = x.slot;
+      lab[v] = (int32_t)v;
+      act0[v] = 1;
+      act1[v] = 1;
+    }
+  }
+}
+
+// Per-slot loop state of admitted graphs: convergence limit, no sweep yet,
+// running unless max_iters is 0.
+__global__ void session_slots(const SessionRange *__restrict__ r, int64_t count, int32_t max_iters, double tol,
+                              int64_t *__restrict__ glimit, int32_t *__restrict__ giters,
+                              uint8_t *__restrict__ gdone, int64_t *__restrict__ gdn) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const SessionRange x = r[i];
+  glimit[x.slot] = x.limit;
+  giters[x.slot] = 0;
+  gdn[x.slot] = 0;
+  gdone[x.slot] = max_iters <= 0 ? 1 : 0;
+}
+
+// Labels for the split of the finishing graphs: theirs as they are, every
+// other vertex its own id (a vertex whose label no neighbour shares joins
+// nothing, so the split passes over the other graphs at little cost).
+__global__ __launch_bounds__(kBlock) void session_split_labels(const int32_t *__restrict__ lab,
+                                                               const int32_t *__restrict__ gid,
+                                                               const uint8_t *__restrict__ sel, int64_t n,
+                                                               int32_t *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride)
+    out[v] = sel[gid[v]] ? lab[v] : (int32_t)v;
+}
+
+// Block per finishing graph: its split labels as local ids into its output,
+// its vertices handed to the dead slot.
+__global__ __launch_bounds__(kBlock) void session_finish(const SessionRange *__restrict__ r, int64_t count,
+                                                         const int32_t *__restrict__ split,
+                                                         int32_t *__restrict__ gid, int32_t dead) {
+  for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const SessionRange x = r[i];
+    for (int64_t k = threadIdx.x; k < x.n; k += kBlock) {
+      x.labels_out[k] = split[x.vb + k] - (int32_t)x.vb;
+      gid[x.vb + k] = dead;
+    }
+  }
+}
+
+// Block per live graph: its CSR rows, entries, weights and labels copied from
+// one arena buffer to the other at its new position (ids shifted by the
+// vertex move, offsets by the entry move), its vertices given its slot and
+// both active flags.
+__global__ __launch_bounds__(kBlock) void session_move(const SessionRange *__restrict__ r, int64_t count,
+                                                       const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
+                                                       const uint32_t *__restrict__ w, const int32_t *__restrict__ lab,
+                                                       int64_t *__restrict__ off2, int32_t *__restrict__ cols2,
+                                                       uint32_t *__restrict__ w2, int32_t *__restrict__ lab2,
+                                                       int32_t *__restrict__ gid, uint8_t *__restrict__ act0,
+                                                       uint8_t *__restrict__ act1) {
+  for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const SessionRange x = r[i];
+    const int32_t dv = (int32_t)(x.new_vb - x.vb);
+    const int64_t de = x.new_eb - x.eb;
+    for (int64_t k = threadIdx.x; k < x.n; k += kBlock) {
+      off2[x.new_vb + k] = off[x.vb + k] + de;
+      lab2[x.new_vb + k] = lab[x.vb + k] + dv;
+      gid[x.new_vb + k] = x.slot;
+      act0[x.new_vb + k] = 1;
+      act1[x.new_vb + k] = 1;
+    }
+    for (int64_t e = threadIdx.x; e < x.nnz; e += kBlock) {
+      cols2[x.new_eb + e] = cols[x.eb + e] + dv;
+      if (w) w2[x.new_eb + e] = w[x.eb + e];
+    }
+  }
+}
+
 unsigned tiles(int64_t count) {
   const int64_t t = (count + kTile - 1) / kTile;
   const int64_t cap = 256 * 64;
@@ -227,11 +315,49 @@ hipError_t launch_graph_entries(const GraphDesc *d, int64_t G, int64_t *cnt, hip
 }
 
 hipError_t launch_gather(const GraphDesc *d, const int64_t *vtx_base, const int64_t *edge_base, int64_t G,
-                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, uint32_t *bad,
-                         hipStream_t s) {
+                         int64_t N, int64_t nnz, int64_t vshift, int64_t eshift, int64_t *off, int32_t *cols,
+                         uint32_t *w, uint32_t *bad, hipStream_t s) {
   if (G <= 0) return hipSuccess;
-  gather_offsets<<<tiles(N + 1), kBlock, 0, s>>>(d, vtx_base, edge_base, G, N, off);
-  if (nnz > 0) gather_entries<<<tiles(nnz), kBlock, 0, s>>>(d, vtx_base, edge_base, G, nnz, cols, w, bad);
+  gather_offsets<<<tiles(N + 1), kBlock, 0, s>>>(d, vtx_base, edge_base, G, N, eshift, off);
+  if (nnz > 0)
+    gather_entries<<<tiles(nnz), kBlock, 0, s>>>(d, vtx_base, edge_base, G, nnz, vshift, cols, w, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_session_admit(const SessionRange *r, int64_t count, int32_t *gid, int32_t *lab, uint8_t *act0,
+                                uint8_t *act1, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  session_admit<<<(unsigned)(count < 4096 ? count : 4096), kBlock, 0, s>>>(r, count, gid, lab, act0, act1);
+  return hipGetLastError();
+}
+
+hipError_t launch_session_slots(const SessionRange *r, int64_t count, int32_t max_iters, double tol, int64_t *glimit,
+                                int32_t *giters, uint8_t *gdone, int64_t *gdn, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  session_slots<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(r, count, max_iters, tol, glimit, giters, gdone, gdn);
+  return hipGetLastError();
+}
+
+hipError_t launch_session_split_labels(const int32_t *lab, const int32_t *gid, const uint8_t *sel, int64_t n,
+                                       int32_t *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  session_split_labels<<<tiles(n), kBlock, 0, s>>>(lab, gid, sel, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_session_finish(const SessionRange *r, int64_t count, const int32_t *split, int32_t *gid,
+                                 int32_t dead, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  session_finish<<<(unsigned)(count < 4096 ? count : 4096), kBlock, 0, s>>>(r, count, split, gid, dead);
+  return hipGetLastError();
+}
+
+hipError_t launch_session_move(const SessionRange *r, int64_t count, const int64_t *off, const int32_t *cols,
+                               const uint32_t *w, const int32_t *lab, int64_t *off2, int32_t *cols2, uint32_t *w2,
+                               int32_t *lab2, int32_t *gid, uint8_t *act0, uint8_t *act1, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  session_move<<<(unsigned)(count < 4096 ? count : 4096), kBlock, 0, s>>>(r, count, off, cols, w, lab, off2, cols2,
+                                                                         w2, lab2, gid, act0, act1);
   return hipGetLastError();
 }
 

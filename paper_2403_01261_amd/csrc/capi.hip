@@ -100,7 +100,9 @@ struct Scratch {
   // hub tier layout (prefix sums over the hubs of the current graph)
   int64_t hub_cap = 0;
   int64_t *hub_chunk_start = nullptr, *hub_part_start = nullptr, *hub_hist_start = nullptr;
-  unsigned long long *hub_best = nullptr, *hub_rowsum = nullptr;
+  unsigned long long *hub_best = nullptr, *hub_rowsum = nullptr, *hub_records = nullptr;
+  int32_t *hub_chunk_owner = nullptr, *hub_part_owner = nullptr;  // hub of every chunk / partition
+  int64_t hub_chunk_owner_cap = 0, hub_part_owner_cap = 0;
   unsigned long long *hub_staging = nullptr;  // (label, sum) pairs of one batch
   int32_t *hub_hist = nullptr;                // partition bounds of one batch
   int64_t hub_staging_cap = 0, hub_hist_cap = 0;
@@ -161,6 +163,51 @@ struct gsl_context {
 };
 
 namespace {
+// One graph of a session (host side).
+struct SessionSlot {
+  bool live = false;
+  int64_t ticket = -1;
+  int64_t vb = 0, n = 0, eb = 0, nnz = 0, limit = 0;
+  int32_t *labels_out = nullptr;
+};
+constexpr int kSessionSweepCap = 64;  // most sweeps one gsl_session_step runs
+}  // namespace
+
+// A session: a resident batch (the arena) that graphs join and leave between
+// sweeps.  Every live graph owns a vertex range and an entry range of the
+// arena, holds global ids there, and runs exactly the sweeps it would run
+// alone; a finished graph's ranges stay as dead space (vertices of the dead
+// slot, never processed) until a compaction moves the live graphs together.
+struct gsl_session {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  Scratch s;
+  int64_t cap_v = 0, cap_e = 0;
+  int32_t cap_g = 0;
+  int32_t max_iters = 20;
+  double tol = 0.05;
+  bool weighted = false;
+  int cur = 0;  // arena buffer in use (the other is the compaction target)
+  int64_t *off[2] = {nullptr, nullptr};
+  int32_t *cols[2] = {nullptr, nullptr};
+  uint32_t *w[2] = {nullptr, nullptr};
+  int32_t *lab[2] = {nullptr, nullptr};
+  int32_t *split_in = nullptr, *split_out = nullptr;
+  uint8_t *sel = nullptr;             // [cap_g + 1] graphs finishing in this step
+  gsl::SessionRange *ranges = nullptr;  // [cap_g] range records for the kernels
+  int64_t vtop = 0, etop = 0;         // arena in use: [0, vtop) vertices, [0, etop) entries
+  int64_t live_v = 0, live_e = 0;
+  std::vector<SessionSlot> slot;
+  std::vector<int32_t> free_slot;
+  int64_t next_ticket = 0;
+  bool dirty = true;                  // the arena changed since the last plan
+  gsl::Counters plan{};
+  gsl::SweepCtrl ctrl{};              // loop state carried from step to step
+  int64_t bytes = 0;                  // device bytes allocated at creation
+};
+
+namespace {
 
 // Returns event k of the pool, creating events on demand.
 hipEvent_t pool_event(Scratch &s, size_t k) {
@@ -192,6 +239,9 @@ void free_scratch(Scratch &s) {
   hipFree(s.hub_hist_start);
   hipFree(s.hub_best);
   hipFree(s.hub_rowsum);
+  hipFree(s.hub_records);
+  hipFree(s.hub_chunk_owner);
+  hipFree(s.hub_part_owner);
   hipFree(s.hub_staging);
   hipFree(s.hub_hist);
   if (s.ctr_host) hipHostFree(s.ctr_host);
@@ -386,12 +436,13 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
     hipFree(s.hub_hist_start);
     hipFree(s.hub_best);
     hipFree(s.hub_rowsum);
+    hipFree(s.hub_records);
     s.hub_chunk_start = s.hub_part_start = s.hub_hist_start = nullptr;
-    s.hub_best = s.hub_rowsum = nullptr;
+    s.hub_best = s.hub_rowsum = s.hub_records = nullptr;
     s.hub_cap = 0;
     if (dmalloc(&s.hub_chunk_start, H + 1) != hipSuccess || dmalloc(&s.hub_part_start, H + 1) != hipSuccess ||
         dmalloc(&s.hub_hist_start, H + 1) != hipSuccess || dmalloc(&s.hub_best, H) != hipSuccess ||
-        dmalloc(&s.hub_rowsum, H) != hipSuccess) {
+        dmalloc(&s.hub_rowsum, H) != hipSuccess || dmalloc(&s.hub_records, H) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GSL_ENOMEM, "hub layout allocation failed");
     }
@@ -399,7 +450,7 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
   }
   HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_best), 0, H, st));
   HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.hub_rowsum), 0, H, st));
-  gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
+  gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start, nullptr, nullptr, s.hub_records};
   HIP_TRY(gsl::launch_hub_layout(offsets, hubs, H, L, st));
   int rc = ensure_pinned(s, kPinSmall + 3 * (H + 1));
   if (rc) return rc;
@@ -411,6 +462,25 @@ int prepare_hubs(Scratch &s, const int64_t *offsets, const int32_t *hubs, int64_
   s.h_chunk.assign(ph, ph + (H + 1));
   s.h_part.assign(ph + (H + 1), ph + 2 * (H + 1));
   s.h_hist.assign(ph + 2 * (H + 1), ph + 3 * (H + 1));
+  // the hub of every chunk and partition (one load in the kernels instead of
+  // a binary search over the hubs)
+  const int64_t total_chunks = s.h_chunk[(size_t)H], total_parts = s.h_part[(size_t)H];
+  if (total_chunks > s.hub_chunk_owner_cap || total_parts > s.hub_part_owner_cap) {
+    if (s.fixed) return fail(GSL_EINVAL, "%lld hub chunks exceed the no-alloc scratch", (long long)total_chunks);
+    hipFree(s.hub_chunk_owner);
+    hipFree(s.hub_part_owner);
+    s.hub_chunk_owner = s.hub_part_owner = nullptr;
+    s.hub_chunk_owner_cap = s.hub_part_owner_cap = 0;
+    if (dmalloc(&s.hub_chunk_owner, total_chunks) != hipSuccess || dmalloc(&s.hub_part_owner, total_parts) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GSL_ENOMEM, "hub owner allocation failed");
+    }
+    s.hub_chunk_owner_cap = total_chunks;
+    s.hub_part_owner_cap = total_parts;
+  }
+  L.chunk_owner = s.hub_chunk_owner;
+  L.part_owner = s.hub_part_owner;
+  HIP_TRY(gsl::launch_hub_owners(L, H, st));
   const int64_t chunk_cap = staging_bytes / ((int64_t)gsl::kHubChunk * 8);
   int64_t k0 = 0;
   for (int64_t k = 0; k < H; ++k) {
@@ -593,7 +663,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
       HIP_TRY(hipEventRecord(s.ev_reorder, st));
     }
     HIP_TRY(gsl::launch_reorder(offsets, cols, weights, n, s.list, plan.tier_count, plan.tier_start,
-                                s.hub_chunk_start, H > 0 ? s.h_chunk[(size_t)H] : 0, s.old2new, s.off2,
+                                s.hub_chunk_start, s.hub_chunk_owner, H > 0 ? s.h_chunk[(size_t)H] : 0, s.old2new, s.off2,
                                 s.cols2, weights ? s.w2 : nullptr, s.lab2, s.blk_counts, s.first_key,
                                 s.hub_rowsum, reinterpret_cast<unsigned long long *>(&s.ctr->first_flags),
                                 dn_arr, max_iters > 0 ? 1 : 0, cfg, st));
@@ -614,6 +684,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   gsl::SweepCtrl hc;
   memset(&hc, 0, sizeof(hc));
   hc.max_iters = max_iters;
+  hc.graph_max_iters = max_iters;
   hc.prune = o.prune ? 1 : 0;
   hc.limit = gsl_convergence_limit(n, tolerance);
   hc.n = n;
@@ -663,7 +734,8 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   a.gdone = batch ? s.gdone : nullptr;
   a.inplace = o.async_sweeps ? 1 : 0;
   a.n = n;
-  const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start};
+  const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start, s.hub_chunk_owner,
+                         s.hub_part_owner, s.hub_records};
 
   // Timing records (timing mode only).
   std::vector<Launch> launches;
@@ -770,6 +842,8 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
                                  (uint64_t)(uintptr_t)s.hub_hist, (uint64_t)(uintptr_t)s.hub_best,
                                  (uint64_t)(uintptr_t)s.hub_rowsum, (uint64_t)(uintptr_t)s.hub_chunk_start,
                                  (uint64_t)(uintptr_t)s.hub_part_start, (uint64_t)(uintptr_t)s.hub_hist_start,
+                                 (uint64_t)(uintptr_t)s.hub_chunk_owner, (uint64_t)(uintptr_t)s.hub_part_owner,
+                                 (uint64_t)(uintptr_t)s.hub_records,
                                  (uint64_t)(uintptr_t)(batch ? batch->vtx_base : nullptr),
                                  (uint64_t)(batch ? batch->graphs : 0), (uint64_t)(uintptr_t)s.gid,
                                  (uint64_t)(uintptr_t)s.gdn, (uint64_t)(uintptr_t)s.glimit,
@@ -960,6 +1034,7 @@ constexpr int64_t kNoAllocStagingPairs = (int64_t)1 << 20;  // 512 chunks: hub r
 constexpr int64_t kNoAllocStagingChunks = kNoAllocStagingPairs / gsl::kHubChunk;
 // Partition records of one staging batch: sum over its hubs of chunks * (partitions + 1), partitions == chunks.
 constexpr int64_t kNoAllocHistEntries = kNoAllocStagingChunks * (kNoAllocStagingChunks + 1);
+constexpr int64_t kNoAllocHubChunks = (int64_t)1 << 16;  // hub rows of up to 2^27 entries in all
 constexpr int64_t kNoAllocCtrBytes =
     (int64_t)sizeof(Counters) + 4 * (int64_t)sizeof(uint64_t) * GSL_NOALLOC_MAX_ITERS;
 
@@ -973,7 +1048,8 @@ constexpr int64_t kNoAllocLayoutBytes =
     al256(4LL * GSL_NOALLOC_MAX_VERTICES) + 3 * al256(kNoAllocFlagBytes) +   // Cn, chg, act[2]
     3 * al256(4LL * GSL_NOALLOC_MAX_VERTICES) +                              // list, parent, rep
     al256(8LL * GSL_NOALLOC_MAX_VERTICES) + al256(8 * kNoAllocPlanEntries) +  // sigma, plan counts
-    3 * al256(8LL * (GSL_NOALLOC_MAX_HUBS + 1)) + 2 * al256(8LL * GSL_NOALLOC_MAX_HUBS) +
+    3 * al256(8LL * (GSL_NOALLOC_MAX_HUBS + 1)) + 3 * al256(8LL * GSL_NOALLOC_MAX_HUBS) +
+    2 * al256(4 * kNoAllocHubChunks) +
     al256(8 * kNoAllocStagingPairs) + al256(4 * kNoAllocHistEntries);
 static_assert(kNoAllocLayoutBytes <= GSL_NOALLOC_SCRATCH_BYTES, "the no-alloc buffers fit the static scratch");
 
@@ -1018,7 +1094,11 @@ int noalloc_setup(NoAlloc &na) {
   carve(&s.hub_hist_start, 8LL * (GSL_NOALLOC_MAX_HUBS + 1));
   carve(&s.hub_best, 8LL * GSL_NOALLOC_MAX_HUBS);
   carve(&s.hub_rowsum, 8LL * GSL_NOALLOC_MAX_HUBS);
+  carve(&s.hub_records, 8LL * GSL_NOALLOC_MAX_HUBS);
   s.hub_cap = GSL_NOALLOC_MAX_HUBS;
+  carve(&s.hub_chunk_owner, 4 * kNoAllocHubChunks);
+  carve(&s.hub_part_owner, 4 * kNoAllocHubChunks);
+  s.hub_chunk_owner_cap = s.hub_part_owner_cap = kNoAllocHubChunks;
   carve(&s.hub_staging, 8 * kNoAllocStagingPairs);
   s.hub_staging_cap = kNoAllocStagingPairs;
   carve(&s.hub_hist, 4 * kNoAllocHistEntries);
@@ -1201,7 +1281,7 @@ int batched_graphs(Scratch &s, hipStream_t st, int64_t G, const gsl_graph *graph
     if ((rc = ensure_array(&s.gcols, &s.gcols_cap, nnz, "global cols"))) return rc;
     if (weighted && (rc = ensure_array(&s.gw, &s.gw_cap, nnz, "global weights"))) return rc;
     if ((rc = ensure_array(&s.glab, &s.batch_glab_cap, N, "batch labels"))) return rc;
-    HIP_TRY(gsl::launch_gather(s.gdesc, s.gvb, s.geb, G, N, nnz, s.goff, s.gcols, weighted ? s.gw : nullptr,
+    HIP_TRY(gsl::launch_gather(s.gdesc, s.gvb, s.geb, G, N, nnz, 0, 0, s.goff, s.gcols, weighted ? s.gw : nullptr,
                                s.gflag, st));
     gsl_options o = {1, 1, 0, 0, 0};
     if (opt) o = *opt;
@@ -1247,6 +1327,325 @@ int check_graph_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const i
   HIP_TRY(hipStreamSynchronize(st));
   if (bad & 1) return fail(GSL_EINVAL, "offsets decrease");
   if (bad & 2) return fail(GSL_EINVAL, "a column index is outside [0, n)");
+  return GSL_OK;
+}
+
+// ---- sessions ----
+// Device bytes of a session of this capacity: the arena (two buffers), the
+// split buffers and per-graph records, the per-vertex and per-graph scratch,
+// and a bound on the hub tier's layout and staging (at most one hub per
+// 4,097 entries, every entry in a hub row).
+int64_t session_bytes(int64_t cap_v, int64_t cap_e, int64_t cap_g, bool weighted) {
+  const int64_t G = cap_g + 1;
+  const int64_t flag = (cap_v + 3) / 4 * 4 + 16;
+  int64_t b = 2 * ((cap_v + 1) * 8 + cap_e * 4 * (weighted ? 2 : 1) + cap_v * 4);  // arena
+  b += 2 * cap_v * 4 + G + cap_g * (int64_t)sizeof(gsl::SessionRange);           // split, sel, ranges
+  b += cap_v * (4 + 4 + 4 + 4 + 8) + 3 * flag + gsl::plan_scratch(cap_v) * 8;      // Cn list parent rep sigma, flags, plan
+  b += 2 * 4096 * 8 + (int64_t)gsl::kNumTiers * gsl::kMaxTierGrid * gsl::kCountFields * 8;  // partials, tier records
+  b += (int64_t)sizeof(Counters) + 4 * 8 * (kSessionSweepCap + 2) + (int64_t)sizeof(gsl::SweepCtrl);
+  b += cap_v * 4 + G * (4 + 8 + 8 + 1 + 8 + 8 + 8 + (int64_t)sizeof(gsl::GraphDesc) + 4) + 8;  // batch arrays
+  const int64_t hubs = cap_e / 4097 + 1, chunks = cap_e / gsl::kHubChunk + hubs;
+  const int64_t staging_pairs = std::min<int64_t>(cap_e + (int64_t)gsl::kHubChunk * hubs,
+                                                  kDefaultHubStagingBytes / 8 + gsl::kHubChunk);
+  b += hubs * (3 * 8 + 3 * 8) + 2 * chunks * 4 + staging_pairs * 8 + chunks * 4 * 2;  // hub layout, owners, staging, hist
+  return b;
+}
+
+void session_free(gsl_session &S) {
+  for (int b = 0; b < 2; ++b) {
+    hipFree(S.off[b]);
+    hipFree(S.cols[b]);
+    hipFree(S.w[b]);
+    hipFree(S.lab[b]);
+  }
+  hipFree(S.split_in);
+  hipFree(S.split_out);
+  hipFree(S.sel);
+  hipFree(S.ranges);
+  free_scratch(S.s);
+}
+
+// One sweep of every live graph of the arena (tiers, hubs, counts, apply,
+// per-graph stop decisions, loop state), enqueued on st; every kernel returns
+// at once once the loop state says done.
+int session_enqueue_sweep(gsl_session &S, const gsl::SweepArgs &a0, const gsl::TierConfig &cfg,
+                          const HubLimits &lim, hipStream_t st) {
+  Scratch &s = S.s;
+  gsl::SweepArgs a = a0;
+  const Counters &plan = S.plan;
+  const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start, s.hub_chunk_owner,
+                         s.hub_part_owner, s.hub_records};
+  gsl::TierGrids grids;
+  for (int t = 0; t < gsl::kNumTiers; ++t) grids.g[t] = 0;
+  for (int t = 1; t < gsl::kNumTiers; ++t) {
+    const int64_t cnt = plan.tier_count[t];
+    if (cnt <= 0) continue;
+    a.tier = &s.ctr->tier_stats[t][0];
+    a.part = s.tier_part + (size_t)t * gsl::kMaxTierGrid * gsl::kCountFields;
+    if (t == gsl::kHubTier) {
+      for (size_t bi = 0; bi < s.hub_batches.size(); ++bi)
+        for (int stage = 0; stage < 2; ++stage)
+          HIP_TRY(gsl::launch_hub_sweep(a, s.list, L, s.h_chunk.data(), s.h_part.data(), s.hub_staging, s.hub_hist,
+                                        s.hub_best, s.hub_rowsum, s.hub_batches[bi].first, s.hub_batches[bi].second,
+                                        s.hub_max_parts[bi], lim.merge_cap, stage, st));
+    } else {
+      HIP_TRY(gsl::launch_sweep_tier(cfg.variant[t], a, s.list, plan.tier_start[t], cnt, &grids.g[t], st));
+    }
+  }
+  HIP_TRY(gsl::launch_reduce_counts(s.tier_part, grids, s.ctr->tier_stats, s.ctrl, a.dn, a.processed, a.edges,
+                                    a.overflow, st));
+  HIP_TRY(gsl::launch_apply(a, S.lab[S.cur], S.vtop, s.gdn, st));
+  HIP_TRY(gsl::launch_graph_end(s.ctrl, s.gdn, s.glimit, s.giters, s.gdone, (int64_t)S.cap_g + 1, st));
+  HIP_TRY(gsl::launch_sweep_end(s.ctrl, a.dn, a.marked_sweeps, a.overflow, st));
+  return GSL_OK;
+}
+
+// Moves the live graphs to the front of the other arena buffer, in order.
+int session_compact(gsl_session &S) {
+  Scratch &s = S.s;
+  const hipStream_t st = S.stream;
+  std::vector<int32_t> live;
+  for (int32_t k = 0; k < S.cap_g; ++k)
+    if (S.slot[(size_t)k].live) live.push_back(k);
+  std::sort(live.begin(), live.end(), [&](int32_t x, int32_t y) { return S.slot[(size_t)x].vb < S.slot[(size_t)y].vb; });
+  std::vector<gsl::SessionRange> r(live.size());
+  int64_t v = 0, e = 0;
+  for (size_t i = 0; i < live.size(); ++i) {
+    SessionSlot &x = S.slot[(size_t)live[i]];
+    r[i] = gsl::SessionRange{x.vb, x.n, x.eb, x.nnz, v, e, x.limit, x.labels_out, live[i], 0};
+    x.vb = v;
+    x.eb = e;
+    v += x.n;
+    e += x.nnz;
+  }
+  const int o = 1 - S.cur;
+  if (!r.empty()) {
+    HIP_TRY(hipMemcpyAsync(S.ranges, r.data(), r.size() * sizeof(gsl::SessionRange), hipMemcpyHostToDevice, st));
+    HIP_TRY(gsl::launch_session_move(S.ranges, (int64_t)r.size(), S.off[S.cur], S.cols[S.cur],
+                                     S.weighted ? S.w[S.cur] : nullptr, S.lab[S.cur], S.off[o], S.cols[o],
+                                     S.weighted ? S.w[o] : nullptr, S.lab[o], s.gid, s.act[0], s.act[1], st));
+  }
+  HIP_TRY(hipMemcpyAsync(S.off[o] + v, &e, sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));  // r and e are host temporaries
+  S.cur = o;
+  S.vtop = v;
+  S.etop = e;
+  S.dirty = true;
+  return GSL_OK;
+}
+
+int session_add(gsl_session &S, int64_t G, const gsl_graph *graphs, int64_t *tickets, int32_t *status) {
+  Scratch &s = S.s;
+  const hipStream_t st = S.stream;
+  for (int64_t g = 0; g < G; ++g) {
+    tickets[g] = -1;
+    status[g] = GSL_OK;
+  }
+  // entry counts (and decreasing offsets) of every graph on the device
+  HIP_TRY(hipMemcpyAsync(s.gdesc, graphs, (size_t)G * sizeof(gsl_graph), hipMemcpyHostToDevice, st));
+  HIP_TRY(gsl::launch_graph_entries(s.gdesc, G, s.gcnt, st));
+  std::vector<int64_t> cnt((size_t)G);
+  HIP_TRY(hipMemcpyAsync(cnt.data(), s.gcnt, (size_t)G * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  // admit in order while the arena has room (compacting once if that makes room)
+  std::vector<int64_t> take;
+  int64_t need_v = 0, need_e = 0;
+  bool full = false;
+  for (int64_t g = 0; g < G; ++g) {
+    const gsl_graph &x = graphs[g];
+    const int64_t c = cnt[(size_t)g];
+    if (x.n < 0 || c < 0 || (c > 0 && !x.cols) || (x.n > 0 && (!x.offsets || !x.labels_out)) ||
+        x.n > S.cap_v || c > S.cap_e || (x.weights && !S.weighted)) {
+      status[g] = GSL_EINVAL;
+      continue;
+    }
+    if (full) {
+      status[g] = GSL_EAGAIN;
+      continue;
+    }
+    if (x.n == 0) continue;  // nothing to run: done at once, ticket -1
+    const bool slot_ok = (int64_t)S.free_slot.size() > (int64_t)take.size();
+    bool room = S.vtop + need_v + x.n <= S.cap_v && S.etop + need_e + c <= S.cap_e;
+    if (slot_ok && !room && S.live_v + need_v + x.n <= S.cap_v && S.live_e + need_e + c <= S.cap_e &&
+        (S.vtop > S.live_v || S.etop > S.live_e)) {
+      // the graphs taken so far are placed after the compaction, from vtop
+      int rc = session_compact(S);
+      if (rc) return rc;
+      room = S.vtop + need_v + x.n <= S.cap_v && S.etop + need_e + c <= S.cap_e;
+    }
+    if (!slot_ok || !room) {
+      full = true;
+      status[g] = GSL_EAGAIN;
+      continue;
+    }
+    take.push_back(g);
+    need_v += x.n;
+    need_e += c;
+  }
+  if (take.empty()) return GSL_OK;
+  // gather the admitted graphs to the top of the arena
+  const int64_t T = (int64_t)take.size();
+  std::vector<gsl_graph> d((size_t)T);
+  std::vector<int64_t> vb((size_t)T + 1, 0), eb((size_t)T + 1, 0);
+  for (int64_t i = 0; i < T; ++i) {
+    const gsl_graph &x = graphs[take[(size_t)i]];
+    d[(size_t)i] = x;
+    vb[(size_t)i + 1] = vb[(size_t)i] + x.n;
+    eb[(size_t)i + 1] = eb[(size_t)i] + cnt[(size_t)take[(size_t)i]];
+  }
+  HIP_TRY(hipMemcpyAsync(s.gdesc, d.data(), (size_t)T * sizeof(gsl_graph), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s.gvb, vb.data(), (size_t)(T + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s.geb, eb.data(), (size_t)(T + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(gsl::launch_fill_u8(reinterpret_cast<uint8_t *>(s.gflag), 0, T * (int64_t)sizeof(uint32_t), st));
+  HIP_TRY(gsl::launch_gather(s.gdesc, s.gvb, s.geb, T, need_v, need_e, S.vtop, S.etop, S.off[S.cur] + S.vtop,
+                             S.cols[S.cur] + S.etop, S.weighted ? S.w[S.cur] + S.etop : nullptr, s.gflag, st));
+  std::vector<uint32_t> bad((size_t)T, 0);
+  HIP_TRY(hipMemcpyAsync(bad.data(), s.gflag, (size_t)T * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  // slots and loop state of the admitted graphs; a graph with an entry
+  // outside [0, n) is rejected (its arena space becomes dead space)
+  std::vector<gsl::SessionRange> r;
+  std::vector<gsl::SessionRange> dead;
+  for (int64_t i = 0; i < T; ++i) {
+    const int64_t g = take[(size_t)i];
+    const int64_t n = vb[(size_t)i + 1] - vb[(size_t)i], c = eb[(size_t)i + 1] - eb[(size_t)i];
+    const gsl::SessionRange x{S.vtop + vb[(size_t)i], n, S.etop + eb[(size_t)i], c, 0, 0,
+                              gsl_convergence_limit(n, S.tol), graphs[g].labels_out, 0, 0};
+    if (bad[(size_t)i]) {
+      status[g] = GSL_EINVAL;
+      gsl::SessionRange y = x;
+      y.slot = S.cap_g;  // the dead slot
+      dead.push_back(y);
+      continue;
+    }
+    const int32_t k = S.free_slot.back();
+    S.free_slot.pop_back();
+    SessionSlot &sl = S.slot[(size_t)k];
+    sl = SessionSlot{true, S.next_ticket++, x.vb, n, x.eb, c, x.limit, graphs[g].labels_out};
+    tickets[g] = sl.ticket;
+    gsl::SessionRange y = x;
+    y.slot = k;
+    r.push_back(y);
+    S.live_v += n;
+    S.live_e += c;
+  }
+  std::vector<gsl::SessionRange> all(r);
+  all.insert(all.end(), dead.begin(), dead.end());
+  HIP_TRY(hipMemcpyAsync(S.ranges, all.data(), all.size() * sizeof(gsl::SessionRange), hipMemcpyHostToDevice, st));
+  HIP_TRY(gsl::launch_session_admit(S.ranges, (int64_t)all.size(), s.gid, S.lab[S.cur], s.act[0], s.act[1], st));
+  HIP_TRY(gsl::launch_session_slots(S.ranges, (int64_t)r.size(), S.max_iters, S.tol, s.glimit, s.giters, s.gdone,
+                                    s.gdn, st));
+  HIP_TRY(hipStreamSynchronize(st));  // the records are host temporaries
+  S.vtop += need_v;
+  S.etop += need_e;
+  S.dirty = true;
+  return GSL_OK;
+}
+
+int session_step(gsl_session &S, int32_t sweeps, int64_t capacity, int64_t *done_tickets, int32_t *done_iters,
+                 int64_t *done_count) {
+  Scratch &s = S.s;
+  const hipStream_t st = S.stream;
+  *done_count = 0;
+  int64_t live = 0;
+  for (const SessionSlot &x : S.slot) live += x.live ? 1 : 0;
+  if (live == 0) return GSL_OK;
+  const gsl::TierConfig cfg = current_tiers();
+  const HubLimits lim = current_hub_limits();
+  const int64_t N = S.vtop;
+  const int64_t *off = S.off[S.cur];
+  int rc = GSL_OK;
+  if (S.dirty) {
+    if ((rc = run_plan(s, off, N, cfg, st))) return rc;
+    S.plan = *s.ctr_host;
+    if ((rc = prepare_hubs(s, off, s.list, S.plan.tier_count[gsl::kHubTier], lim.staging_bytes, st))) return rc;
+    S.dirty = false;
+  }
+  // loop state: the sweep index keeps the parity of the active-flag arrays
+  // from step to step; the per-sweep counters restart
+  const int p = S.ctrl.it & 1;
+  gsl::SweepCtrl hc = S.ctrl;
+  hc.it = p;
+  hc.done = 0;
+  hc.max_iters = p + sweeps;
+  hc.graph_max_iters = S.max_iters;
+  hc.prune = 1;
+  hc.error = 0;
+  hc.limit = 0;
+  hc.n = S.live_v;
+  hc.graphs = (int64_t)S.cap_g + 1;
+  hc.active = 0;
+  HIP_TRY(gsl::launch_fill_u64(reinterpret_cast<uint64_t *>(s.ctr), 0, s.ctr_bytes / 8, st));
+  HIP_TRY(hipMemcpyAsync(s.ctrl, &hc, sizeof(hc), hipMemcpyHostToDevice, st));
+  gsl::SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.off = off;
+  a.cols = S.cols[S.cur];
+  a.w = S.weighted ? S.w[S.cur] : nullptr;
+  a.C = S.lab[S.cur];
+  a.Cn = s.Cn;
+  a.chg = s.chg;
+  a.act0 = s.act[0];
+  a.act1 = s.act[1];
+  a.ctrl = s.ctrl;
+  a.dn = sweep_array(s.ctr, 0, kSessionSweepCap + 2);
+  a.processed = sweep_array(s.ctr, 1, kSessionSweepCap + 2);
+  a.edges = sweep_array(s.ctr, 2, kSessionSweepCap + 2);
+  a.marked_sweeps = sweep_array(s.ctr, 3, kSessionSweepCap + 2);
+  a.overflow = reinterpret_cast<unsigned long long *>(&s.ctr->overflow);
+  a.gid = s.gid;
+  a.gdone = s.gdone;
+  a.inplace = 0;
+  a.n = N;
+  for (int k = 0; k < sweeps; ++k)
+    if ((rc = session_enqueue_sweep(S, a, cfg, lim, st))) return rc;
+  // which graphs stopped
+  std::vector<uint8_t> gdone((size_t)S.cap_g);
+  std::vector<int32_t> giters((size_t)S.cap_g);
+  HIP_TRY(hipMemcpyAsync(&hc, s.ctrl, sizeof(hc), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(gdone.data(), s.gdone, (size_t)S.cap_g, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(giters.data(), s.giters, (size_t)S.cap_g * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  S.ctrl = hc;
+  if (hc.error)
+    return fail(GSL_EOVERFLOW, "a vertex's summed row weight reaches 2^32; the session's graphs are lost");
+  std::vector<int32_t> fin;
+  for (int32_t k = 0; k < S.cap_g; ++k)
+    if (S.slot[(size_t)k].live && gdone[(size_t)k] && (int64_t)fin.size() < capacity) fin.push_back(k);
+  if (fin.empty()) return GSL_OK;
+  // the split of the finishing graphs, their labels out, their space dead
+  std::vector<uint8_t> sel((size_t)S.cap_g + 1, 0);
+  std::vector<gsl::SessionRange> r;
+  for (int32_t k : fin) {
+    sel[(size_t)k] = 1;
+    const SessionSlot &x = S.slot[(size_t)k];
+    r.push_back(gsl::SessionRange{x.vb, x.n, x.eb, x.nnz, 0, 0, x.limit, x.labels_out, k, 0});
+  }
+  HIP_TRY(hipMemcpyAsync(S.sel, sel.data(), sel.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(S.ranges, r.data(), r.size() * sizeof(gsl::SessionRange), hipMemcpyHostToDevice, st));
+  HIP_TRY(gsl::launch_session_split_labels(S.lab[S.cur], s.gid, S.sel, N, S.split_in, st));
+  HIP_TRY(gsl::launch_split(off, S.cols[S.cur], N, S.split_in, s.parent, S.split_out, s.list, S.plan.tier_count,
+                            S.plan.tier_start, nullptr, nullptr, N, s.rep, s.sigma, cfg, st));
+  HIP_TRY(gsl::launch_session_finish(S.ranges, (int64_t)r.size(), S.split_out, s.gid, S.cap_g, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (size_t i = 0; i < fin.size(); ++i) {
+    SessionSlot &x = S.slot[(size_t)fin[i]];
+    done_tickets[i] = x.ticket;
+    if (done_iters) done_iters[i] = giters[(size_t)fin[i]];
+    S.live_v -= x.n;
+    S.live_e -= x.nnz;
+    x = SessionSlot{};
+    S.free_slot.push_back(fin[i]);
+  }
+  *done_count = (int64_t)fin.size();
+  // an empty arena starts again from the bottom
+  if (S.live_v == 0 && S.live_e == 0) {
+    S.vtop = 0;
+    S.etop = 0;
+    HIP_TRY(hipMemcpyAsync(S.off[S.cur], &S.etop, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    S.dirty = true;
+  }
   return GSL_OK;
 }
 
@@ -1660,6 +2059,151 @@ void gsl_release(void) {
   if (have) (void)hipSetDevice(cur);
 }
 
-const char *gsl_version(void) { return "gsl_lpa 0.2 (gfx950)"; }
+const char *gsl_version(void) { return "gsl_lpa 0.3 (gfx950)"; }
+
+int64_t gsl_session_bytes(int64_t max_vertices, int64_t max_entries, int32_t max_graphs, int32_t weighted) {
+  if (max_vertices < 1 || max_vertices >= ((int64_t)1 << 31) - 1 || max_entries < 0 || max_graphs < 1) return -1;
+  return session_bytes(max_vertices, max_entries, max_graphs, weighted != 0);
+}
+
+int gsl_session_create(int64_t max_vertices, int64_t max_entries, int32_t max_graphs, int32_t max_iters,
+                       double tolerance, int32_t weighted, gsl_session **out) {
+  if (!out) return fail(GSL_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (max_vertices < 1 || max_vertices >= ((int64_t)1 << 31) - 1)
+    return fail(GSL_EINVAL, "max_vertices must be in [1, 2^31 - 1)");
+  if (max_entries < 0) return fail(GSL_EINVAL, "max_entries must be >= 0");
+  if (max_graphs < 1 || max_graphs > (1 << 24)) return fail(GSL_EINVAL, "max_graphs must be in [1, 2^24]");
+  if (max_iters < 0) return fail(GSL_EINVAL, "max_iters must be >= 0");
+  if (bad_tolerance(tolerance)) return fail(GSL_EINVAL, "tolerance must be in [0, 1]");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  gsl_session *S = new (std::nothrow) gsl_session();
+  if (!S) return fail(GSL_ENOMEM, "host allocation failed");
+  S->device = dev;
+  S->cap_v = max_vertices;
+  S->cap_e = max_entries;
+  S->cap_g = max_graphs;
+  S->max_iters = max_iters;
+  S->tol = tolerance;
+  S->weighted = weighted != 0;
+  S->slot.assign((size_t)max_graphs, SessionSlot{});
+  for (int32_t k = max_graphs - 1; k >= 0; --k) S->free_slot.push_back(k);
+  auto bail = [&](int code) {
+    if (S->stream) {
+      (void)hipStreamSynchronize(S->stream);
+      hipStreamDestroy(S->stream);
+    }
+    session_free(*S);
+    delete S;
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    S->stream = nullptr;
+    return bail(fail(GSL_EDEVICE, "hipStreamCreateWithFlags failed"));
+  }
+  Scratch &s = S->s;
+  int rc = GSL_OK;
+  if ((rc = ensure_pinned(s, kPinSmall)) || (rc = ensure_scratch(s, max_vertices, kSessionSweepCap + 2)) ||
+      (rc = ensure_batch(s, max_vertices, (int64_t)max_graphs + 1)))
+    return bail(rc);
+  for (int b = 0; b < 2; ++b) {
+    if (dmalloc(&S->off[b], max_vertices + 1) != hipSuccess || dmalloc(&S->cols[b], max_entries) != hipSuccess ||
+        dmalloc(&S->lab[b], max_vertices) != hipSuccess ||
+        (S->weighted && dmalloc(&S->w[b], max_entries) != hipSuccess)) {
+      (void)hipGetLastError();
+      return bail(fail(GSL_ENOMEM, "session arena allocation failed"));
+    }
+  }
+  if (dmalloc(&S->split_in, max_vertices) != hipSuccess || dmalloc(&S->split_out, max_vertices) != hipSuccess ||
+      dmalloc(&S->sel, (int64_t)max_graphs + 1) != hipSuccess || dmalloc(&S->ranges, max_graphs) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(GSL_ENOMEM, "session allocation failed"));
+  }
+  // every slot (and the dead slot, max_graphs) starts stopped; the arena
+  // starts empty.  The change flags start clear and stay clear between
+  // sweeps (the apply kernel clears what a sweep sets): a stale flag would
+  // copy an unwritten Cn entry into the labels and count a change for the
+  // graph id of a vertex that may lie past the arena's top.
+  const int64_t zero = 0;
+  const int64_t flag_bytes = (s.n_cap + 3) / 4 * 4 + 16;
+  if (gsl::launch_fill_u8(s.chg, 0, flag_bytes, S->stream) != hipSuccess ||
+      gsl::launch_fill_u8(s.act[0], 0, flag_bytes, S->stream) != hipSuccess ||
+      gsl::launch_fill_u8(s.act[1], 0, flag_bytes, S->stream) != hipSuccess ||
+      gsl::launch_fill_u8(s.gdone, 1, (int64_t)max_graphs + 1, S->stream) != hipSuccess ||
+      hipMemcpyAsync(S->off[0], &zero, sizeof(int64_t), hipMemcpyHostToDevice, S->stream) != hipSuccess ||
+      hipStreamSynchronize(S->stream) != hipSuccess)
+    return bail(fail(GSL_EDEVICE, "session initialisation failed"));
+  memset(&S->ctrl, 0, sizeof(S->ctrl));
+  S->ctrl.dense = 1;
+  S->bytes = session_bytes(max_vertices, max_entries, max_graphs, S->weighted);
+  *out = S;
+  return GSL_OK;
+}
+
+void gsl_session_destroy(gsl_session *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (hipSetDevice(S->device) == hipSuccess) {
+      if (S->stream) (void)hipStreamSynchronize(S->stream);
+      session_free(*S);
+      if (S->stream) hipStreamDestroy(S->stream);
+    }
+    if (have) (void)hipSetDevice(cur);
+  }
+  delete S;
+}
+
+void *gsl_session_stream(gsl_session *S) { return S ? reinterpret_cast<void *>(S->stream) : nullptr; }
+
+int gsl_session_add(gsl_session *S, int64_t num_graphs, const gsl_graph *graphs, int64_t *tickets_out,
+                    int32_t *status_out) {
+  if (!S) return fail(GSL_EINVAL, "session must not be NULL");
+  if (num_graphs < 0) return fail(GSL_EINVAL, "num_graphs must be >= 0");
+  if (num_graphs == 0) return GSL_OK;
+  if (!graphs || !tickets_out || !status_out) return fail(GSL_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != S->device) return fail(GSL_EINVAL, "the session belongs to device %d, current is %d", S->device, cur);
+  const int64_t G = std::min<int64_t>(num_graphs, S->cap_g);
+  const int rc = session_add(*S, G, graphs, tickets_out, status_out);
+  for (int64_t g = G; g < num_graphs; ++g) {
+    tickets_out[g] = -1;
+    status_out[g] = GSL_EAGAIN;
+  }
+  return rc;
+}
+
+int gsl_session_step(gsl_session *S, int32_t sweeps, int64_t capacity, int64_t *done_tickets,
+                     int32_t *done_iterations, int64_t *done_count) {
+  if (!S || !done_count) return fail(GSL_EINVAL, "NULL argument");
+  *done_count = 0;
+  if (sweeps < 1 || sweeps > kSessionSweepCap) return fail(GSL_EINVAL, "sweeps must be in [1, %d]", kSessionSweepCap);
+  if (capacity < 0 || (capacity > 0 && !done_tickets)) return fail(GSL_EINVAL, "bad done_tickets / capacity");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != S->device) return fail(GSL_EINVAL, "the session belongs to device %d, current is %d", S->device, cur);
+  return session_step(*S, sweeps, capacity, done_tickets, done_iterations, done_count);
+}
+
+int gsl_session_info(gsl_session *S, int64_t *live_graphs, int64_t *live_vertices, int64_t *live_entries,
+                     int64_t *free_vertices, int64_t *free_entries, int64_t *device_bytes) {
+  if (!S) return fail(GSL_EINVAL, "session must not be NULL");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int64_t g = 0;
+  for (const SessionSlot &x : S->slot) g += x.live ? 1 : 0;
+  if (live_graphs) *live_graphs = g;
+  if (live_vertices) *live_vertices = S->live_v;
+  if (live_entries) *live_entries = S->live_e;
+  if (free_vertices) *free_vertices = S->cap_v - S->live_v;
+  if (free_entries) *free_entries = S->cap_e - S->live_e;
+  if (device_bytes) *device_bytes = S->bytes;
+  return GSL_OK;
+}
 
 }  // extern "C"

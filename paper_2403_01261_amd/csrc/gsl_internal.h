@@ -104,7 +104,7 @@ struct SweepCtrl {
   int32_t max_iters;
   int32_t prune;
   int32_t error;       // 1: a row's weight sum reached 2^32
-  int32_t pad;
+  int32_t graph_max_iters;  // batches: each graph's own sweep cap (a session's sweeps outrun any graph's)
   int64_t limit;       // largest dN that counts as converged (one graph)
   int64_t n;           // vertices, for the marking heuristic
   int64_t graphs;      // 0: one graph; else graphs of a batch
@@ -196,9 +196,16 @@ struct HubLayout {
   int64_t *chunk_start;
   int64_t *part_start;
   int64_t *hist_start;
+  int32_t *chunk_owner;          // [total chunks] hub of each chunk
+  int32_t *part_owner;           // [total partitions] hub of each partition
+  unsigned long long *records;   // [H] (label, sum) records staged in the current sweep
 };
+// Chunk and partition prefix sums of the hubs (owners and records are filled
+// by launch_hub_owners once the host has sized them).
 hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, HubLayout L,
                              hipStream_t s);
+// chunk_owner / part_owner from the prefix sums; records cleared.
+hipError_t launch_hub_owners(HubLayout L, int64_t H, hipStream_t s);
 hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L,
                             const int64_t *chunk_start_h, const int64_t *part_start_h,
                             unsigned long long *staging, int32_t *hist, unsigned long long *best,
@@ -253,11 +260,35 @@ hipError_t launch_globalize_cols(const int32_t *cols, const int64_t *edge_base, 
                                  int64_t G, int64_t nnz, int32_t *out, hipStream_t s);
 // cnt[g] = offsets[n] - offsets[0] of graph g, -1 if its offsets decrease.
 hipError_t launch_graph_entries(const GraphDesc *d, int64_t G, int64_t *cnt, hipStream_t s);
-// Separate graphs -> one global CSR (off [N + 1], cols [nnz], w [nnz] or NULL).
-// An entry outside [0, n_g) sets bad[g] and is replaced by local vertex 0.
+// Separate graphs -> one global CSR (off [N + 1], cols [nnz], w [nnz] or NULL),
+// vertex ids shifted by vshift and entry positions by eshift (the position
+// of the gathered block in a larger array; 0 for a batch of its own).  An
+// entry outside [0, n_g) sets bad[g] and is replaced by local vertex 0.
 hipError_t launch_gather(const GraphDesc *d, const int64_t *vtx_base, const int64_t *edge_base, int64_t G,
-                         int64_t N, int64_t nnz, int64_t *off, int32_t *cols, uint32_t *w, uint32_t *bad,
-                         hipStream_t s);
+                         int64_t N, int64_t nnz, int64_t vshift, int64_t eshift, int64_t *off, int32_t *cols,
+                         uint32_t *w, uint32_t *bad, hipStream_t s);
+// ---- sessions: graphs joining and leaving a resident batch between sweeps ----
+// One graph of a session: vertices [vb, vb + n) and entries [eb, eb + nnz) of
+// the arena, its slot, its convergence limit, its output, and (compaction)
+// its new position.
+struct SessionRange {
+  int64_t vb, n, eb, nnz;
+  int64_t new_vb, new_eb;
+  int64_t limit;
+  int32_t *labels_out;
+  int32_t slot, pad;
+};
+hipError_t launch_session_admit(const SessionRange *r, int64_t count, int32_t *gid, int32_t *lab, uint8_t *act0,
+                                uint8_t *act1, hipStream_t s);
+hipError_t launch_session_slots(const SessionRange *r, int64_t count, int32_t max_iters, double tol, int64_t *glimit,
+                                int32_t *giters, uint8_t *gdone, int64_t *gdn, hipStream_t s);
+hipError_t launch_session_split_labels(const int32_t *lab, const int32_t *gid, const uint8_t *sel, int64_t n,
+                                       int32_t *out, hipStream_t s);
+hipError_t launch_session_finish(const SessionRange *r, int64_t count, const int32_t *split, int32_t *gid,
+                                 int32_t dead, hipStream_t s);
+hipError_t launch_session_move(const SessionRange *r, int64_t count, const int64_t *off, const int32_t *cols,
+                               const uint32_t *w, const int32_t *lab, int64_t *off2, int32_t *cols2, uint32_t *w2,
+                               int32_t *lab2, int32_t *gid, uint8_t *act0, uint8_t *act1, hipStream_t s);
 // One graph: *bad |= 1 if offsets[0] != 0 or offsets decrease, |= 2 if a
 // column is outside [0, n).
 hipError_t launch_check_graph(const int64_t *off, const int32_t *cols, int64_t n, int64_t nnz,
@@ -292,7 +323,8 @@ hipError_t launch_disconnected(const int32_t *labels, const int32_t *comp, int64
                                uint8_t *D, unsigned long long *count, hipStream_t s);
 hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_t *w, int64_t n,
                           const int32_t *list, const int64_t *tier_count_h, const int64_t *tier_start_h,
-                          const int64_t *hub_chunk_start, int64_t hub_chunks, int32_t *old2new,
+                          const int64_t *hub_chunk_start, const int32_t *hub_chunk_owner, int64_t hub_chunks,
+                          int32_t *old2new,
                           int64_t *off2, int32_t *cols2, uint32_t *w2, int32_t *lab,
                           int64_t *scan_tmp, unsigned long long *first_key,
                           unsigned long long *hub_rowsum, unsigned long long *flags,

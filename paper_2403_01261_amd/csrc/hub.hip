@@ -44,18 +44,6 @@ constexpr int kChunkGroup = 1024;                       // chunks whose slices o
 static_assert(kHubChunk % kHubBlock == 0, "chunk must split evenly over the block");
 static_assert(2 * kHubChunk <= kTabSlots, "insert table must hold every chunk entry");
 
-// Largest k with start[k] <= x, for k in [lo, hi).
-__device__ __forceinline__ int64_t owner(const int64_t *start, int64_t lo, int64_t hi, int64_t x) {
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) / 2;
-    if (start[mid] <= x)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ int hub_parts(int64_t d) {
   int64_t p = (d + kPartSize - 1) / kPartSize;
   return (int)(p < 1 ? 1 : (p > kMaxParts ? kMaxParts : p));
@@ -167,7 +155,7 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
   SweepView sv;
   if (!sweep_view(a, sv)) return;
   const int64_t c = h.L.chunk_start[h.k0] + blockIdx.x;
-  const int64_t k = owner(h.L.chunk_start, h.k0, h.k1, c);
+  const int64_t k = h.L.chunk_owner[c];
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!sweep_takes(a, sv, v)) return;  // uniform over the block
   const int64_t rb = a.off[v], re = a.off[v + 1];
@@ -218,40 +206,40 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
     if (slot[q] >= 0) stage[hist[pp[q]] + rank[q]] = x[q];
   int32_t *gh = h.hist + (h.L.hist_start[k] - h.L.hist_start[h.k0]) + cl * (P + 1);
   for (int i = threadIdx.x; i <= P; i += kHubBlock) gh[i] = hist[i];
+  const int chunk_records = hist[P];  // written by the scan, read before block_sum's barriers
   rs = block_sum(rs, red);
-  if (threadIdx.x == 0 && rs)
-    __hip_atomic_fetch_add(&h.rowsum[k], rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    if (rs) __hip_atomic_fetch_add(&h.rowsum[k], rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (chunk_records)
+      __hip_atomic_fetch_add(&h.L.records[k], (unsigned long long)chunk_records, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h) {
   __shared__ unsigned long long tab[kTabSlots];
   __shared__ int pre[kChunkGroup + 1];
   __shared__ int scan_part[kMergeBlock];
-  __shared__ int claimed, overflow, records;
+  __shared__ int claimed, overflow;
   __shared__ unsigned long long red[kMergeBlock / kWave];
   SweepView sv;
   if (!sweep_view(a, sv)) return;
   const int64_t gp = h.L.part_start[h.k0] + blockIdx.x;
-  const int64_t k = owner(h.L.part_start, h.k0, h.k1, gp);
+  const int64_t k = h.L.part_owner[gp];
+  // The partition count is sized for rows whose labels are all distinct.
+  // When the hub's (label, sum) records of all partitions fit one table --
+  // usual once the labels have merged -- workgroup 0 merges them all and the
+  // others return.  hub_insert counted the records of every chunk.
+  const unsigned long long records = h.L.records[k];
+  const int p = (int)(gp - h.L.part_start[k]);
+  const bool whole = records <= (unsigned long long)h.merge_cap;  // uniform
+  if (whole && p > 0) return;
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!sweep_takes(a, sv, v)) return;
-  const int p = (int)(gp - h.L.part_start[k]);
   const int P = hub_parts(a.off[v + 1] - a.off[v]);
   const int64_t c0 = h.L.chunk_start[k], nc = h.L.chunk_start[k + 1] - c0;
   const int32_t *gh = h.hist + (h.L.hist_start[k] - h.L.hist_start[h.k0]);
   const unsigned long long *stage = h.staging + (c0 - h.L.chunk_start[h.k0]) * kHubChunk;
-  // The partition count is sized for rows whose labels are all distinct.
-  // When the hub's (label, sum) records of all partitions fit one table --
-  // usual once the labels have merged -- workgroup 0 merges them all and the
-  // others return.
-  if (threadIdx.x == 0) records = 0;
-  __syncthreads();
-  int mine = 0;
-  for (int64_t i = threadIdx.x; i < nc; i += kMergeBlock) mine += gh[i * (P + 1) + P];
-  if (mine) atomicAdd(&records, mine);
-  __syncthreads();
-  const bool whole = records <= h.merge_cap;  // uniform
-  if (whole && p > 0) return;
   const int p_lo = whole ? 0 : p, p_hi = whole ? P : p + 1;  // partitions merged here
   unsigned long long best = 0;
   for (uint32_t R = 1;; R <<= 1) {
@@ -336,6 +324,7 @@ __global__ __launch_bounds__(256) void hub_decide(SweepArgs a, HubArgs h) {
       const unsigned long long rs = h.rowsum[k];
       h.best[k] = 0;
       h.rowsum[k] = 0;
+      h.L.records[k] = 0;
       lc.processed = 1;
       lc.edges = (unsigned long long)(a.off[v + 1] - a.off[v]);
       lc.overflow = rs >> 32 ? 1 : 0;
@@ -384,7 +373,7 @@ __global__ __launch_bounds__(kHubBlock) void hub_mark(SweepArgs a, HubArgs h) {
   SweepView sv;
   if (!sweep_view(a, sv) || !sv.mark) return;
   const int64_t c = h.L.chunk_start[h.k0] + blockIdx.x;
-  const int64_t k = owner(h.L.chunk_start, h.k0, h.k1, c);
+  const int64_t k = h.L.chunk_owner[c];
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
   if (!a.chg[v]) return;  // uniform: only hubs changed in this sweep
   const int64_t rb = a.off[v], re = a.off[v + 1];
@@ -396,7 +385,25 @@ __global__ __launch_bounds__(kHubBlock) void hub_mark(SweepArgs a, HubArgs h) {
   }
 }
 
+// Block per hub (grid-stride): the hub's chunks and partitions name it as
+// their owner, and its record count starts at zero.
+__global__ __launch_bounds__(256) void hub_owners(HubLayout L, int64_t H) {
+  for (int64_t k = blockIdx.x; k < H; k += gridDim.x) {
+    const int64_t c0 = L.chunk_start[k], c1 = L.chunk_start[k + 1];
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) L.chunk_owner[c] = (int32_t)k;
+    const int64_t p0 = L.part_start[k], p1 = L.part_start[k + 1];
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) L.part_owner[p] = (int32_t)k;
+    if (threadIdx.x == 0) L.records[k] = 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_hub_owners(HubLayout L, int64_t H, hipStream_t s) {
+  if (H <= 0) return hipSuccess;
+  hub_owners<<<(unsigned)(H < 65536 ? H : 65536), 256, 0, s>>>(L, H);
+  return hipGetLastError();
+}
 
 hipError_t launch_hub_layout(const int64_t *off, const int32_t *hubs, int64_t H, HubLayout L,
                              hipStream_t s) {

@@ -96,20 +96,6 @@ struct CopyArgs {
                                    // bit 1: a row's weight sum reaches 2^32
 };
 
-// One row entry's share of the first-sweep work.
-__device__ __forceinline__ void first_entry(const CopyArgs &c, int32_t v, int64_t q, int64_t re,
-                                            unsigned long long &best, unsigned long long &rowsum,
-                                            int &unsorted) {
-  const int32_t j = c.cols[q];
-  const uint32_t w = c.w ? c.w[q] : 1u;
-  if (q + 1 < re && c.cols[q + 1] <= j) unsorted = 1;
-  rowsum += w;
-  if (j != v) {
-    const unsigned long long key = argmax_key((uint32_t)j, w);
-    best = key > best ? key : best;
-  }
-}
-
 // Rows [first, first + count) of the new numbering, G lanes per row (G <= 64
 // or the whole block), each lane owning at most K entries of the row (the
 // tier bound is G * K) with all its loads issued before any use.
@@ -141,11 +127,17 @@ __global__ __launch_bounds__(BLOCK) void reorder_rows(CopyArgs c, int64_t first,
       jn[k] = in && q + 1 < e ? c.cols[q + 1] : 0x7fffffff;
       w[k] = in ? (c.w ? c.w[q] : 1u) : 0u;
     }
+    // every old->new lookup is issued before the first store (a store could
+    // alias a later lookup's address as far as the compiler knows, which
+    // would keep one random gather in flight per lane)
+    int32_t nj[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) nj[k] = j[k] >= 0 ? c.old2new[j[k]] : 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (j[k] < 0) continue;
       const int64_t q = b + lane + (int64_t)k * G;
-      c.cols2[b2 + (q - b)] = c.old2new[j[k]];
+      c.cols2[b2 + (q - b)] = nj[k];
       if (c.w) c.w2[b2 + (q - b)] = w[k];
       unsorted |= jn[k] <= j[k];
       rowsum += w[k];
@@ -185,31 +177,47 @@ __global__ __launch_bounds__(BLOCK) void reorder_rows(CopyArgs c, int64_t first,
 }
 
 // Hub rows in chunks of kHubChunk entries, one block per chunk; chunk_start
-// is the hub layout (prefix of chunks per hub, hubs = new ids 0..H-1).  The
-// first-sweep key and weight sum of a hub are combined across its chunks.
+// and chunk_owner are the hub layout (hubs = new ids 0..H-1).  Each lane
+// loads its kChunk / 256 entries, then issues all their old->new lookups,
+// then stores.  The first-sweep key and weight sum of a hub are combined
+// across its chunks.
 constexpr int kChunk = kHubChunk;
-__global__ __launch_bounds__(256) void reorder_hub_rows(CopyArgs c, const int64_t *chunk_start, int64_t H) {
+constexpr int kChunkPerLane = kChunk / 256;
+__global__ __launch_bounds__(256) void reorder_hub_rows(CopyArgs c, const int64_t *chunk_start,
+                                                        const int32_t *chunk_owner) {
   __shared__ unsigned long long red[256 / kWave], red2[256 / kWave];
   const int64_t ch = blockIdx.x;
-  int64_t lo = 0, hi = H;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) / 2;
-    if (chunk_start[mid] <= ch)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const int64_t p = lo;
+  const int64_t p = chunk_owner[ch];
   const int32_t v = c.list[p];
   const int64_t rb = c.off[v], re = c.off[v + 1], b2 = c.off2[p];
   const int64_t b = rb + (ch - chunk_start[p]) * kChunk;
   const int64_t e = b + kChunk < re ? b + kChunk : re;
   unsigned long long best = 0, rowsum = 0;
   int unsorted = 0;
-  for (int64_t q = b + threadIdx.x; q < e; q += 256) {
-    c.cols2[b2 + (q - rb)] = c.old2new[c.cols[q]];
-    if (c.w) c.w2[b2 + (q - rb)] = c.w[q];
-    first_entry(c, v, q, re, best, rowsum, unsorted);
+  int32_t j[kChunkPerLane], jn[kChunkPerLane], nj[kChunkPerLane];
+  uint32_t w[kChunkPerLane];
+#pragma unroll
+  for (int k = 0; k < kChunkPerLane; ++k) {
+    const int64_t q = b + threadIdx.x + (int64_t)k * 256;
+    const bool in = q < e;
+    j[k] = in ? c.cols[q] : -1;
+    jn[k] = in && q + 1 < re ? c.cols[q + 1] : 0x7fffffff;
+    w[k] = in ? (c.w ? c.w[q] : 1u) : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < kChunkPerLane; ++k) nj[k] = j[k] >= 0 ? c.old2new[j[k]] : 0;
+#pragma unroll
+  for (int k = 0; k < kChunkPerLane; ++k) {
+    if (j[k] < 0) continue;
+    const int64_t q = b + threadIdx.x + (int64_t)k * 256;
+    c.cols2[b2 + (q - rb)] = nj[k];
+    if (c.w) c.w2[b2 + (q - rb)] = w[k];
+    unsorted |= jn[k] <= j[k];
+    rowsum += w[k];
+    if (j[k] != v) {
+      const unsigned long long key = argmax_key((uint32_t)j[k], w[k]);
+      best = key > best ? key : best;
+    }
   }
   best = group_max<kWave>(best);
   rowsum = wave_sum(rowsum);
@@ -288,8 +296,8 @@ int grid_of(int64_t items, int per_block, int cap) {
 // initial labels lab[p] = list[p].  scan_tmp needs plan_blocks(np) + 1 entries.
 hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_t *w, int64_t n,
                           const int32_t *list, const int64_t *tier_count_h, const int64_t *tier_start_h,
-                          const int64_t *hub_chunk_start, int64_t hub_chunks, int32_t *old2new,
-                          int64_t *off2, int32_t *cols2, uint32_t *w2, int32_t *lab,
+                          const int64_t *hub_chunk_start, const int32_t *hub_chunk_owner, int64_t hub_chunks,
+                          int32_t *old2new, int64_t *off2, int32_t *cols2, uint32_t *w2, int32_t *lab,
                           int64_t *scan_tmp, unsigned long long *first_key,
                           unsigned long long *hub_rowsum, unsigned long long *flags,
                           unsigned long long *dn0, int apply_first, const TierConfig &cfg, hipStream_t s) {
@@ -305,7 +313,7 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
   }
   CopyArgs c{off, cols, w, list, old2new, off2, cols2, w2, first_key, hub_rowsum, flags};
   const int64_t H = tier_count_h[kNumTiers - 1];
-  if (H > 0) hipMemsetAsync(first_key, 0, (size_t)H * sizeof(unsigned long long), s);
+  if (H > 0) launch_fill_u64(reinterpret_cast<uint64_t *>(first_key), 0, H, s);
   for (int t = 1; t < kNumTiers; ++t) {
     const int64_t cnt = tier_count_h[t], first = tier_start_h[t];
     if (cnt <= 0) continue;
@@ -313,7 +321,8 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
     // covers the tier's degree bound
     const int64_t d = cfg.bound[t];
     if (t == kNumTiers - 1) {
-      if (hub_chunks > 0) reorder_hub_rows<<<(unsigned)hub_chunks, 256, 0, s>>>(c, hub_chunk_start, cnt);
+      if (hub_chunks > 0)
+        reorder_hub_rows<<<(unsigned)hub_chunks, 256, 0, s>>>(c, hub_chunk_start, hub_chunk_owner);
     } else if (d <= 8) {
       reorder_rows<1, 256, 8><<<grid_of(cnt, 256, kCap), 256, 0, s>>>(c, first, cnt);
     } else if (d <= 16) {

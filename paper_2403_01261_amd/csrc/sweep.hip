@@ -624,7 +624,7 @@ __global__ __launch_bounds__(256) void graph_end(SweepCtrl *c, int64_t *__restri
   if (g < graphs && !gdone[g]) {
     const int32_t it = giters[g] + 1;
     giters[g] = it;
-    if (gdn[g] <= glimit[g] || it >= c->max_iters)
+    if (gdn[g] <= glimit[g] || it >= c->graph_max_iters)
       gdone[g] = 1;
     else
       running = 1;

@@ -239,6 +239,128 @@ class Server:
         return reqs
 
 
+class ContinuousServer:
+    """Continuous batching at sweep granularity over one resident batch (a
+    gsl_session).  The loop alternates two things: admit queued requests, in
+    arrival order, as far as the session's free vertices, entries and graph
+    slots allow; run a step of a few sweeps of every admitted graph, after
+    which the graphs that stopped leave with their labels.  A request that
+    arrives while others run joins them at the next step instead of waiting
+    for a batch to drain, and its result is what it would get alone (each
+    graph keeps its own sweeps and convergence test in the session).
+
+    backend.add(requests) returns one (ticket, status) per request (status 0:
+    admitted, ticket -1 when nothing has to run; EAGAIN: no room now, and the
+    later requests of the call were not tried; anything else: rejected),
+    backend.step(sweeps) returns [(ticket, sweeps_run)] of finished graphs,
+    backend.live() the graphs still running.  Plain Python, tested on the CPU
+    with a fake backend; SessionBackend is the GPU one."""
+
+    EAGAIN = -5
+
+    def __init__(self, backend, sweeps_per_step: int = 2, max_admit: int = 256,
+                 clock: Callable[[], float] = time.perf_counter):
+        if sweeps_per_step < 1 or max_admit < 1:
+            raise ValueError("sweeps_per_step and max_admit must be positive")
+        self.backend = backend
+        self.sweeps = int(sweeps_per_step)
+        self.max_admit = int(max_admit)
+        self.clock = clock
+        self.steps = 0
+        self.admissions: List[int] = []   # requests admitted before each step
+
+    def serve(self, requests: List[Request], cancel: Optional[dict] = None) -> List[Request]:
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        pending = collections.deque(reqs)
+        queue: collections.deque = collections.deque()
+        cancels = sorted((cancel or {}).items())
+        by_ticket = {}
+        t0 = self.clock()
+        while pending or queue or by_ticket:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                r.state = "queued"
+                queue.append(r)
+            while cancels and cancels[0][0] <= now:
+                for rid in cancels.pop(0)[1]:
+                    for r in list(queue):
+                        if r.rid == rid:
+                            queue.remove(r)
+                            r.state = "cancelled"
+            admitted = 0
+            while queue:
+                head = [queue[k] for k in range(min(len(queue), self.max_admit))]
+                res = self.backend.add(head)
+                stop = False
+                t = self.clock() - t0
+                for r, (ticket, status) in zip(head, res):
+                    if status == self.EAGAIN:
+                        stop = True
+                        break
+                    queue.popleft()
+                    r.t_admit = t
+                    if status != 0:
+                        r.state, r.code, r.error, r.t_done = "failed", status, "graph rejected by the library", t
+                    elif ticket < 0:
+                        r.state, r.iterations, r.t_done = "done", 0, t
+                    else:
+                        r.state = "running"
+                        by_ticket[ticket] = r
+                        admitted += 1
+                if stop or len(res) < len(head):
+                    break
+            if by_ticket:
+                self.admissions.append(admitted)
+                finished = self.backend.step(self.sweeps)
+                self.steps += 1
+                t = self.clock() - t0
+                for ticket, iters in finished:
+                    r = by_ticket.pop(ticket)
+                    r.state, r.iterations, r.t_done = "done", iters, t
+                    self.backend.collect(r)
+            elif pending:
+                wait = pending[0].arrival - (self.clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.05))
+            elif queue:
+                raise RuntimeError("queued requests can never be admitted")
+        return reqs
+
+
+class SessionBackend:
+    """ContinuousServer backend on one gsl_session.  A request's payload is
+    (offsets, cols, weights or None) device tensors with local ids; its labels
+    land in a tensor of its own (request.labels)."""
+
+    def __init__(self, max_vertices: int, max_entries: int, max_graphs: int = 4096, max_iters: int = 20,
+                 tolerance: float = 0.05, weighted: bool = False):
+        from . import Session
+        self.session = Session(max_vertices, max_entries, max_graphs, max_iters, tolerance, weighted)
+        self._out = {}
+
+    def add(self, reqs):
+        res = self.session.add([tuple(r.payload[:3]) for r in reqs])
+        out = []
+        for r, (ticket, status, lab) in zip(reqs, res):
+            if status == 0:
+                r.labels = lab
+            out.append((ticket, status))
+        return out
+
+    def step(self, sweeps: int):
+        return self.session.step(sweeps)
+
+    def collect(self, r):
+        pass
+
+    def live(self) -> int:
+        return self.session.info()["live_graphs"]
+
+    def close(self):
+        self.session.close()
+
+
 def summarize(reqs: List[Request], batches: Optional[List[List[Request]]] = None) -> dict:
     """Latency percentiles (ms), throughput (graphs/s from the first arrival
     to the last completion) and outcome counts."""

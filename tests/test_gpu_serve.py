@@ -68,3 +68,47 @@ def test_served_results_equal_alone_and_oracle(gsl):
         np.testing.assert_array_equal(lab, alone.cpu().numpy())
         assert st["iterations"] == r.iterations
     assert s["done"] == len(graphs) - 2
+
+
+def test_continuous_server_requests_join_running_graphs(gsl):
+    """Sweep-level continuous batching (ContinuousServer over a gsl_session):
+    requests arriving while others run join them at the next step; every
+    result equals gsl_lpa alone and the oracle, and a malformed graph fails
+    alone."""
+    from paper_2403_01261_amd.serve import ContinuousServer, Request, SessionBackend, poisson_arrivals, summarize
+    b = workloads.make(5, small=True)
+    graphs = [b.subgraph(k) for k in range(b.num_graphs)]
+    graphs.insert(5, graphgen.from_entries(4, [], []))
+    graphs.insert(9, graphgen.from_undirected(6, [(0, 1), (1, 2)]))
+    times = poisson_arrivals(len(graphs), 2000.0, 11)
+    reqs = []
+    for k, (g, t) in enumerate(zip(graphs, times)):
+        off, cols, w = to_device(g)
+        if k == 9:
+            cols = cols.clone()
+            cols[0] = 17  # outside [0, 6)
+        reqs.append(Request(rid=k, arrival=float(t), n=g.n, nnz=g.nnz, payload=(off, cols, w)))
+    torch.cuda.synchronize()
+    backend = SessionBackend(max_vertices=150_000, max_entries=3_000_000, max_graphs=32)
+    srv = ContinuousServer(backend, sweeps_per_step=1)
+    try:
+        srv.serve(reqs)
+    finally:
+        backend.close()
+    s = summarize(reqs)
+    say("continuous:", s, "steps", srv.steps)
+    assert reqs[9].state == "failed" and reqs[9].code == gsl.GSL_EINVAL
+    # some request was admitted while earlier ones were still running
+    running_at_admit = [sum(1 for q in reqs if q.t_admit < r.t_admit < q.t_done) for r in reqs if r.state == "done"]
+    assert max(running_at_admit) > 0
+    for k, (g, r) in enumerate(zip(graphs, reqs)):
+        if k == 9:
+            continue
+        assert r.state == "done", (k, r.state, r.error)
+        exp = oracle.lpa(g)
+        lab = r.labels.cpu().numpy()
+        np.testing.assert_array_equal(lab, exp.labels, err_msg="request %d" % k)
+        assert r.iterations == exp.iterations
+        off, cols, w = r.payload
+        alone, st = gsl.gsl_lpa_ex(off, cols, w)
+        np.testing.assert_array_equal(lab, alone.cpu().numpy())

@@ -15,7 +15,8 @@ import pytest
 
 import graphgen
 import oracle
-from paper_2403_01261_amd.serve import Request, Scheduler, Server, footprint, poisson_arrivals, summarize
+from paper_2403_01261_amd.serve import (ContinuousServer, Request, Scheduler, Server, footprint, poisson_arrivals,
+                                        summarize)
 
 
 class FakeExecutor:
@@ -158,8 +159,10 @@ def test_requests_admitted_while_others_run():
     # slot 0 is busy with the first batch when request 1 arrives: it must start
     # on slot 1 before the first batch ends (continuous batching, not a queue)
     reqs = make_requests(2, rate=1.0)
-    reqs[0].arrival, reqs[1].arrival = 0.0, 0.01
-    ex = FakeExecutor(0.1)
+    # arrivals 0.1 s apart: the server's first look at the queue may come late
+    # on a loaded machine, and both requests must not be there yet
+    reqs[0].arrival, reqs[1].arrival = 0.0, 0.1
+    ex = FakeExecutor(1.0)
     srv = Server(ex, slots=2, budget_bytes=1 << 30)
     srv.serve(reqs)
     assert reqs[0].slot != reqs[1].slot
@@ -172,3 +175,96 @@ def test_poisson_arrivals():
     assert abs(np.diff(t).mean() - 0.0005) < 0.00002
     with pytest.raises(ValueError):
         Scheduler(0)
+
+
+class FakeSession:
+    """A session on the CPU: graphs take vertex / entry / slot capacity while
+    they run, every step advances each running graph by `sweeps` sweeps, and
+    a graph leaves with the oracle's labels once it has run the oracle's
+    number of sweeps.  Records what was resident at every step."""
+
+    def __init__(self, cap_v, cap_e, cap_g, seconds_per_step=0.002):
+        self.cap_v, self.cap_e, self.cap_g = cap_v, cap_e, cap_g
+        self.dt = seconds_per_step
+        self.live = {}          # ticket -> [request, sweeps done, sweeps needed, labels]
+        self.next = 0
+        self.steps = []         # sets of resident request ids, per step
+
+    def _used(self):
+        return (sum(r.n for r, *_ in self.live.values()), sum(r.nnz for r, *_ in self.live.values()))
+
+    def add(self, reqs):
+        out = []
+        for r in reqs:
+            if r.n > self.cap_v or r.nnz > self.cap_e:
+                out.append((-1, -1))
+                continue
+            v, e = self._used()
+            if len(self.live) >= self.cap_g or v + r.n > self.cap_v or e + r.nnz > self.cap_e:
+                out.append((-1, ContinuousServer.EAGAIN))
+                break
+            if r.n == 0:
+                out.append((-1, 0))
+                continue
+            res = oracle.lpa(r.payload)
+            self.live[self.next] = [r, 0, res.iterations, res.labels]
+            out.append((self.next, 0))
+            self.next += 1
+        return out
+
+    def step(self, sweeps):
+        time.sleep(self.dt)
+        self.steps.append({x[0].rid for x in self.live.values()})
+        done = []
+        for t, x in list(self.live.items()):
+            x[1] = min(x[1] + sweeps, x[2])
+            if x[1] >= x[2]:
+                x[0].labels = x[3]
+                done.append((t, x[2]))
+                del self.live[t]
+        return done
+
+    def collect(self, r):
+        pass
+
+    def live_count(self):
+        return len(self.live)
+
+
+def test_continuous_server_admits_between_sweeps_and_matches_oracle():
+    reqs = make_requests(50, rate=3000.0)
+    fs = FakeSession(cap_v=2000, cap_e=40_000, cap_g=8)
+    srv = ContinuousServer(fs, sweeps_per_step=1)
+    srv.serve(reqs)
+    assert all(r.state == "done" for r in reqs)
+    check_against_oracle(reqs)
+    # requests joined batches that were already running (continuous batching)
+    joined = any(len(a - b) > 0 and len(a & b) > 0 for b, a in zip(fs.steps, fs.steps[1:]))
+    assert joined
+    assert max(len(s) for s in fs.steps) <= 8
+    assert summarize(reqs)["done"] == 50
+
+
+def test_continuous_server_capacity_retry_and_rejection():
+    reqs = make_requests(30, rate=1e6, sizes=(300, 400))   # all at once, more than fits
+    huge = Request(rid=999, arrival=0.0, n=10 ** 6, nnz=10, payload=None)
+    fs = FakeSession(cap_v=1000, cap_e=10 ** 6, cap_g=64)
+    srv = ContinuousServer(fs, sweeps_per_step=2)
+    srv.serve(reqs + [huge])
+    assert huge.state == "failed"
+    assert all(r.state == "done" for r in reqs)
+    check_against_oracle(reqs)
+    # never more resident vertices than the capacity
+    by_rid = {r.rid: r for r in reqs}
+    assert all(sum(by_rid[i].n for i in s) <= 1000 for s in fs.steps)
+    # later requests waited for earlier ones to leave
+    assert min(r.t_admit for r in reqs[-5:]) > 0
+
+
+def test_continuous_server_cancel():
+    reqs = make_requests(20, rate=1e6)
+    fs = FakeSession(cap_v=500, cap_e=10 ** 6, cap_g=2, seconds_per_step=0.005)
+    srv = ContinuousServer(fs, sweeps_per_step=1)
+    srv.serve(reqs, cancel={0.002: [19]})
+    assert reqs[19].state == "cancelled"
+    assert sum(r.state == "done" for r in reqs) == 19
