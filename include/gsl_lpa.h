@@ -403,6 +403,14 @@ int gsl_session_info(gsl_session *s, int64_t *live_graphs, int64_t *live_vertice
                      int64_t *free_vertices, int64_t *free_entries, int64_t *device_bytes);
 
 /*
+ * gsl_graphs_bytes -- host-only: an upper bound of the device scratch that a
+ * gsl_lpa_graphs call on `graphs` graphs with n vertices and nnz entries in
+ * all (weighted or not, max_iters sweeps) adds to its context's cache (for a
+ * server's memory budget); -1 for bad arguments.
+ */
+int64_t gsl_graphs_bytes(int64_t n, int64_t nnz, int64_t graphs, int32_t weighted, int32_t max_iters);
+
+/*
  * gsl_check_graph -- checks a CSR on the device: offsets[0] == 0, offsets
  * non-decreasing, every column in [0, n).  Returns GSL_OK or GSL_EINVAL (the
  * message names the defect).  Symmetry is not checked.  Every other entry

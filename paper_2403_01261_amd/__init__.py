@@ -124,6 +124,8 @@ def load(path: str = None):
     lib.gsl_convergence_limit.restype = ctypes.c_int64
     lib.gsl_set_hub_limits.argtypes = [ctypes.c_int64, ctypes.c_int32]
     lib.gsl_lpa_noalloc.argtypes = [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _VP]
+    lib.gsl_graphs_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+    lib.gsl_graphs_bytes.restype = ctypes.c_int64
     lib.gsl_session_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
     lib.gsl_session_bytes.restype = ctypes.c_int64
     lib.gsl_session_create.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -382,6 +384,12 @@ class Context:
 
 
 GSL_EAGAIN = -5
+
+
+def gsl_graphs_bytes(n, nnz, graphs=1, weighted=False, max_iters=20) -> int:
+    """Upper bound of the device scratch a gsl_lpa_graphs call on a batch of
+    that size adds (library query, host only)."""
+    return int(load().gsl_graphs_bytes(int(n), int(nnz), int(graphs), int(bool(weighted)), int(max_iters)))
 
 
 class Session:

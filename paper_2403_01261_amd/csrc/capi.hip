@@ -1330,6 +1330,36 @@ int check_graph_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const i
   return GSL_OK;
 }
 
+// Bound of the hub tier's buffers for nnz entries: at most one hub per
+// 4,097 entries (H + 1 prefix entries and three records each), at most
+// nnz / kHubChunk + H chunks C, partition owners no more than chunks, a
+// staging batch of min(C, staging limit) chunks or the largest hub's chunks
+// (a batch holds at least one hub), and per chunk of a batch one partition
+// histogram of P + 1 counts, P <= min(largest hub's chunks, kHubMaxParts).
+int64_t hub_bytes_bound(int64_t nnz) {
+  const int64_t hubs = nnz / 4097 + 1, chunks = nnz / gsl::kHubChunk + hubs;
+  const int64_t widest = nnz / gsl::kHubChunk + 1;  // chunks of the largest possible hub
+  const int64_t limit = current_hub_limits().staging_bytes / ((int64_t)gsl::kHubChunk * 8);
+  const int64_t batch = std::min<int64_t>(chunks, std::max<int64_t>(limit, widest));
+  const int64_t P = std::min<int64_t>(widest, gsl::kHubMaxParts);
+  return hubs * (3 * 8 + 3 * 8) + 2 * chunks * 4 + batch * gsl::kHubChunk * 8 + batch * (P + 1) * 4;
+}
+
+// Device scratch a gsl_lpa_graphs call on a batch of `graphs` graphs with n
+// vertices and nnz entries in all grows the cache to (an upper bound: the
+// per-vertex arrays, the gathered global CSR and labels, the per-graph
+// arrays, the counters for max_iters sweeps and the hub-tier bound).
+int64_t graphs_bytes(int64_t n, int64_t nnz, int64_t graphs, bool weighted, int32_t max_iters) {
+  const int64_t G = graphs + 1;
+  const int64_t flag = (n + 3) / 4 * 4 + 16;
+  int64_t b = n * (4 + 4 + 4 + 4 + 8) + 3 * flag + gsl::plan_scratch(n) * 8;   // Cn list parent rep sigma, flags, plan
+  b += 2 * 4096 * 8 + (int64_t)gsl::kNumTiers * gsl::kMaxTierGrid * gsl::kCountFields * 8;
+  b += (int64_t)sizeof(Counters) + 4 * 8 * (int64_t)(max_iters > 0 ? max_iters : 1) + (int64_t)sizeof(gsl::SweepCtrl);
+  b += n * 4 + G * (4 + 8 + 8 + 1 + 8 + 8 + 8 + (int64_t)sizeof(gsl::GraphDesc) + 4) + 8;  // batch arrays
+  b += (n + 1) * 8 + nnz * 4 * (weighted ? 2 : 1) + n * 4;                          // gathered CSR, labels
+  return b + hub_bytes_bound(nnz);
+}
+
 // ---- sessions ----
 // Device bytes of a session of this capacity: the arena (two buffers), the
 // split buffers and per-graph records, the per-vertex and per-graph scratch,
@@ -1344,11 +1374,7 @@ int64_t session_bytes(int64_t cap_v, int64_t cap_e, int64_t cap_g, bool weighted
   b += 2 * 4096 * 8 + (int64_t)gsl::kNumTiers * gsl::kMaxTierGrid * gsl::kCountFields * 8;  // partials, tier records
   b += (int64_t)sizeof(Counters) + 4 * 8 * (kSessionSweepCap + 2) + (int64_t)sizeof(gsl::SweepCtrl);
   b += cap_v * 4 + G * (4 + 8 + 8 + 1 + 8 + 8 + 8 + (int64_t)sizeof(gsl::GraphDesc) + 4) + 8;  // batch arrays
-  const int64_t hubs = cap_e / 4097 + 1, chunks = cap_e / gsl::kHubChunk + hubs;
-  const int64_t staging_pairs = std::min<int64_t>(cap_e + (int64_t)gsl::kHubChunk * hubs,
-                                                  kDefaultHubStagingBytes / 8 + gsl::kHubChunk);
-  b += hubs * (3 * 8 + 3 * 8) + 2 * chunks * 4 + staging_pairs * 8 + chunks * 4 * 2;  // hub layout, owners, staging, hist
-  return b;
+  return b + hub_bytes_bound(cap_e);
 }
 
 void session_free(gsl_session &S) {
@@ -2060,6 +2086,11 @@ void gsl_release(void) {
 }
 
 const char *gsl_version(void) { return "gsl_lpa 0.3 (gfx950)"; }
+
+int64_t gsl_graphs_bytes(int64_t n, int64_t nnz, int64_t graphs, int32_t weighted, int32_t max_iters) {
+  if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || graphs < 0 || max_iters < 0) return -1;
+  return graphs_bytes(n, nnz, graphs, weighted != 0, max_iters);
+}
 
 int64_t gsl_session_bytes(int64_t max_vertices, int64_t max_entries, int32_t max_graphs, int32_t weighted) {
   if (max_vertices < 1 || max_vertices >= ((int64_t)1 << 31) - 1 || max_entries < 0 || max_graphs < 1) return -1;

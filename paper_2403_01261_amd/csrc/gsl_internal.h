@@ -189,6 +189,8 @@ hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
 // over the hubs (H + 1 entries each) of their chunks, hash partitions and
 // partition-boundary records (chunks * (partitions + 1)).
 constexpr int kHubChunk = 2048;
+// Most hash partitions of one hub row.
+constexpr int kHubMaxParts = 8192;
 // Merge table claims before a hub partition is re-merged in hashed
 // sub-passes (the largest value; see hub.hip).
 constexpr int kHubMergeCapMax = 4096 - 256 - 1;

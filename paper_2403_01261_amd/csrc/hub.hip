@@ -31,7 +31,7 @@ constexpr int kHubBlock = 256;
 constexpr int kHubK = kHubChunk / kHubBlock;  // row entries per lane
 constexpr int kTabLog2 = 12;                  // 4096 LDS slots (2 per chunk entry)
 constexpr int kTabSlots = 1 << kTabLog2;
-constexpr int kMaxParts = 8192;
+constexpr int kMaxParts = kHubMaxParts;
 constexpr int kPartSize = 2048;               // expected distinct labels per partition
 constexpr int kMergeBlock = 256;
 // Claims before a merge pass gives up and the partition is split into

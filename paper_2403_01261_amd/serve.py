@@ -11,10 +11,11 @@ idle slot, so batches of different slots overlap on the device, and a new
 request never waits for a whole earlier batch to drain unless every slot is
 busy or the budget is spent.
 
-Admission is by device-memory footprint (footprint()): the scratch the
-library allocates per vertex and per entry for a batch, plus the labels.  The
-sum over admitted, unfinished requests never exceeds the budget; a request
-whose own footprint exceeds it is rejected at once.  Errors stay with their
+Admission is by device-memory footprint (footprint()): the library's bound
+of the scratch a batch needs for the graph (gsl_graphs_bytes), plus the
+labels; each slot's fixed scratch comes off the budget once.  The sum over
+admitted, unfinished requests never exceeds the budget; a request whose own
+footprint exceeds it is rejected at once.  Errors stay with their
 request: gsl_lpa_graphs reports a malformed graph on its own (status
 GSL_EINVAL), and if a whole batch fails (for instance a weight overflow), the
 slot reruns its requests one by one so only the culprit fails.
@@ -33,16 +34,22 @@ import threading
 import time
 from typing import Any, Callable, List, Optional
 
-# Library scratch per vertex of a batch (label and flag arrays, vertex list,
-# split parents, graph ids, gathered offsets, batch labels) plus the 4-byte
-# output label, and per CSR entry (gathered global cols; weights double it).
-BYTES_PER_VERTEX = 64
-BYTES_PER_ENTRY = 4
-
-
 def footprint(n: int, nnz: int, weighted: bool = False) -> int:
-    """Device bytes a request adds to a batch while it runs."""
-    return BYTES_PER_VERTEX * (n + 1) + BYTES_PER_ENTRY * nnz * (2 if weighted else 1)
+    """Device bytes a request adds to a batch while it runs, from the
+    library's own bound (gsl_graphs_bytes): what a batch holding this graph
+    needs beyond an empty batch, plus the request's 4-byte output labels.  The
+    bound's terms grow no faster than linearly with a batch's totals, except
+    the hub tier's, which is bounded per graph; so the footprints of a
+    batch's graphs plus base_bytes() bound the batch."""
+    from . import gsl_graphs_bytes
+    return gsl_graphs_bytes(n, nnz, 1, weighted) - gsl_graphs_bytes(0, 0, 0, weighted) + 4 * n
+
+
+def base_bytes(weighted: bool = False) -> int:
+    """Scratch of an empty batch (counters, per-tier records, partials): held
+    once per slot."""
+    from . import gsl_graphs_bytes
+    return gsl_graphs_bytes(0, 0, 0, weighted)
 
 
 @dataclasses.dataclass
@@ -63,10 +70,11 @@ class Request:
     batch_id: int = -1
     labels: Any = None
     iterations: int = -1
+    cost: int = -1              # device bytes charged to the budget (set by the scheduler)
 
     @property
     def bytes(self) -> int:
-        return footprint(self.n, self.nnz, self.weighted)
+        return self.cost if self.cost >= 0 else footprint(self.n, self.nnz, self.weighted)
 
     @property
     def latency(self) -> float:
@@ -74,11 +82,15 @@ class Request:
 
 
 class Scheduler:
-    """FIFO admission under a device-memory budget (no GPU involved)."""
+    """FIFO admission under a device-memory budget (no GPU involved).
+    `cost(n, nnz, weighted)` gives a request's device bytes (footprint() by
+    default)."""
 
-    def __init__(self, budget_bytes: int, max_batch_graphs: int = 1024, max_batch_bytes: Optional[int] = None):
+    def __init__(self, budget_bytes: int, max_batch_graphs: int = 1024, max_batch_bytes: Optional[int] = None,
+                 cost: Optional[Callable[[int, int, bool], int]] = None):
         if budget_bytes <= 0 or max_batch_graphs <= 0:
             raise ValueError("budget and batch size must be positive")
+        self.cost = cost or footprint
         self.budget = int(budget_bytes)
         self.max_graphs = int(max_batch_graphs)
         self.max_bytes = int(max_batch_bytes) if max_batch_bytes else self.budget
@@ -87,6 +99,7 @@ class Scheduler:
         self.peak_in_flight = 0
 
     def submit(self, req: Request) -> bool:
+        req.cost = int(self.cost(req.n, req.nnz, req.weighted))
         if req.bytes > min(self.budget, self.max_bytes):
             req.state = "rejected"
             req.code = -2  # GSL_ENOMEM: can never fit
@@ -128,12 +141,22 @@ class Server:
     request of the batch or raises; status 0 is success."""
 
     def __init__(self, executor, slots: int = 2, budget_bytes: int = 32 << 30, max_batch_graphs: int = 1024,
-                 max_batch_bytes: Optional[int] = None, clock: Callable[[], float] = time.perf_counter):
+                 max_batch_bytes: Optional[int] = None, clock: Callable[[], float] = time.perf_counter,
+                 cost: Optional[Callable[[int, int, bool], int]] = None, slot_base_bytes: Optional[int] = None):
+        """cost: a request's device bytes (footprint() by default);
+        slot_base_bytes: what each slot holds with an empty batch, taken off
+        the budget once per slot (base_bytes(True) by default, 0 with a
+        custom cost)."""
         if slots <= 0:
             raise ValueError("slots must be positive")
         self.executor = executor
         self.slots = slots
-        self.sched = Scheduler(budget_bytes, max_batch_graphs, max_batch_bytes)
+        if slot_base_bytes is None:
+            slot_base_bytes = 0 if cost is not None else base_bytes(True)
+        budget = int(budget_bytes) - slots * int(slot_base_bytes)
+        if budget <= 0:
+            raise ValueError("the budget does not cover the slots' fixed scratch (%d bytes each)" % slot_base_bytes)
+        self.sched = Scheduler(budget, max_batch_graphs, max_batch_bytes, cost)
         self.clock = clock
         self.batches: List[List[Request]] = []
 

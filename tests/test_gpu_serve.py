@@ -112,3 +112,39 @@ def test_continuous_server_requests_join_running_graphs(gsl):
         off, cols, w = r.payload
         alone, st = gsl.gsl_lpa_ex(off, cols, w)
         np.testing.assert_array_equal(lab, alone.cpu().numpy())
+
+
+def test_footprints_bound_what_the_library_allocates(gsl):
+    """The serving budget's bytes are real: a fresh context running a batch of
+    graphs, and a session with its graphs running, take no more device memory
+    than the library's bounds (footprints plus the empty batch; the session's
+    device_bytes) allow, up to allocation granularity."""
+    from paper_2403_01261_amd.serve import base_bytes, footprint
+    b = workloads.make(5, small=True)
+    graphs = [b.subgraph(k) for k in range(b.num_graphs)]
+    tens = [to_device(g)[:2] + (None, torch.empty(g.n, dtype=torch.int32, device="cuda")) for g in graphs]
+    slack = 32 << 20
+    bound = base_bytes() + sum(footprint(g.n, g.nnz) for g in graphs)
+    with gsl.Context() as ctx:
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        labs, its, _ = ctx.lpa_graphs(tens)
+        torch.cuda.synchronize()
+        used = free0 - torch.cuda.mem_get_info()[0]
+    say("batch of %d graphs: %d bytes allocated, bound %d" % (len(graphs), used, bound))
+    assert used <= bound + slack
+    for g, lab in zip(graphs[:4], labs[:4]):
+        np.testing.assert_array_equal(lab.cpu().numpy(), oracle.lpa(g).labels)
+    cap_v, cap_e, cap_g = 1 << 20, 1 << 24, 64
+    sbound = gsl.Session.device_bytes(cap_v, cap_e, cap_g)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    with gsl.Session(cap_v, cap_e, cap_g) as sess:
+        got = sess.add(tens[:30])
+        live = {t for t, st, _ in got if t >= 0}
+        while live:
+            live -= {t for t, _ in sess.step(2)}
+        used = free0 - torch.cuda.mem_get_info()[0]
+        assert sess.info()["device_bytes"] == sbound
+    say("session: %d bytes allocated, bound %d" % (used, sbound))
+    assert used <= sbound + slack

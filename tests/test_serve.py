@@ -72,14 +72,39 @@ def check_against_oracle(reqs):
         assert r.iterations == res.iterations
 
 
-def test_footprint_formula():
-    assert footprint(0, 0) == 64
-    assert footprint(10, 100) == 64 * 11 + 400
-    assert footprint(10, 100, weighted=True) == 64 * 11 + 800
+def lin_cost(n, nnz, weighted=False):
+    """A stand-in cost for the scheduling tests (no library needed)."""
+    return 64 * (n + 1) + 4 * nnz * (2 if weighted else 1)
+
+
+def test_footprint_is_the_library_bound():
+    """footprint() is gsl_graphs_bytes' growth for one graph plus its labels,
+    grows with the graph and covers the arrays every batch holds per vertex
+    and per entry (the GPU tests check it against what a batch allocates)."""
+    import os
+    import paper_2403_01261_amd as gsl
+    if not os.path.exists(gsl.LIB_PATH):
+        pytest.skip("libgsl_lpa.so not built")
+    from paper_2403_01261_amd.serve import base_bytes
+    b0 = gsl.gsl_graphs_bytes(0, 0, 0)
+    assert base_bytes() == b0 > 0
+    assert footprint(10, 100) == gsl.gsl_graphs_bytes(10, 100, 1) - b0 + 40
+    assert footprint(10, 100, weighted=True) == footprint(10, 100) + 400
+    assert gsl.gsl_graphs_bytes(-1, 0, 1) == -1
+    # per vertex: at least the label, change/flag, list, split and graph-id
+    # arrays and the gathered offsets; per entry: the gathered column
+    assert footprint(10 ** 6, 0) - footprint(0, 0) >= 10 ** 6 * 40
+    assert footprint(0, 10 ** 6) - footprint(0, 0) >= 4 * 10 ** 6
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        n, e = int(rng.integers(0, 10 ** 6)), int(rng.integers(0, 10 ** 8))
+        assert footprint(n + 1, e) > footprint(n, e) and footprint(n, e + 4097) > footprint(n, e)
+    # one hub of 16 M entries: staging and partition records grow with it
+    assert footprint(2, 1 << 24) > footprint(2, 1 << 23) * 1.9
 
 
 def test_scheduler_fifo_budget_and_limits():
-    s = Scheduler(budget_bytes=10_000, max_batch_graphs=2)
+    s = Scheduler(budget_bytes=10_000, max_batch_graphs=2, cost=lin_cost)
     reqs = [Request(rid=k, arrival=0.0, n=30, nnz=100) for k in range(5)]  # 2384 bytes each
     for r in reqs:
         assert s.submit(r)
@@ -98,7 +123,7 @@ def test_scheduler_fifo_budget_and_limits():
 def test_all_requests_served_and_match_oracle():
     reqs = make_requests(60, rate=2000.0)
     ex = FakeExecutor(0.01)
-    srv = Server(ex, slots=2, budget_bytes=1 << 30)
+    srv = Server(ex, slots=2, budget_bytes=1 << 30, cost=lin_cost)
     srv.serve(reqs)
     assert all(r.state == "done" for r in reqs)
     check_against_oracle(reqs)
@@ -110,9 +135,9 @@ def test_all_requests_served_and_match_oracle():
 
 def test_budget_is_never_exceeded():
     reqs = make_requests(40, rate=5000.0, sizes=(200, 400))
-    budget = 3 * max(r.bytes for r in reqs)
+    budget = 3 * max(lin_cost(r.n, r.nnz) for r in reqs)
     ex = FakeExecutor(0.005)
-    srv = Server(ex, slots=3, budget_bytes=budget)
+    srv = Server(ex, slots=3, budget_bytes=budget, cost=lin_cost)
     srv.serve(reqs)
     assert all(r.state == "done" for r in reqs)
     assert ex.peak_bytes <= budget
@@ -123,7 +148,7 @@ def test_budget_is_never_exceeded():
 def test_oversize_request_rejected_alone():
     reqs = make_requests(10, rate=1000.0)
     huge = Request(rid=99, arrival=0.001, n=10 ** 6, nnz=10 ** 7, payload=None)
-    srv = Server(FakeExecutor(0.002), slots=2, budget_bytes=1 << 20)
+    srv = Server(FakeExecutor(0.002), slots=2, budget_bytes=1 << 20, cost=lin_cost)
     srv.serve(reqs + [huge])
     assert huge.state == "rejected"
     assert all(r.state == "done" for r in reqs)
@@ -133,7 +158,7 @@ def test_oversize_request_rejected_alone():
 def test_failing_request_fails_alone():
     reqs = make_requests(30, rate=20000.0)  # bursty: batches of several requests
     ex = FakeExecutor(0.005, poison={7}, bad={11})
-    srv = Server(ex, slots=2, budget_bytes=1 << 30)
+    srv = Server(ex, slots=2, budget_bytes=1 << 30, cost=lin_cost)
     srv.serve(reqs)
     for r in reqs:
         if r.rid in (7, 11):
@@ -148,7 +173,7 @@ def test_failing_request_fails_alone():
 def test_cancel_queued_request():
     reqs = make_requests(12, rate=1e6)  # all arrive at once
     ex = FakeExecutor(0.02)
-    srv = Server(ex, slots=1, budget_bytes=1 << 30, max_batch_graphs=2)
+    srv = Server(ex, slots=1, budget_bytes=1 << 30, max_batch_graphs=2, cost=lin_cost)
     srv.serve(reqs, cancel={0.005: [11]})
     assert reqs[11].state == "cancelled"
     assert not any(11 in rids for _, rids, _ in ex.calls)
@@ -163,7 +188,7 @@ def test_requests_admitted_while_others_run():
     # on a loaded machine, and both requests must not be there yet
     reqs[0].arrival, reqs[1].arrival = 0.0, 0.1
     ex = FakeExecutor(1.0)
-    srv = Server(ex, slots=2, budget_bytes=1 << 30)
+    srv = Server(ex, slots=2, budget_bytes=1 << 30, cost=lin_cost)
     srv.serve(reqs)
     assert reqs[0].slot != reqs[1].slot
     assert reqs[1].t_admit < reqs[0].t_done
