@@ -22,13 +22,15 @@ __global__ void reorder_invert(const int32_t *__restrict__ list, int64_t n, int3
     old2new[list[p]] = (int32_t)p;
 }
 
-// off2[p + 1] = degree of list[p]; off2[0] = 0.  Also the initial labels.
+// off2[p + 1] = degree of list[p] for the np non-isolated rows; off2[0] = 0.
+// Also the initial labels of all n vertices (an isolated vertex keeps its
+// own, even where an entry of a graph that is not symmetric names it).
 __global__ void reorder_degrees(const int64_t *__restrict__ off, const int32_t *__restrict__ list,
-                                int64_t np, int64_t *__restrict__ off2, int32_t *__restrict__ lab) {
+                                int64_t np, int64_t n, int64_t *__restrict__ off2, int32_t *__restrict__ lab) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
     const int32_t v = list[p];
-    off2[p + 1] = off[v + 1] - off[v];
+    if (p < np) off2[p + 1] = off[v + 1] - off[v];
     lab[p] = v;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) off2[0] = 0;
@@ -304,7 +306,7 @@ hipError_t launch_reorder(const int64_t *off, const int32_t *cols, const uint32_
   const int64_t np = n - tier_count_h[0];
   constexpr int kCap = 256 * 32;
   reorder_invert<<<grid_of(n, 256, kCap), 256, 0, s>>>(list, n, old2new);
-  reorder_degrees<<<grid_of(np > 0 ? np : 1, 256, kCap), 256, 0, s>>>(off, list, np, off2, lab);
+  reorder_degrees<<<grid_of(n, 256, kCap), 256, 0, s>>>(off, list, np, n, off2, lab);
   if (np > 0) {
     const int64_t nb = (np + kScanBlock - 1) / kScanBlock;
     scan_local<<<(unsigned)nb, kScanBlock, 0, s>>>(off2 + 1, np, scan_tmp);

@@ -481,3 +481,27 @@ def test_lpa_rejects_offsets_not_starting_at_zero(gsl):
     assert e.value.code == gsl.GSL_EINVAL
     lab, st = gsl.gsl_lpa_ex(off, cols, w)
     np.testing.assert_array_equal(lab.cpu().numpy(), oracle.lpa(g).labels)
+
+
+def test_entries_naming_vertices_without_entries(gsl):
+    """Outside the symmetric-input contract: a directed graph whose entries
+    name vertices that have no entries of their own.  Such a vertex lies in
+    the isolated tier of the renumbered layout and must still hold its own
+    id as label there (never an unwritten value), so both layouts match the
+    oracle's sweeps row for row.  Pruning and the split are defined for
+    symmetric graphs, so both are off."""
+    rng = np.random.default_rng(41)
+    n, active = 6000, 4000
+    deg = np.minimum(rng.zipf(1.6, active), 3000)
+    deg[:2] = (5000, 9000)                        # two rows in the hub tier
+    rows = np.repeat(np.arange(active), deg)
+    cols = rng.integers(0, n, rows.size)          # a third of the targets have no row
+    cols = np.sort((rows.astype(np.int64) << 32) | cols) & 0xFFFFFFFF   # each row sorted by target
+    g = graphgen.from_entries(n, rows, cols)
+    for max_iters in (1, 2, 20):
+        r = oracle.lpa(g, max_iters, 0.0, prune=False, split=False)
+        for layout in ("original", "renumbered"):
+            lab, st = run_gpu(gsl, g, max_iters, 0.0, prune=False, split=False, layout=layout)
+            assert st["iterations"] == r.iterations, (max_iters, layout)
+            np.testing.assert_array_equal(lab, r.labels, err_msg="max_iters %d %s" % (max_iters, layout))
+            assert lab.min() >= 0 and lab.max() < n
