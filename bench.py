@@ -122,6 +122,34 @@ def measured_traffic(workload: str, kernel: str, levels, launches_per_step: int,
 COPY_BYTES = 1 << 30  # plain device-to-device copy used to calibrate the PMC counters
 
 
+# L2-to-memory requests by size: read bytes are 32, 64 and 128 times these
+# counts, write bytes 64 times the 64-byte writes and 32 times the rest.
+RAW_READ = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+RAW_WRITE = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum")
+
+
+def _dispatch_bytes(d: str, kind: str):
+    """{dispatch_id: (kernel_name, bytes)} of L2-to-memory traffic from a
+    rocprofv3 --pmc csv directory (kind "read" or "write"): from the request
+    counts by size when the run collected them, else from FETCH_SIZE /
+    WRITE_SIZE (KiB).  Returns (record, source)."""
+    names = RAW_READ if kind == "read" else RAW_WRITE
+    raw = {c: _read_counter_csv(d, c) for c in names}
+    if all(raw.values()):
+        out = {}
+        for did, (name, _) in raw[names[0]].items():
+            v = {c: raw[c].get(did, (name, 0.0))[1] for c in names}
+            if kind == "read":
+                b = 32.0 * v[names[0]] + 64.0 * v[names[1]] + 128.0 * v[names[2]]
+            else:
+                b = 32.0 * (v[names[0]] - v[names[1]]) + 64.0 * v[names[1]]
+            out[did] = (name, b)
+        return out, "request counts " + ", ".join(names)
+    counter = "FETCH_SIZE" if kind == "read" else "WRITE_SIZE"
+    rec = _read_counter_csv(d, counter)
+    return {k: (n, v * 1024.0) for k, (n, v) in rec.items()}, counter
+
+
 def _read_counter_csv(d: str, counter: str):
     """{dispatch_id: (kernel_name, value)} from a rocprofv3 --pmc csv directory."""
     import csv
@@ -171,20 +199,22 @@ def _short(name: str) -> str:
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int, kernel: str,
-                  commands: list, calls: int, levels, launches_per_call: int, out_dir: str = None) -> dict:
-    """Traffic of `kernel` from FETCH_SIZE / WRITE_SIZE runs, each scaled by
-    the counter's reading for the plain COPY_BYTES copy: the sum over every
-    dispatch of the kernel divided by the number of gsl_lpa calls the run
-    made (`calls`, each with `launches_per_call` working launches of the
-    kernel under the tier table `levels`).  Launches enqueued after a loop
-    converged return at once and add next to nothing, so bytes per call over
-    working launches per call is the traffic of one working launch -- the
-    same launch set the benchmark's per-launch durations average over.
-    Writes traffic.json and the kernel-trace summary into out_dir
-    (profiles/)."""
+                  commands: list, calls: int, levels, launches_per_call: int, out_dir: str = None,
+                  trace_calls: int = 0) -> dict:
+    """Traffic of `kernel` from two counter runs (reads, then writes): the
+    sum over every dispatch of the kernel divided by the number of gsl_lpa
+    calls the run made (`calls`, each with `launches_per_call` working
+    launches of the kernel under the tier table `levels`).  Launches enqueued
+    after a loop converged return at once and add next to nothing, so bytes
+    per call over working launches per call is the traffic of one working
+    launch -- the same launch set the benchmark's per-launch durations
+    average over.  With the request counts by size the bytes are exact and
+    the plain COPY_BYTES copy of the runs checks them; with FETCH_SIZE /
+    WRITE_SIZE they are scaled by what those read for the copy.  Writes
+    traffic.json and the kernel-trace summary into out_dir (profiles/)."""
     from graphgen import workloads
-    fetch = _read_counter_csv(fetch_dir, "FETCH_SIZE")
-    write = _read_counter_csv(write_dir, "WRITE_SIZE")
+    fetch, fsrc = _dispatch_bytes(fetch_dir, "read")
+    write, wsrc = _dispatch_bytes(write_dir, "write")
 
     def calib(rec):
         copies = [v for n, v in rec.values() if "copyBuffer" in n]
@@ -195,10 +225,11 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
     kw = [v for n, v in write.values() if _short(n).startswith(kernel)]
     if not kf or not kw or not cf or not cw:
         raise SystemExit("counter runs lack the kernel %r or the calibration copy" % kernel)
-    sf = COPY_BYTES / (cf * 1024.0)
-    sw = COPY_BYTES / (cw * 1024.0)
-    fetch_step = sum(kf) * 1024.0 * sf / calls
-    write_step = sum(kw) * 1024.0 * sw / calls
+    exact_r, exact_w = fsrc.startswith("request"), wsrc.startswith("request")
+    sf = 1.0 if exact_r else COPY_BYTES / cf
+    sw = 1.0 if exact_w else COPY_BYTES / cw
+    fetch_step = sum(kf) * sf / calls
+    write_step = sum(kw) * sw / calls
     fetch_b = fetch_step / launches_per_call
     write_b = write_step / launches_per_call
     wname = workloads.NAMES[workload]
@@ -213,8 +244,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
         "launches_per_call": launches_per_call, "levels": [list(x) for x in levels],
         "bytes_per_launch": int(round(fetch_b + write_b)), "fetch_bytes_per_launch": int(round(fetch_b)),
         "write_bytes_per_launch": int(round(write_b)), "dispatches": len(kf),
-        "copy_fetch_kib": cf, "copy_write_kib": cw, "scale_fetch": sf, "scale_write": sw,
-        "source_hash": source_hash(), "commands": commands}
+        "read_counters": fsrc, "write_counters": wsrc,
+        "copy_read_bytes": cf, "copy_write_bytes": cw, "copy_bytes": COPY_BYTES, "scale_fetch": sf,
+        "scale_write": sw, "source_hash": source_hash(), "commands": commands}
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
@@ -229,11 +261,21 @@ def summarize_pmc(fetch_dir: str, write_dir: str, trace_dir: str, workload: int,
         for c in commands:
             f.write("    %s\n" % c)
         f.write("\nTier table (max degree, variant) of the runs: %s.\n\n" % json.dumps([list(x) for x in levels]))
-        f.write("HBM traffic of `%s`: %d dispatches over %d gsl_lpa calls of %d working launches each; "
-                "per working launch fetch %.3f GB, write %.3f GB (FETCH_SIZE / WRITE_SIZE summed over the "
-                "dispatches, scaled by a %d MiB copy: x%.4f / x%.4f).\n\n"
-                % (kernel, len(kf), calls, launches_per_call, fetch_b / 1e9, write_b / 1e9, COPY_BYTES >> 20,
-                   sf, sw))
+        f.write("L2-to-memory traffic of `%s`: %d dispatches over %d gsl_lpa calls of %d working launches "
+                "each; per working launch read %.3f GB, write %.3f GB.  Reads from %s, writes from %s, summed "
+                "over the dispatches; the plain %d MiB copy of the same runs reads %.1f MiB and writes %.1f MiB "
+                "by the same counters (scale applied: x%.4f / x%.4f).\n\n"
+                % (kernel, len(kf), calls, launches_per_call, fetch_b / 1e9, write_b / 1e9, fsrc, wsrc,
+                   COPY_BYTES >> 20, cf / 2 ** 20, cw / 2 ** 20, sf, sw))
+        mine = [r for r in stats if _short(r["Name"]).startswith(kernel)] if stats else []
+        if mine and trace_calls > 0:
+            tot = sum(r["TotalDurationNs"] for r in mine) / 1e6
+            f.write("Launches as the benchmark counts them (its `launches_per_step`): %d per gsl_lpa call.  "
+                    "The trace's %d calls spend %.2f ms in `%s`: %.3f ms per call, %.3f ms per launch (for the "
+                    "kernel the benchmark's roofline names, the figure its `avg_launch_ms` measures with HIP "
+                    "events).\n\n"
+                    % (launches_per_call, trace_calls, tot, kernel, tot / trace_calls,
+                       tot / (trace_calls * launches_per_call)))
         if stats:
             f.write("Kernel trace of the first command.  `calls` counts every dispatch; sweep kernels "
                     "enqueued after the loop converged return at once, so `working calls` and their "
@@ -572,6 +614,33 @@ def batched_gpu(b, args, tiers_mode):
     return res
 
 
+def batched_profile(b, calls: int) -> int:
+    """Exactly `calls` gsl_lpa_batched calls over the whole batch with the
+    default tiers (as the batch rides along in the default run), then one in
+    timing mode for the launch counts (a profiler sees calls + 1 calls)."""
+    import torch
+
+    import paper_2403_01261_amd as gsl
+    from graphgen import workloads
+    gsl.load()
+    dev = torch.device("cuda:0")
+    off = torch.from_numpy(b.offsets).to(dev)
+    cols = torch.from_numpy(b.cols).to(dev)
+    vb = torch.from_numpy(b.vtx_base).to(dev)
+    eb = torch.from_numpy(b.edge_base).to(dev)
+    out = torch.empty(b.n, dtype=torch.int32, device=dev)
+    mi, tol = workloads.MAX_ITERS, workloads.TOLERANCE
+    for _ in range(calls):
+        gsl.gsl_lpa_batched(vb, eb, off, cols, None, mi, tol, out=out)
+    torch.cuda.synchronize()
+    _, _, st = gsl.gsl_lpa_batched(vb, eb, off, cols, None, mi, tol, out=out, timing=True)
+    print(json.dumps({"profile_calls": calls + 1, "levels": gsl.gsl_get_tiers(),
+                      "tier_launches": [t["launches"] for t in st["tiers"]],
+                      "ms_tier": [round(t["ms"], 4) for t in st["tiers"]],
+                      "iterations": st["iterations"]}), flush=True)
+    return 0
+
+
 def bench_batched(args):
     """Workload 5 as the headline: graphs/s of one gsl_lpa_batched call over
     the 4,096 graphs, with the plain loop, the servers and the CPU baselines
@@ -580,6 +649,8 @@ def bench_batched(args):
     t0 = time.time()
     b = workloads.make(5, small=args.small)
     log("generated batch: %d graphs, N=%d, nnz=%d in %.1fs" % (b.num_graphs, b.n, b.nnz, time.time() - t0))
+    if args.profile_steps:
+        return batched_profile(b, args.profile_steps)
     pool = None if args.no_cpu_baseline or args.small else batched_cpu_pool(b)
     import paper_2403_01261_amd as gsl
     gsl.load()
@@ -640,12 +711,14 @@ def main(argv=None):
     ap.add_argument("--levels", default=None, help="tier table of the profiled runs, JSON (--summarize-pmc)")
     ap.add_argument("--launches-per-call", type=int, default=0,
                     help="working launches of the kernel per call (--summarize-pmc)")
+    ap.add_argument("--trace-calls", type=int, default=0,
+                    help="gsl_lpa calls of the kernel-trace run (--summarize-pmc)")
     args = ap.parse_args(argv)
     if args.tiers is None:
         args.tiers = "default" if args.workload == 4 else "tune"
     if args.summarize_pmc:
         r = summarize_pmc(*args.summarize_pmc, args.workload, args.kernel, args.commands, args.calls,
-                          json.loads(args.levels), args.launches_per_call)
+                          json.loads(args.levels), args.launches_per_call, trace_calls=args.trace_calls)
         print(json.dumps(r))
         return 0
     if args.gpus != 1:

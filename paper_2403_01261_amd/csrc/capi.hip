@@ -997,19 +997,23 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
       stats->ms_sweeps = elapsed(s.ev[1], s.ev[2]);
       stats->ms_split = elapsed(s.ev[2], s.ev[3]);
       stats->ms_total = elapsed(s.ev[0], s.ev[3]);
-      // Only sweeps that ran (k < it) count; a record spans its event to the
-      // next one.  Hub finishing kernels (kind 1) go to ms_hub_finish.
+      // Only sweeps that ran count: enqueued sweep e is sweep e +
+      // first_kernel_sweep of the loop.  A record spans its event to the next
+      // one.  Hub finishing kernels (kind 1) go to ms_hub_finish.
+      const int ran = it - first_kernel_sweep;
       for (const Launch &l : launches) {
-        if (l.sweep >= it) continue;
+        if (l.sweep >= ran) continue;
         const float ms = elapsed(s.pool[l.ev], s.pool[l.ev + 1]);
         if (l.kind == 1)
           stats->ms_hub_finish += ms;
         else
           stats->ms_tier[l.tier] += ms;
       }
-      for (int k = first_kernel_sweep; k < it && k < (int)sweep_ev.size() && k < GSL_STATS_MAX_ITERS; ++k) {
-        const size_t end = k + 1 < (int)sweep_ev.size() ? sweep_ev[k + 1] - 1 : nev - 1;
-        stats->ms_sweep[k] = elapsed(s.pool[sweep_ev[k]], s.pool[end]);
+      for (int k = first_kernel_sweep; k < it && k < GSL_STATS_MAX_ITERS; ++k) {
+        const int e = k - first_kernel_sweep;
+        if (e >= (int)sweep_ev.size()) break;
+        const size_t end = e + 1 < (int)sweep_ev.size() ? sweep_ev[(size_t)e + 1] - 1 : nev - 1;
+        stats->ms_sweep[k] = elapsed(s.pool[sweep_ev[(size_t)e]], s.pool[end]);
       }
     }
   }

@@ -82,3 +82,30 @@ def test_summarize_pmc_scales_by_the_copy(tmp_path):
     assert bench.measured_traffic("rmat-s22", "sweep_lds<8, 5, 256, 2>", other, 2, path=path) is None
     assert bench.measured_traffic("rmat-s22", "sweep_lds<8, 5, 256, 2>", levels, 0, path=path) is None
     assert bench.measured_traffic("rmat-s26", "sweep_lds<8, 5, 256, 2>", levels, 2, path=path) is None
+
+
+def test_summarize_pmc_from_request_counts(tmp_path):
+    """With the L2 request counts by size the bytes are exact (no scaling):
+    32 / 64 / 128 bytes per read request, 64 per 64-byte write, 32 per other
+    write; the copy is recorded as a check."""
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    copy = "__amd_rocclr_copyBuffer"
+    kern = "gsl::(anonymous namespace)::hub_insert(gsl::SweepArgs, gsl::(anonymous namespace)::HubArgs)"
+    r32, r64, r128 = bench.RAW_READ
+    wall, w64 = bench.RAW_WRITE
+    reads = [[1, copy, r32, 0], [1, copy, r64, 0], [1, copy, r128, (1 << 30) // 128]]
+    writes = [[1, copy, wall, (1 << 30) // 64], [1, copy, w64, (1 << 30) // 64]]
+    for d in (2, 3):  # two working launches in one call
+        reads += [[d, kern, r32, 10], [d, kern, r64, 100], [d, kern, r128, 1000]]
+        writes += [[d, kern, wall, 50], [d, kern, w64, 20]]
+    _write(str(tmp_path / "r" / "r_counter_collection.csv"), hdr, reads)
+    _write(str(tmp_path / "w" / "w_counter_collection.csv"), hdr, writes)
+    out = tmp_path / "profiles"
+    levels = [[32, 16], [64, 6], [128, 8], [512, 9], [1024, 17], [2048, 11], [4096, 13]]
+    rec = bench.summarize_pmc(str(tmp_path / "r"), str(tmp_path / "w"), str(tmp_path / "t"), 4, "hub_insert",
+                              ["cmd"], 1, levels, 2, out_dir=str(out))
+    assert rec["scale_fetch"] == 1.0 and rec["scale_write"] == 1.0
+    assert rec["copy_read_bytes"] == 1 << 30 and rec["copy_write_bytes"] == 1 << 30
+    assert rec["fetch_bytes_per_launch"] == 32 * 10 + 64 * 100 + 128 * 1000
+    assert rec["write_bytes_per_launch"] == 32 * 30 + 64 * 20
+    assert rec["read_counters"].startswith("request counts")
