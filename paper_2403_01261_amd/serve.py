@@ -272,12 +272,17 @@ class ContinuousServer:
     for a batch to drain, and its result is what it would get alone (each
     graph keeps its own sweeps and convergence test in the session).
 
+    A step that fails (a weight overflow fails the whole session) loses the
+    graphs it held: the backend is reset and those requests run again one at
+    a time, each alone in the session, so only the culprit fails.
+
     backend.add(requests) returns one (ticket, status) per request (status 0:
     admitted, ticket -1 when nothing has to run; EAGAIN: no room now, and the
     later requests of the call were not tried; anything else: rejected),
-    backend.step(sweeps) returns [(ticket, sweeps_run)] of finished graphs,
-    backend.live() the graphs still running.  Plain Python, tested on the CPU
-    with a fake backend; SessionBackend is the GPU one."""
+    backend.step(sweeps) returns [(ticket, sweeps_run)] of finished graphs or
+    raises, backend.reset() empties the session after a failed step.  Plain
+    Python, tested on the CPU with a fake backend; SessionBackend is the GPU
+    one."""
 
     EAGAIN = -5
 
@@ -291,6 +296,46 @@ class ContinuousServer:
         self.clock = clock
         self.steps = 0
         self.admissions: List[int] = []   # requests admitted before each step
+        self.failed_steps = 0
+
+    def _admit(self, queue, by_ticket, suspects, t0) -> int:
+        """Admits from the head of the queue; returns how many now run.  A
+        suspect (it shared a failed step) runs only in an empty session and
+        keeps the session to itself."""
+        admitted = 0
+        while queue:
+            if any(r.rid in suspects for r in by_ticket.values()):
+                break
+            head = []
+            for k in range(min(len(queue), self.max_admit)):
+                r = queue[k]
+                if r.rid in suspects:
+                    if not head and not by_ticket:
+                        head = [r]
+                    break
+                head.append(r)
+            if not head:
+                break
+            res = self.backend.add(head)
+            stop = False
+            t = self.clock() - t0
+            for r, (ticket, status) in zip(head, res):
+                if status == self.EAGAIN:
+                    stop = True
+                    break
+                queue.popleft()
+                r.t_admit = t
+                if status != 0:
+                    r.state, r.code, r.error, r.t_done = "failed", status, "graph rejected by the library", t
+                elif ticket < 0:
+                    r.state, r.iterations, r.t_done = "done", 0, t
+                else:
+                    r.state = "running"
+                    by_ticket[ticket] = r
+                    admitted += 1
+            if stop or len(res) < len(head):
+                break
+        return admitted
 
     def serve(self, requests: List[Request], cancel: Optional[dict] = None) -> List[Request]:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -298,6 +343,7 @@ class ContinuousServer:
         queue: collections.deque = collections.deque()
         cancels = sorted((cancel or {}).items())
         by_ticket = {}
+        suspects = set()
         t0 = self.clock()
         while pending or queue or by_ticket:
             now = self.clock() - t0
@@ -311,31 +357,26 @@ class ContinuousServer:
                         if r.rid == rid:
                             queue.remove(r)
                             r.state = "cancelled"
-            admitted = 0
-            while queue:
-                head = [queue[k] for k in range(min(len(queue), self.max_admit))]
-                res = self.backend.add(head)
-                stop = False
-                t = self.clock() - t0
-                for r, (ticket, status) in zip(head, res):
-                    if status == self.EAGAIN:
-                        stop = True
-                        break
-                    queue.popleft()
-                    r.t_admit = t
-                    if status != 0:
-                        r.state, r.code, r.error, r.t_done = "failed", status, "graph rejected by the library", t
-                    elif ticket < 0:
-                        r.state, r.iterations, r.t_done = "done", 0, t
-                    else:
-                        r.state = "running"
-                        by_ticket[ticket] = r
-                        admitted += 1
-                if stop or len(res) < len(head):
-                    break
+            admitted = self._admit(queue, by_ticket, suspects, t0)
             if by_ticket:
                 self.admissions.append(admitted)
-                finished = self.backend.step(self.sweeps)
+                try:
+                    finished = self.backend.step(self.sweeps)
+                except Exception as e:  # the session's graphs are lost
+                    self.failed_steps += 1
+                    running = sorted(by_ticket.values(), key=lambda q: (q.arrival, q.rid))
+                    by_ticket.clear()
+                    self.backend.reset()
+                    t = self.clock() - t0
+                    if len(running) == 1 and running[0].rid in suspects:
+                        r = running[0]
+                        r.state, r.code, r.error, r.t_done = "failed", getattr(e, "code", -3), str(e), t
+                    else:
+                        for r in reversed(running):  # back to the head of the queue, in order
+                            suspects.add(r.rid)
+                            r.state = "queued"
+                            queue.appendleft(r)
+                    continue
                 self.steps += 1
                 t = self.clock() - t0
                 for ticket, iters in finished:
@@ -359,8 +400,8 @@ class SessionBackend:
     def __init__(self, max_vertices: int, max_entries: int, max_graphs: int = 4096, max_iters: int = 20,
                  tolerance: float = 0.05, weighted: bool = False):
         from . import Session
-        self.session = Session(max_vertices, max_entries, max_graphs, max_iters, tolerance, weighted)
-        self._out = {}
+        self._args = (max_vertices, max_entries, max_graphs, max_iters, tolerance, weighted)
+        self.session = Session(*self._args)
 
     def add(self, reqs):
         res = self.session.add([tuple(r.payload[:3]) for r in reqs])
@@ -379,6 +420,12 @@ class SessionBackend:
 
     def live(self) -> int:
         return self.session.info()["live_graphs"]
+
+    def reset(self):
+        """A new, empty session in place of one whose step failed."""
+        from . import Session
+        self.session.close()
+        self.session = Session(*self._args)
 
     def close(self):
         self.session.close()

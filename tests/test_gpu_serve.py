@@ -148,3 +148,37 @@ def test_footprints_bound_what_the_library_allocates(gsl):
         assert sess.info()["device_bytes"] == sbound
     say("session: %d bytes allocated, bound %d" % (used, sbound))
     assert used <= sbound + slack
+
+
+def test_continuous_server_weight_overflow_fails_alone(gsl):
+    """A graph whose row weights sum to 2^32 makes its session step fail
+    (GSL_EOVERFLOW) and loses the session's graphs; the continuous server
+    starts a new session and reruns them one at a time, so only that graph
+    fails and every other result still equals the oracle."""
+    from paper_2403_01261_amd.serve import ContinuousServer, Request, SessionBackend
+    b = workloads.make(5, small=True)
+    graphs = [b.subgraph(k) for k in range(12)]
+    ovf = graphgen.from_undirected(3, [(0, 1), (0, 2)], [1 << 31, 1 << 31])
+    graphs.insert(4, ovf)
+    reqs = []
+    for k, g in enumerate(graphs):
+        off, cols, _ = to_device(g)
+        w = torch.from_numpy((g.weights if g.weights is not None else np.ones(g.nnz, np.uint32)).view(np.int32))
+        reqs.append(Request(rid=k, arrival=0.0, n=g.n, nnz=g.nnz, weighted=True, payload=(off, cols, w.cuda())))
+    torch.cuda.synchronize()
+    backend = SessionBackend(max_vertices=150_000, max_entries=3_000_000, max_graphs=32, weighted=True)
+    srv = ContinuousServer(backend, sweeps_per_step=2)
+    try:
+        srv.serve(reqs)
+    finally:
+        backend.close()
+    say("failed steps", srv.failed_steps)
+    assert reqs[4].state == "failed" and reqs[4].code == gsl.GSL_EOVERFLOW
+    assert srv.failed_steps >= 2
+    for k, (g, r) in enumerate(zip(graphs, reqs)):
+        if k == 4:
+            continue
+        assert r.state == "done", (k, r.state, r.error)
+        exp = oracle.lpa(g)
+        np.testing.assert_array_equal(r.labels.cpu().numpy(), exp.labels, err_msg="request %d" % k)
+        assert r.iterations == exp.iterations

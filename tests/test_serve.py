@@ -208,12 +208,14 @@ class FakeSession:
     a graph leaves with the oracle's labels once it has run the oracle's
     number of sweeps.  Records what was resident at every step."""
 
-    def __init__(self, cap_v, cap_e, cap_g, seconds_per_step=0.002):
+    def __init__(self, cap_v, cap_e, cap_g, seconds_per_step=0.002, poison=()):
         self.cap_v, self.cap_e, self.cap_g = cap_v, cap_e, cap_g
         self.dt = seconds_per_step
+        self.poison = set(poison)  # a step holding one of these fails (a weight overflow)
         self.live = {}          # ticket -> [request, sweeps done, sweeps needed, labels]
         self.next = 0
         self.steps = []         # sets of resident request ids, per step
+        self.resets = 0
 
     def _used(self):
         return (sum(r.n for r, *_ in self.live.values()), sum(r.nnz for r, *_ in self.live.values()))
@@ -240,6 +242,10 @@ class FakeSession:
     def step(self, sweeps):
         time.sleep(self.dt)
         self.steps.append({x[0].rid for x in self.live.values()})
+        if self.poison & self.steps[-1]:
+            err = RuntimeError("a row's summed weight reaches 2^32")
+            err.code = -4
+            raise err
         done = []
         for t, x in list(self.live.items()):
             x[1] = min(x[1] + sweeps, x[2])
@@ -251,6 +257,10 @@ class FakeSession:
 
     def collect(self, r):
         pass
+
+    def reset(self):
+        self.live.clear()
+        self.resets += 1
 
     def live_count(self):
         return len(self.live)
@@ -293,3 +303,21 @@ def test_continuous_server_cancel():
     srv.serve(reqs, cancel={0.002: [19]})
     assert reqs[19].state == "cancelled"
     assert sum(r.state == "done" for r in reqs) == 19
+
+
+def test_continuous_server_failing_step_fails_only_the_culprit():
+    """A step that fails loses every graph it held; the server resets the
+    session and runs those requests again one at a time, so only the culprit
+    fails (with the library's code) and the others match the oracle."""
+    reqs = make_requests(40, rate=20000.0)  # bursty: many graphs per step
+    fs = FakeSession(cap_v=4000, cap_e=10 ** 6, cap_g=16, poison={12})
+    srv = ContinuousServer(fs, sweeps_per_step=1)
+    srv.serve(reqs)
+    assert reqs[12].state == "failed" and reqs[12].code == -4
+    assert all(r.state == "done" for r in reqs if r.rid != 12)
+    check_against_oracle(reqs)
+    assert srv.failed_steps >= 2 and fs.resets == srv.failed_steps
+    # the failed step held others besides the culprit, and the culprit's last
+    # step held it alone
+    failed = [st for st in fs.steps if 12 in st]
+    assert len(failed[0]) > 1 and failed[-1] == {12}
