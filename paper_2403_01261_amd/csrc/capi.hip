@@ -171,6 +171,8 @@ struct SessionSlot {
   int32_t *labels_out = nullptr;
 };
 constexpr int kSessionSweepCap = 64;  // most sweeps one gsl_session_step runs
+// Dead space a session keeps before it compacts at the start of a step.
+constexpr int64_t kSessionCompactVertices = 1 << 16, kSessionCompactEntries = 1 << 20;
 }  // namespace
 
 // A session: a resident batch (the arena) that graphs join and leave between
@@ -1580,6 +1582,14 @@ int session_step(gsl_session &S, int32_t sweeps, int64_t capacity, int64_t *done
   int64_t live = 0;
   for (const SessionSlot &x : S.slot) live += x.live ? 1 : 0;
   if (live == 0) return GSL_OK;
+  // Dead space (finished or rejected graphs) costs every step its plan, a
+  // flag check per listed vertex and split passes; once it outgrows the live
+  // graphs, they are moved together first.
+  if (S.vtop - S.live_v > std::max<int64_t>(S.live_v, kSessionCompactVertices) ||
+      S.etop - S.live_e > std::max<int64_t>(S.live_e, kSessionCompactEntries)) {
+    const int crc = session_compact(S);
+    if (crc) return crc;
+  }
   const gsl::TierConfig cfg = current_tiers();
   const HubLimits lim = current_hub_limits();
   const int64_t N = S.vtop;
@@ -1655,7 +1665,7 @@ int session_step(gsl_session &S, int32_t sweeps, int64_t capacity, int64_t *done
   HIP_TRY(hipMemcpyAsync(S.ranges, r.data(), r.size() * sizeof(gsl::SessionRange), hipMemcpyHostToDevice, st));
   HIP_TRY(gsl::launch_session_split_labels(S.lab[S.cur], s.gid, S.sel, N, S.split_in, st));
   HIP_TRY(gsl::launch_split(off, S.cols[S.cur], N, S.split_in, s.parent, S.split_out, s.list, S.plan.tier_count,
-                            S.plan.tier_start, nullptr, nullptr, N, s.rep, s.sigma, cfg, st));
+                            S.plan.tier_start, nullptr, nullptr, N, s.rep, s.sigma, cfg, st, s.gid, S.sel));
   HIP_TRY(gsl::launch_session_finish(S.ranges, (int64_t)r.size(), S.split_out, s.gid, S.cap_g, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (size_t i = 0; i < fin.size(); ++i) {

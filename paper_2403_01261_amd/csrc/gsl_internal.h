@@ -305,11 +305,16 @@ hipError_t launch_init_labels(int32_t *C, int32_t *Cn, int64_t n, hipStream_t s)
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t count, hipStream_t s);
 
+// Alg. 2 split by union-find.  With gid / sel (batches), the first linking
+// pass skips the rows of graphs g with sel[g] == 0: a caller that gives those
+// vertices their own ids as labels keeps them singletons at the cost of a
+// flag check.
 hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, const int32_t *C,
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *rep,
-                        unsigned long long *cp, const TierConfig &cfg, hipStream_t s);
+                        unsigned long long *cp, const TierConfig &cfg, hipStream_t s,
+                        const int32_t *gid = nullptr, const uint8_t *sel = nullptr);
 // Alg. 1 split (min-label propagation on intra-community entries): labels
 // and flags initialised by launch_split_lp_init (f0 all set, f1 clear; NULL
 // flags for LP without pruning), then rounds until *changed stays 0.

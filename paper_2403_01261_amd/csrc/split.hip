@@ -89,9 +89,14 @@ constexpr int kLinkChunk = 8;
 __global__ __launch_bounds__(256) void split_link_first(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
                                                         const int32_t *__restrict__ C,
-                                                        int32_t *parent, int64_t n) {
+                                                        int32_t *parent, int64_t n,
+                                                        const int32_t *__restrict__ gid,
+                                                        const uint8_t *__restrict__ sel) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    // rows of graphs outside the selection stay singletons (their labels are
+    // their own ids, so no entry could link them anyway)
+    if (gid && !sel[gid[u]]) continue;
     const int64_t b = off[u];
     const int64_t e = off[u + 1] < b + kLinkScan ? off[u + 1] : b + kLinkScan;
     const int32_t cu = C[u];
@@ -469,11 +474,12 @@ hipError_t launch_split(const int64_t *off, const int32_t *cols, int64_t n, cons
                         int32_t *parent, int32_t *out, const int32_t *list,
                         const int64_t *tier_count_host, const int64_t *tier_start_host,
                         const int32_t *orig, int32_t *minorig, int64_t n_total, int32_t *rep,
-                        unsigned long long *cp, const TierConfig &cfg, hipStream_t s) {
+                        unsigned long long *cp, const TierConfig &cfg, hipStream_t s, const int32_t *gid,
+                        const uint8_t *sel) {
   constexpr int kCap = 256 * 16;
   if (n > 0) {
     split_init<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
-    split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n);
+    split_link_first<<<grid_cap(n, 256, kCap), 256, 0, s>>>(off, cols, C, parent, n, gid, sel);
     split_flatten<<<grid_cap(n, 256, kCap), 256, 0, s>>>(parent, n);
     split_rep<<<grid_cap(n, 256, kCap), 256, 0, s>>>(C, parent, n, rep);
     split_pack<<<grid_cap(n, 256, kCap), 256, 0, s>>>(C, parent, n, cp);
