@@ -434,6 +434,12 @@ def roofline_from_stats(stats, weighted, steps, wname, n):
             "algorithmic_bytes_per_launch": bytes_total // max(launches, 1)}
 
 
+# The continuous server's session for the batch of 4,096 graphs: room for
+# about a quarter of the batch at once (64 Mi vertices, 1.6 G entries), four
+# sweeps per step.
+SESSION_CAP = (64 << 20, 1600 << 20, 4096)
+SESSION_SWEEPS = 4
+
 _POOL_BATCH = None
 
 
@@ -589,11 +595,11 @@ def batched_gpu(b, args, tiers_mode):
                             payload=(off[vb[k]:vb[k + 1] + 1], cols, None)) for k in range(G)]
             srv = Server(ex, slots=2, budget_bytes=64 << 30)
         else:
-            ex = SessionBackend(max_vertices=16 << 20, max_entries=400 << 20, max_graphs=4096, max_iters=mi,
-                                tolerance=tol)
+            ex = SessionBackend(max_vertices=SESSION_CAP[0], max_entries=SESSION_CAP[1], max_graphs=SESSION_CAP[2],
+                                max_iters=mi, tolerance=tol)
             reqs = [Request(rid=k, arrival=float(times[k]), n=int(vb[k + 1] - vb[k]), nnz=int(eb[k + 1] - eb[k]),
                             payload=(loc_off[k], loc_cols[k], None)) for k in range(G)]
-            srv = ContinuousServer(ex, sweeps_per_step=2)
+            srv = ContinuousServer(ex, sweeps_per_step=SESSION_SWEEPS)
         torch.cuda.synchronize()
         srv.serve(reqs)
         if mode != "plain":
@@ -603,7 +609,9 @@ def batched_gpu(b, args, tiers_mode):
                                                 for r in reqs)
         if mode == "continuous":
             summ["steps"] = srv.steps
-            summ["session_bytes"] = gsl.Session.device_bytes(16 << 20, 400 << 20, 4096)
+            summ["session_bytes"] = gsl.Session.device_bytes(*SESSION_CAP)
+            summ["session_capacity"] = {"vertices": SESSION_CAP[0], "entries": SESSION_CAP[1],
+                                        "graphs": SESSION_CAP[2], "sweeps_per_step": SESSION_SWEEPS}
         key = "%s_%d" % (mode, int(rate))
         served[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
         log("served %s: %s" % (key, served[key]))

@@ -280,9 +280,10 @@ class ContinuousServer:
     admitted, ticket -1 when nothing has to run; EAGAIN: no room now, and the
     later requests of the call were not tried; anything else: rejected),
     backend.step(sweeps) returns [(ticket, sweeps_run)] of finished graphs or
-    raises, backend.reset() empties the session after a failed step.  Plain
-    Python, tested on the CPU with a fake backend; SessionBackend is the GPU
-    one."""
+    raises, backend.reset() empties the session after a failed step, and
+    backend.room() (optional) gives the free (vertices, entries, graphs).
+    Plain Python, tested on the CPU with a fake backend; SessionBackend is the
+    GPU one."""
 
     EAGAIN = -5
 
@@ -303,9 +304,14 @@ class ContinuousServer:
         suspect (it shared a failed step) runs only in an empty session and
         keeps the session to itself."""
         admitted = 0
+        room = getattr(self.backend, "room", None)
         while queue:
             if any(r.rid in suspects for r in by_ticket.values()):
                 break
+            # as many as the session's free capacity can hold (the first is
+            # always tried: it may be rejected outright), so a long queue does
+            # not cost a table of max_admit graphs every step
+            fv, fe, fg = room() if room else (float("inf"),) * 3
             head = []
             for k in range(min(len(queue), self.max_admit)):
                 r = queue[k]
@@ -313,7 +319,10 @@ class ContinuousServer:
                     if not head and not by_ticket:
                         head = [r]
                     break
+                if head and (r.n > fv or r.nnz > fe or fg < 1):
+                    break
                 head.append(r)
+                fv, fe, fg = fv - r.n, fe - r.nnz, fg - 1
             if not head:
                 break
             res = self.backend.add(head)
@@ -420,6 +429,11 @@ class SessionBackend:
 
     def live(self) -> int:
         return self.session.info()["live_graphs"]
+
+    def room(self):
+        """Free vertices, entries and graph slots of the session."""
+        i = self.session.info()
+        return i["free_vertices"], i["free_entries"], self.session.max_graphs - i["live_graphs"]
 
     def reset(self):
         """A new, empty session in place of one whose step failed."""

@@ -216,11 +216,13 @@ class FakeSession:
         self.next = 0
         self.steps = []         # sets of resident request ids, per step
         self.resets = 0
+        self.add_calls = []     # graphs offered per add call
 
     def _used(self):
         return (sum(r.n for r, *_ in self.live.values()), sum(r.nnz for r, *_ in self.live.values()))
 
     def add(self, reqs):
+        self.add_calls.append(len(reqs))
         out = []
         for r in reqs:
             if r.n > self.cap_v or r.nnz > self.cap_e:
@@ -262,6 +264,10 @@ class FakeSession:
         self.live.clear()
         self.resets += 1
 
+    def room(self):
+        v, e = self._used()
+        return self.cap_v - v, self.cap_e - e, self.cap_g - len(self.live)
+
     def live_count(self):
         return len(self.live)
 
@@ -294,6 +300,9 @@ def test_continuous_server_capacity_retry_and_rejection():
     assert all(sum(by_rid[i].n for i in s) <= 1000 for s in fs.steps)
     # later requests waited for earlier ones to leave
     assert min(r.t_admit for r in reqs[-5:]) > 0
+    # the server offers only what the free capacity can hold (three graphs of
+    # 300-400 vertices at most here), not a long slice of the queue each step
+    assert max(fs.add_calls) <= 3
 
 
 def test_continuous_server_cancel():
