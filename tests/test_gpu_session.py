@@ -162,3 +162,28 @@ def test_session_capacity_and_bytes(gsl):
         assert info["device_bytes"] == b and info["live_graphs"] == 0
     with pytest.raises(gsl.GslError):
         gsl.Session(0, 10, 1)
+
+
+def test_hub_graphs_in_a_session(gsl):
+    """Graphs with hub rows (degree above 4,096) joining a running session:
+    the hub tier's chunk sums, staging and merge run over the arena's hubs --
+    with the default limits, and with 1 MiB staging batches and 8 merge claims
+    per pass, so the several-batch and sub-pass branches run too -- and every
+    graph still gets the oracle's labels and sweep count."""
+    graphs = [graphgen.rmat(16, 32, 7), graphgen.rmat(14, 32, 1), graphgen.rmat(15, 16, 4)]
+    b = workloads.make(5, small=True)
+    graphs += [b.subgraph(k) for k in range(6)]
+    assert sum(int((np.diff(g.offsets) > 4096).sum()) for g in graphs) >= 10
+    refs = [oracle.lpa(g, 20, 0.05) for g in graphs]
+    order = list(np.random.default_rng(5).permutation(len(graphs)))
+    for limits in ((0, 0), (1 << 20, 8)):
+        gsl.gsl_set_hub_limits(*limits)
+        try:
+            with gsl.Session(400_000, 12_000_000, 16) as sess:
+                res = _run(gsl, sess, order, graphs, admit_every=1, sweeps=2)
+        finally:
+            gsl.gsl_set_hub_limits(0, 0)
+        for i, g in enumerate(graphs):
+            lab, it = res[i]
+            np.testing.assert_array_equal(lab, refs[i].labels, err_msg="graph %d limits %s" % (i, limits))
+            assert it == refs[i].iterations, (i, limits)
