@@ -34,6 +34,7 @@ constexpr int kTabSlots = 1 << kTabLog2;
 constexpr int kMaxParts = kHubMaxParts;
 constexpr int kPartSize = 2048;               // expected distinct labels per partition
 constexpr int kMergeBlock = 256;
+constexpr int kHubFoldRounds = 1;  // label fold rounds per wave before the inserts (as in the tiers)
 // Claims before a merge pass gives up and the partition is split into
 // sub-passes: at most kHubMergeCapMax, so that a free slot always remains
 // (up to kMergeBlock threads may pass the check at once); a smaller cap can
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kHubBlock) void hub_insert(SweepArgs a, HubArgs h) 
   unsigned long long rs = 0;
 #pragma unroll
   for (int q = 0; q < kHubK; ++q) rs += wt[q];
-  wave_fold_labels<kHubK>(lab, wt, 4);  // the whole chunk belongs to one hub
+  wave_fold_labels<kHubK>(lab, wt, kHubFoldRounds);  // the whole chunk belongs to one hub
   __syncthreads();  // table and histogram initialised
   int slot[kHubK];
 #pragma unroll
@@ -227,20 +228,24 @@ __global__ __launch_bounds__(kMergeBlock) void hub_merge(SweepArgs a, HubArgs h)
   const int64_t gp = h.L.part_start[h.k0] + blockIdx.x;
   const int64_t k = h.L.part_owner[gp];
   // The partition count is sized for rows whose labels are all distinct.
-  // When the hub's (label, sum) records of all partitions fit one table --
-  // usual once the labels have merged -- workgroup 0 merges them all and the
-  // others return.  hub_insert counted the records of every chunk.
+  // Workgroup p merges the group of partitions [p * g, (p + 1) * g): g is as
+  // many as the hub's records (hub_insert counted them) fill three quarters
+  // of a table on average -- all of them once the labels have merged -- and
+  // workgroups past the last group return.  A group that still overflows
+  // the table falls back to hashed sub-passes below.
   const unsigned long long records = h.L.records[k];
   const int p = (int)(gp - h.L.part_start[k]);
-  const bool whole = records <= (unsigned long long)h.merge_cap;  // uniform
-  if (whole && p > 0) return;
   const int32_t v = h.hubs ? h.hubs[k] : (int32_t)k;
-  if (!sweep_takes(a, sv, v)) return;
   const int P = hub_parts(a.off[v + 1] - a.off[v]);
+  const unsigned long long fit = (unsigned long long)h.merge_cap * 3 / 4 * (unsigned long long)P;
+  const int g = records <= (unsigned long long)h.merge_cap ? P
+                : (int)(fit / records < 1 ? 1 : (fit / records > (unsigned long long)P ? P : fit / records));
+  if ((int64_t)p * g >= P) return;  // uniform
+  if (!sweep_takes(a, sv, v)) return;
   const int64_t c0 = h.L.chunk_start[k], nc = h.L.chunk_start[k + 1] - c0;
   const int32_t *gh = h.hist + (h.L.hist_start[k] - h.L.hist_start[h.k0]);
   const unsigned long long *stage = h.staging + (c0 - h.L.chunk_start[h.k0]) * kHubChunk;
-  const int p_lo = whole ? 0 : p, p_hi = whole ? P : p + 1;  // partitions merged here
+  const int p_lo = p * g, p_hi = p_lo + g < P ? p_lo + g : P;  // partitions merged here
   unsigned long long best = 0;
   for (uint32_t R = 1;; R <<= 1) {
     bool ok = true;

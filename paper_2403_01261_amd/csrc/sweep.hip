@@ -25,8 +25,11 @@ namespace gsl {
 
 namespace {
 
-// Repeated labels folded per wave before the LDS inserts (wave_fold_labels).
-constexpr int kFoldRounds = 4;
+// Repeated labels folded per wave before the LDS inserts (wave_fold_labels):
+// one round, for the wave's most common label.  Measured on rmat-s26 /
+// rmat-s22: no fold 207 / 9.33 ms, one round 196 / 8.71 ms, two 196 / 8.82,
+// four 198 / 8.89, eight 197.5 ms.
+constexpr int kFoldRounds = 1;
 
 __device__ __forceinline__ void record_change(const SweepArgs &a, int32_t v, uint32_t cstar,
                                               LocalCounts &lc) {
