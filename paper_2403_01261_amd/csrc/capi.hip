@@ -1473,12 +1473,23 @@ int session_add(gsl_session &S, int64_t G, const gsl_graph *graphs, int64_t *tic
     tickets[g] = -1;
     status[g] = GSL_OK;
   }
-  // entry counts (and decreasing offsets) of every graph on the device
-  HIP_TRY(hipMemcpyAsync(s.gdesc, graphs, (size_t)G * sizeof(gsl_graph), hipMemcpyHostToDevice, st));
+  // entry counts (and decreasing offsets) of every graph on the device; a
+  // descriptor the host can already reject (negative or oversized n, NULL
+  // offsets or output) goes to the device with n = 0, so nothing reads it
+  std::vector<gsl_graph> desc(graphs, graphs + G);
+  std::vector<uint8_t> rejected((size_t)G, 0);
+  for (int64_t g = 0; g < G; ++g) {
+    const gsl_graph &x = graphs[g];
+    if (x.n < 0 || x.n > S.cap_v || (x.n > 0 && (!x.offsets || !x.labels_out))) {
+      rejected[(size_t)g] = 1;
+      desc[(size_t)g].n = 0;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(s.gdesc, desc.data(), (size_t)G * sizeof(gsl_graph), hipMemcpyHostToDevice, st));
   HIP_TRY(gsl::launch_graph_entries(s.gdesc, G, s.gcnt, st));
   std::vector<int64_t> cnt((size_t)G);
   HIP_TRY(hipMemcpyAsync(cnt.data(), s.gcnt, (size_t)G * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipStreamSynchronize(st));  // also keeps desc alive until the copy is done
   // admit in order while the arena has room (compacting once if that makes room)
   std::vector<int64_t> take;
   int64_t need_v = 0, need_e = 0;
@@ -1486,8 +1497,7 @@ int session_add(gsl_session &S, int64_t G, const gsl_graph *graphs, int64_t *tic
   for (int64_t g = 0; g < G; ++g) {
     const gsl_graph &x = graphs[g];
     const int64_t c = cnt[(size_t)g];
-    if (x.n < 0 || c < 0 || (c > 0 && !x.cols) || (x.n > 0 && (!x.offsets || !x.labels_out)) ||
-        x.n > S.cap_v || c > S.cap_e || (x.weights && !S.weighted)) {
+    if (rejected[(size_t)g] || c < 0 || (c > 0 && !x.cols) || c > S.cap_e || (x.weights && !S.weighted)) {
       status[g] = GSL_EINVAL;
       continue;
     }

@@ -187,3 +187,30 @@ def test_hub_graphs_in_a_session(gsl):
             lab, it = res[i]
             np.testing.assert_array_equal(lab, refs[i].labels, err_msg="graph %d limits %s" % (i, limits))
             assert it == refs[i].iterations, (i, limits)
+
+
+def test_descriptors_rejected_on_the_host(gsl):
+    """A descriptor with NULL offsets, or a negative vertex count, is rejected
+    (GSL_EINVAL) before anything on the device reads it; the good graph of
+    the same call runs as usual."""
+    import ctypes
+    lib = gsl.load()
+    good = workloads.make(1)
+    off, cols, _ = to_device(good)
+    out = torch.empty(good.n, dtype=torch.int32, device="cuda")
+    spare = torch.empty(8, dtype=torch.int32, device="cuda")
+    tab = (gsl._Graph * 3)()
+    tab[0].offsets, tab[0].cols, tab[0].labels_out, tab[0].n = None, None, spare.data_ptr(), 5
+    tab[1].offsets, tab[1].cols, tab[1].labels_out, tab[1].n = off.data_ptr(), cols.data_ptr(), out.data_ptr(), good.n
+    tab[2].offsets, tab[2].cols, tab[2].labels_out, tab[2].n = off.data_ptr(), cols.data_ptr(), spare.data_ptr(), -3
+    tickets = (ctypes.c_int64 * 3)()
+    status = (ctypes.c_int32 * 3)()
+    with gsl.Session(100_000, 1_000_000, 8) as sess:
+        sess.stream.wait_stream(torch.cuda.current_stream())
+        assert lib.gsl_session_add(sess._h, 3, tab, tickets, status) == gsl.GSL_OK
+        assert list(status) == [gsl.GSL_EINVAL, gsl.GSL_OK, gsl.GSL_EINVAL]
+        assert tickets[0] == -1 and tickets[2] == -1 and tickets[1] >= 0
+        done = {}
+        while tickets[1] not in done:
+            done.update(dict(sess.step(4)))
+        np.testing.assert_array_equal(out.cpu().numpy(), oracle.lpa(good).labels)
