@@ -26,9 +26,9 @@ namespace gsl {
 namespace {
 
 // Repeated labels folded per wave before the LDS inserts (wave_fold_labels):
-// one round, for the wave's most common label.  Measured on rmat-s26 /
-// rmat-s22: no fold 207 / 9.33 ms, one round 196 / 8.71 ms, two 196 / 8.82,
-// four 198 / 8.89, eight 197.5 ms.
+// a single pass, for the wave's most common label.  Measured on rmat-s26 /
+// rmat-s22 (ms per call): no fold 207 / 9.33, a single pass 196 / 8.71, two
+// passes 196 / 8.82, four 198 / 8.89, eight 197.5 on rmat-s26.
 constexpr int kFoldRounds = 1;
 
 __device__ __forceinline__ void record_change(const SweepArgs &a, int32_t v, uint32_t cstar,
