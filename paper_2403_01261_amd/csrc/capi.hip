@@ -296,6 +296,12 @@ hipError_t dmalloc(T **p, int64_t count) {
 // kChunkSweeps sweeps and are launched chunk by chunk (see lpa_impl).
 constexpr int64_t kChunkMinEntries = int64_t(1) << 23;
 constexpr int kChunkSweeps = 2;
+// Most kernel launches one captured loop graph holds.  Every hub batch adds
+// four launches to a sweep, so many hubs over a small staging area make wide
+// sweeps: a 20-sweep graph of about 2 * 10^5 chained launches has ended the
+// process inside the call where one of 4 * 10^4 ran.  Wider loops capture
+// fewer sweeps per graph, and a sweep wider than this is launched directly.
+constexpr int64_t kMaxGraphLaunches = 1 << 14;
 
 int ensure_scratch(Scratch &s, int64_t n, int32_t max_iters) {
   const int64_t need = (int64_t)sizeof(Counters) + 4 * (int64_t)sizeof(uint64_t) * (max_iters > 0 ? max_iters : 1);
@@ -804,13 +810,17 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     return GSL_OK;
   };
 
+  // launches of one sweep, at most: one per tier, four per hub batch, the
+  // closing kernels
+  const int64_t sweep_launches = gsl::kNumTiers + 4 * (int64_t)s.hub_batches.size() + 8;
   if (timed || max_iters == 0) {
     for (int k = 0; k < max_iters; ++k)
       if ((rc = enqueue_sweep(k))) return rc;
-  } else if (s.fixed) {
+  } else if (s.fixed || sweep_launches > kMaxGraphLaunches) {
     // Without allocation there is no loop graph (instantiating one
-    // allocates): the sweeps are enqueued directly, and the loop state is
-    // read back after every kChunkSweeps sweeps to stop early.
+    // allocates), nor for a sweep too wide for one: the sweeps are enqueued
+    // directly, and the loop state is read back after every kChunkSweeps
+    // sweeps to stop early.
     for (int k = 0; k < max_iters; ++k) {
       if ((rc = enqueue_sweep(k))) return rc;
       if ((k + 1) % kChunkSweeps == 0 && k + 1 < max_iters) {
@@ -825,13 +835,15 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     // was built from stays the same.  Small graphs: all max_iters sweeps in
     // one graph (a sweep enqueued after convergence costs only empty
     // launches, a few microseconds each).  Large graphs: a graph of
-    // kChunkSweeps sweeps launched repeatedly; the host queues chunk c before
+    // kChunkSweeps sweeps (wide sweeps: as many as kMaxGraphLaunches
+    // allows) launched repeatedly; the host queues chunk c before
     // it waits for the stop flag after chunk c - 1, so the device never waits
     // for the host and at most one chunk runs after the loop has stopped
     // (every sweep kernel reads the same device loop state, so the chunks
     // are identical).
-    const bool chunked = nnz >= kChunkMinEntries && max_iters > kChunkSweeps;
-    const int len = chunked ? kChunkSweeps : max_iters;
+    int len = nnz >= kChunkMinEntries && max_iters > kChunkSweeps ? kChunkSweeps : max_iters;
+    if ((int64_t)len * sweep_launches > kMaxGraphLaunches) len = (int)(kMaxGraphLaunches / sweep_launches);
+    const bool chunked = len < max_iters;
     std::vector<uint64_t> key = {(uint64_t)len, (uint64_t)n, (uint64_t)n_sweep, (uint64_t)nnz, (uint64_t)max_iters,
                                  (uint64_t)o.prune, (uint64_t)renumber, (uint64_t)a.inplace, (uint64_t)f32,
                                  (uint64_t)(uintptr_t)s.fkeys, (uint64_t)(uintptr_t)s.fsums,

@@ -5,6 +5,8 @@ Eq. 2 sweeps, Alg. 2 split).
   - hub rows summed over several staging batches (every batch after the
     first starts at a hub k0 > 0) and partitions merged in hashed
     sub-passes, forced on small graphs with gsl_set_hub_limits;
+  - sweeps of thousands of hub batches, which the loop graph holds one
+    sweep at a time or not at all;
   - the cached loop graph is rebuilt when only the hub chunk totals change
     (two graphs with equal n, nnz, tier counts and hub count, at the same
     device addresses);
@@ -106,6 +108,23 @@ def test_hub_limits_on_rmat_with_low_hub_bound(gsl):
         gsl.gsl_set_tiers(LOW_HUB_LEVELS)
         gsl.gsl_set_hub_limits(5 * 2048 * 8, 40)
         check(gsl, g, tag="rmat small, hubs > 256")
+    finally:
+        gsl.gsl_set_tiers(None)
+        gsl.gsl_set_hub_limits(0, 0)
+
+
+@pytest.mark.parametrize("hub_above", [256, 128])
+def test_wide_hub_sweeps(gsl, hub_above):
+    """One staging chunk per batch over R-MAT's 2,517 rows above degree 256
+    (a sweep of about 10^4 launches: loop graphs of one sweep each) or its
+    6,834 rows above 128 (about 2.7 * 10^4: no loop graph, sweeps launched
+    directly)."""
+    g = workloads.make(4, small=True)
+    levels = LOW_HUB_LEVELS if hub_above == 256 else LOW_HUB_LEVELS[:4] + [(128, 8)] * 3
+    try:
+        gsl.gsl_set_tiers(levels)
+        gsl.gsl_set_hub_limits(2048 * 8, 0)
+        check(gsl, g, tag="rmat small, hubs > %d, one chunk per batch" % hub_above)
     finally:
         gsl.gsl_set_tiers(None)
         gsl.gsl_set_hub_limits(0, 0)
