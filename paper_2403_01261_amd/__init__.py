@@ -559,13 +559,15 @@ def gsl_tier_variants():
                     "per_lane": info.per_lane, "capacity": info.capacity})
 
 
-def variant_kernel_name(v: dict, weighted: bool = False, n: int = 0) -> str:
+def variant_kernel_name(v: dict, weighted: bool = False, n: int = 0, aligned: bool = True) -> str:
     """The sweep kernel's name as profilers print it (template arguments;
     the thread variants have weighted and unit-weight kernels, each with
-    32-bit gather offsets for fewer than 2^30 vertices or 64-bit ones)."""
+    32-bit gather offsets for fewer than 2^30 vertices or 64-bit ones, and
+    16-byte row loads when the column and weight arrays are 16-byte aligned,
+    as the library's own copies always are)."""
     if v["group"] == 1:
-        return "sweep_thread<%d, %s, %s>" % (v["per_lane"], "true" if weighted else "false",
-                                             "true" if n < (1 << 30) else "false")
+        t = lambda x: "true" if x else "false"  # noqa: E731
+        return "sweep_thread<%d, %s, %s, %s>" % (v["per_lane"], t(weighted), t(n < (1 << 30)), t(aligned))
     return "sweep_lds<%d, %d, %d, %d>" % (v["group"], v["table_log2"], v["block"], v["per_lane"])
 
 

@@ -18,6 +18,8 @@
 // Weights are summed exactly in 32-bit integers; every sweep checks that no
 // row's total weight reaches 2^32 and raises `overflow` otherwise (such a
 // row records no change, so no label outside [0, n) ever reaches C).
+#include <utility>
+
 #include "device_common.h"
 #include "gsl_internal.h"
 
@@ -89,7 +91,65 @@ __device__ __forceinline__ uint32_t gather_label(const int32_t *__restrict__ C, 
     return (uint32_t)C[c];
 }
 
-template <int D, bool W, bool O32>
+// Row entries [b, b + d) of a 4-byte array into r[0..D), `fill` beyond d.
+// V4: 16-byte loads of the aligned words that cover the row -- at most
+// D / 4 + 1 loads instead of D, vector memory instructions being what the
+// thread-per-vertex sweep waits on -- then shifted into place in registers.
+// Only words that hold an entry of the row are loaded, and an aligned 16-byte
+// word lies within one page (the page of that entry), so no load reaches
+// unmapped memory.  V4 needs a 16-byte aligned array.  Register indices are
+// template constants (index sequences rather than loops), so the words stay
+// in registers.
+template <int... Q>
+__device__ __forceinline__ void load_words(const uint4 *__restrict__ p, int lim, uint32_t fill, uint32_t *t,
+                                           std::integer_sequence<int, Q...>) {
+  ((t[4 * Q] = fill, t[4 * Q + 1] = fill, t[4 * Q + 2] = fill, t[4 * Q + 3] = fill), ...);
+  ([&] {
+    if (4 * Q < lim) {
+      const uint4 v = p[Q];
+      t[4 * Q] = v.x;
+      t[4 * Q + 1] = v.y;
+      t[4 * Q + 2] = v.z;
+      t[4 * Q + 3] = v.w;
+    }
+  }(), ...);
+}
+
+// Word K + sh of t (sh in 0..3).  The empty asm hands the selects plain
+// register values: a select between two array elements would otherwise
+// become a load through a selected address, which keeps the array in
+// scratch memory.
+template <int K>
+__device__ __forceinline__ uint32_t shifted_word(const uint32_t *t, int sh, int d, uint32_t fill) {
+  uint32_t c0 = t[K], c1 = t[K + 1], c2 = t[K + 2], c3 = t[K + 3];
+  asm("" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3));
+  const uint32_t lo = (sh & 1) ? c1 : c0, hi = (sh & 1) ? c3 : c2;
+  return K < d ? ((sh & 2) ? hi : lo) : fill;
+}
+
+template <int... K>
+__device__ __forceinline__ void shift_words(const uint32_t *t, int sh, int d, uint32_t fill, uint32_t *r,
+                                            std::integer_sequence<int, K...>) {
+  ((r[K] = shifted_word<K>(t, sh, d, fill)), ...);
+}
+
+template <int D, bool V4>
+__device__ __forceinline__ void load_row(const uint32_t *__restrict__ x, int64_t b, int d, uint32_t fill,
+                                         uint32_t (&r)[D]) {
+  if constexpr (!V4) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) r[k] = k < d ? x[b + k] : fill;
+  } else {
+    constexpr int Q = D / 4 + 1;
+    const int64_t b4 = b & ~int64_t(3);
+    const int sh = (int)(b - b4);
+    uint32_t t[4 * Q];
+    load_words(reinterpret_cast<const uint4 *>(x + b4), sh + d, fill, t, std::make_integer_sequence<int, Q>{});
+    shift_words(t, sh, d, fill, r, std::make_integer_sequence<int, D>{});
+  }
+}
+
+template <int D, bool W, bool O32, bool V4>
 __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *__restrict__ list,
                                                     int64_t first, int64_t count) {
   __shared__ unsigned long long red[256 / kWave];
@@ -113,18 +173,15 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
     const uint8_t *dp = a.gdone ? a.gdone + g : &kZeroU8;
     if (*dp) continue;
     uint32_t lab[D], w[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) lab[k] = k < d ? (uint32_t)a.cols[b + k] : (uint32_t)v;
+    load_row<D, V4>(reinterpret_cast<const uint32_t *>(a.cols), b, d, (uint32_t)v, lab);
 #pragma unroll
     for (int k = 0; k < D; ++k) lab[k] = lab[k] != (uint32_t)v ? gather_label<O32>(a.C, (int32_t)lab[k]) : kNoLabel;
     unsigned long long rowsum = (unsigned long long)d;
     if constexpr (W) {
       rowsum = 0;
+      load_row<D, V4>(a.w, b, d, 0u, w);
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        w[k] = k < d ? a.w[b + k] : 0u;
-        rowsum += w[k];
-      }
+      for (int k = 0; k < D; ++k) rowsum += w[k];
     }
     sort_by_label<D, W>(lab, w);
     unsigned long long best = 0;
@@ -157,21 +214,32 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
   flush_counts(a, lc, red);
 }
 
-template <int D>
-void launch_thread(const SweepArgs &a, const int32_t *list, int64_t first, int64_t count, int grid,
-                   hipStream_t s) {
+template <int D, bool V4>
+void launch_thread_rows(const SweepArgs &a, const int32_t *list, int64_t first, int64_t count, int grid,
+                        hipStream_t s) {
   const bool o32 = a.n < (int64_t(1) << 30);
   if (a.w) {
     if (o32)
-      sweep_thread<D, true, true><<<grid, 256, 0, s>>>(a, list, first, count);
+      sweep_thread<D, true, true, V4><<<grid, 256, 0, s>>>(a, list, first, count);
     else
-      sweep_thread<D, true, false><<<grid, 256, 0, s>>>(a, list, first, count);
+      sweep_thread<D, true, false, V4><<<grid, 256, 0, s>>>(a, list, first, count);
   } else {
     if (o32)
-      sweep_thread<D, false, true><<<grid, 256, 0, s>>>(a, list, first, count);
+      sweep_thread<D, false, true, V4><<<grid, 256, 0, s>>>(a, list, first, count);
     else
-      sweep_thread<D, false, false><<<grid, 256, 0, s>>>(a, list, first, count);
+      sweep_thread<D, false, false, V4><<<grid, 256, 0, s>>>(a, list, first, count);
   }
+}
+
+// 16-byte row loads when the column (and weight) arrays are 16-byte aligned
+// (the library's own copies always are; a caller's array may not be).
+template <int D>
+void launch_thread(const SweepArgs &a, const int32_t *list, int64_t first, int64_t count, int grid,
+                   hipStream_t s) {
+  if (((uintptr_t)a.cols & 15) == 0 && ((uintptr_t)a.w & 15) == 0)
+    launch_thread_rows<D, true>(a, list, first, count, grid, s);
+  else
+    launch_thread_rows<D, false>(a, list, first, count, grid, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -143,6 +143,42 @@ def test_unit_weights_null_equals_ones(gsl):
     np.testing.assert_array_equal(a, b)
 
 
+THREAD_LEVELS = [(8, 0), (16, 15), (32, 16), (64, 6), (128, 8), (512, 9), (4096, 13)]
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2, 3])
+def test_row_loads_at_any_alignment(gsl, shift):
+    """The thread-per-vertex sweeps load a row 16 bytes at a time when the
+    column and weight arrays are 16-byte aligned, 4 bytes at a time
+    otherwise.  Arrays that start 0-3 entries into a larger buffer take both
+    paths (original layout: the sweep reads the caller's arrays), with rows of
+    degree 1-64 starting at every offset within a 16-byte word, through the
+    thread kernels for rows of up to 8, 16 and 32 entries; unit and integer
+    weights.  Every case gives the oracle's labels and sweep counts."""
+    graphs = [graphgen.planted(6000, 60, p, 3000, 17 + k, wmin=1, wmax=wmax)
+              for k, (p, wmax) in enumerate(((0.1, 0), (0.3, 0), (0.1, 9), (0.3, 9)))]
+
+    def at_shift(x):
+        if x is None:
+            return None
+        buf = torch.zeros(x.numel() + 8, dtype=x.dtype, device=x.device)
+        buf[shift:shift + x.numel()] = x
+        return buf[shift:shift + x.numel()]
+
+    try:
+        for levels in (None, THREAD_LEVELS):
+            gsl.gsl_set_tiers(levels)
+            for g in graphs:
+                r = oracle.lpa(g, 20, 0.05)
+                off, cols, w = to_device(g)
+                lab, st = gsl.gsl_lpa_ex(off, at_shift(cols), at_shift(w), 20, 0.05, layout="original")
+                assert st["iterations"] == r.iterations, (shift, levels, g.name)
+                np.testing.assert_array_equal(lab.cpu().numpy(), r.labels,
+                                              err_msg="shift %d levels %s %s" % (shift, levels, g.name))
+    finally:
+        gsl.gsl_set_tiers(None)
+
+
 def test_deterministic_across_runs(gsl):
     g = workloads.make(2, small=True)
     first, _ = run_gpu(gsl, g)
