@@ -154,9 +154,12 @@ def test_row_loads_at_any_alignment(gsl, shift):
     paths (original layout: the sweep reads the caller's arrays), with rows of
     degree 1-64 starting at every offset within a 16-byte word, through the
     thread kernels for rows of up to 8, 16 and 32 entries; unit and integer
-    weights.  Every case gives the oracle's labels and sweep counts."""
-    graphs = [graphgen.planted(6000, 60, p, 3000, 17 + k, wmin=1, wmax=wmax)
-              for k, (p, wmax) in enumerate(((0.1, 0), (0.3, 0), (0.1, 9), (0.3, 9)))]
+    weights.  The labels go to an output at the same offset, so the sweeps'
+    label copy takes its 16-byte and 4-byte paths too, with vertex counts
+    that do and do not fill the last group of four.  Every case gives the
+    oracle's labels and sweep counts."""
+    graphs = [graphgen.planted(n, 60, p, 3000, 17 + k, wmin=1, wmax=wmax)
+              for k, (n, p, wmax) in enumerate(((6000, 0.1, 0), (6002, 0.3, 0), (6001, 0.1, 9), (6000, 0.3, 9)))]
 
     def at_shift(x):
         if x is None:
@@ -171,7 +174,9 @@ def test_row_loads_at_any_alignment(gsl, shift):
             for g in graphs:
                 r = oracle.lpa(g, 20, 0.05)
                 off, cols, w = to_device(g)
-                lab, st = gsl.gsl_lpa_ex(off, at_shift(cols), at_shift(w), 20, 0.05, layout="original")
+                out = at_shift(torch.zeros(g.n, dtype=torch.int32, device=off.device))
+                lab, st = gsl.gsl_lpa_ex(off, at_shift(cols), at_shift(w), 20, 0.05, out=out, layout="original")
+                assert lab.data_ptr() == out.data_ptr()
                 assert st["iterations"] == r.iterations, (shift, levels, g.name)
                 np.testing.assert_array_equal(lab.cpu().numpy(), r.labels,
                                               err_msg="shift %d levels %s %s" % (shift, levels, g.name))
