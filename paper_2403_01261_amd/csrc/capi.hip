@@ -742,6 +742,11 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
   a.gdone = batch ? s.gdone : nullptr;
   a.inplace = o.async_sweeps ? 1 : 0;
   a.n = n;
+  // Sparse sweeps walk a frontier of the active vertices per tier, built at
+  // the start of the sweep into the split's parent array (unused until the
+  // split) with the counts in the counters block; fp32 weights keep the scan.
+  const bool frontier = o.prune && !f32;
+  a.flist = frontier ? s.parent : nullptr;
   const gsl::HubLayout L{s.hub_chunk_start, s.hub_part_start, s.hub_hist_start, s.hub_chunk_owner,
                          s.hub_part_owner, s.hub_records};
 
@@ -767,11 +772,14 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     }
     gsl::TierGrids grids;
     for (int t = 0; t < gsl::kNumTiers; ++t) grids.g[t] = 0;
+    if (frontier)
+      HIP_TRY(gsl::launch_frontier(a, n_sweep, cfg, plan.tier_start, s.parent, s.ctr->fcount, cur));
     for (int t = 1; t < gsl::kNumTiers; ++t) {
       const int64_t cnt = plan.tier_count[t];
       if (cnt <= 0) continue;
       a.tier = &s.ctr->tier_stats[t][0];
       a.part = s.tier_part + (size_t)t * gsl::kMaxTierGrid * gsl::kCountFields;
+      a.fcount = frontier && t != gsl::kHubTier ? &s.ctr->fcount[t] : nullptr;
       if (timed) {
         launches.push_back({t, k, 0, nev});
         if ((rc = rec(nev++))) return rc;
@@ -805,7 +813,7 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     HIP_TRY(gsl::launch_apply(a, C, n_sweep, batch ? s.gdn : nullptr, cur));
     if (batch)
       HIP_TRY(gsl::launch_graph_end(s.ctrl, s.gdn, s.glimit, s.giters, s.gdone, batch->graphs, cur));
-    HIP_TRY(gsl::launch_sweep_end(s.ctrl, dn_arr, mk_arr, a.overflow, cur));
+    HIP_TRY(gsl::launch_sweep_end(s.ctrl, dn_arr, mk_arr, a.overflow, cur, frontier ? s.ctr->fcount : nullptr));
     if (timed && (rc = rec(nev++))) return rc;
     return GSL_OK;
   };

@@ -73,6 +73,15 @@ struct TierBounds {
   int64_t b[kNumTiers];
 };
 
+// Tier of a row of d entries: 0 empty, t for the first bound b[t] >= d
+// (t = 1 .. kNumTiers - 2), kNumTiers - 1 (hubs) above the last.
+__host__ __device__ __forceinline__ int tier_of(int64_t d, const TierBounds &tb) {
+  if (d <= 0) return 0;
+  for (int t = 1; t < kNumTiers - 1; ++t)
+    if (d <= tb.b[t]) return t;
+  return kNumTiers - 1;
+}
+
 // Device-side counters; one block of memory zeroed at the start of every call.
 struct Counters {
   int64_t tier_count[16];   // vertices per tier
@@ -87,6 +96,7 @@ struct Counters {
   double q;
   uint64_t pad[3];
   int64_t tier_edges[16];   // row entries per tier
+  int64_t fcount[16];       // sparse sweeps: active vertices of each tier (the frontier)
   // per tier, summed over sweeps: processed, edges, changed, marked
   unsigned long long tier_stats[kNumTiers][4];
   // followed by per-sweep arrays dn[max_iters], processed[], edges[], marked[]
@@ -109,6 +119,8 @@ struct SweepCtrl {
   int64_t n;           // vertices, for the marking heuristic
   int64_t graphs;      // 0: one graph; else graphs of a batch
   int64_t active;      // graphs still running after the last sweep (batch)
+  int32_t front;       // this sweep (when sparse) walks a frontier: the last one changed at most n/16
+  int32_t pad;
 };
 
 // Arguments common to every sweep kernel.
@@ -136,11 +148,16 @@ struct SweepArgs {
   // in-place lpaMove); results then depend on timing.
   int32_t inplace;
   int64_t n;  // vertices (labels C[0..n))
+  // Frontier of a sparse sweep: this tier's taking part vertices are
+  // flist[first + i], i < *fcount (the tier's own range of the list layout).
+  // fcount NULL: the tier list is scanned against the active flags.
+  const int32_t *flist;
+  const int64_t *fcount;
 };
 
 // What a sweep kernel needs from the loop state.
 struct SweepView {
-  int it, dense, mark;
+  int it, dense, mark, front;
   const uint8_t *act;
   uint8_t *nact;
 };
@@ -151,6 +168,7 @@ __device__ __forceinline__ bool sweep_view(const SweepArgs &a, SweepView &v) {
   v.it = c->it;
   v.dense = c->dense;
   v.mark = c->mark;
+  v.front = c->front;
   v.act = (v.it & 1) ? a.act1 : a.act0;
   v.nact = (v.it & 1) ? a.act0 : a.act1;
   return true;
@@ -217,9 +235,18 @@ hipError_t launch_hub_sweep(const SweepArgs &a, const int32_t *hubs, HubLayout L
 // active flags when it was sparse).  Batches (gdn != NULL): also adds each
 // graph's changes to gdn[graph].
 hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, int64_t *gdn, hipStream_t s);
+// Sparse sweeps that follow a sweep with few changes only (the kernel reads
+// the loop state): the frontier of the sweep about to run -- each vertex of
+// [0, n) whose active flag is set, whose row is not empty and not a hub's, and
+// whose graph still runs -- into its tier's range [tier_start[t], +count) of
+// flist, the counts added to fcount[t] (cleared by the sweep_end before).
+// Other sweeps return at once.
+hipError_t launch_frontier(const SweepArgs &a, int64_t n, const TierConfig &cfg, const int64_t *tier_start_h,
+                           int32_t *flist, int64_t *fcount, hipStream_t s);
 // Advances the loop state after a sweep.
 hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsigned long long *marked_sweeps,
-                            const unsigned long long *overflow, hipStream_t s);
+                            const unsigned long long *overflow, hipStream_t s,
+                            int64_t *fcount = nullptr);
 // Loop state before the first sweep; first_flags (NULL unless renumbered)
 // tells whether the renumbering copy already ran sweep 0.
 hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_flags, unsigned long long *dn,

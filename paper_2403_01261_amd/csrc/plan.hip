@@ -17,14 +17,6 @@ namespace {
 
 constexpr int kPlanBlock = 1024;
 
-__device__ __forceinline__ int tier_of(int64_t d, const TierBounds &tb) {
-  if (d <= 0) return 0;
-#pragma unroll
-  for (int t = 1; t < kNumTiers - 1; ++t)
-    if (d <= tb.b[t]) return t;
-  return kNumTiers - 1;
-}
-
 __global__ __launch_bounds__(kPlanBlock) void plan_count(const int64_t *__restrict__ off, int64_t n,
                                                          int64_t *__restrict__ blk_counts,
                                                          Counters *ctr, TierBounds tb) {

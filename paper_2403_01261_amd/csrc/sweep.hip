@@ -217,6 +217,12 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
   SweepView sv;
   if (!sweep_view(a, sv)) return;
   LocalCounts lc;
+  // a sparse sweep with a frontier walks the frontier instead of the tier
+  const bool front = !sv.dense && sv.front && a.fcount;
+  if (front) {
+    list = a.flist;
+    count = *a.fcount;
+  }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx0 < count; idx0 += kAhead * stride) {
     int32_t vv[kAhead];
@@ -227,7 +233,7 @@ __global__ __launch_bounds__(256) void sweep_thread(SweepArgs a, const int32_t *
       vv[k] = idx < count ? (list ? list[first + idx] : (int32_t)(first + idx)) : -1;
     }
 #pragma unroll
-    for (int k = 0; k < kAhead; ++k) take[k] = vv[k] >= 0 && (sv.dense || sv.act[vv[k]]);
+    for (int k = 0; k < kAhead; ++k) take[k] = vv[k] >= 0 && (sv.dense || front || sv.act[vv[k]]);
 #pragma unroll 1
     for (int k = 0; k < kAhead; ++k)
       if (take[k]) thread_vertex<D, W, O32, V4>(a, sv, vv[k], lc);
@@ -299,6 +305,11 @@ __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *_
   const int wid = threadIdx.x / kWave, wl = threadIdx.x % kWave;
   unsigned long long *T = tab + g * S;
   LocalCounts lc;
+  // a sparse sweep with a frontier walks the frontier instead of the tier
+  if (!sv.dense && sv.front && a.fcount) {
+    list = a.flist;
+    count = *a.fcount;
+  }
   for (int64_t w0 = (int64_t)blockIdx.x * win; w0 < count; w0 += (int64_t)gridDim.x * win) {
     // pack the taken vertices of the window with their row bounds (loaded
     // here, all at once, instead of one dependent load per group round)
@@ -492,6 +503,55 @@ __global__ __launch_bounds__(256) void apply_changes(SweepArgs a, int32_t *__res
   }
 }
 
+// Frontier of a sparse sweep (see launch_frontier): one thread per vertex of
+// a 1,024-vertex chunk, ranks within the chunk by ballot per tier, one atomic
+// per tier and chunk.  The grid is capped (chunks in a grid-stride loop), so
+// the launch costs little in the sweeps that do not build one.
+constexpr int kFrontierBlock = 1024;
+constexpr int kFrontierGrid = 1024;
+
+__global__ __launch_bounds__(kFrontierBlock) void frontier_build(SweepArgs a, int64_t n, TierBounds tb,
+                                                                 TierBounds start, int32_t *__restrict__ flist,
+                                                                 int64_t *__restrict__ fcount) {
+  constexpr int W = kFrontierBlock / kWave;
+  __shared__ int wcnt[W][kNumTiers];
+  __shared__ unsigned long long base[kNumTiers];
+  SweepView sv;
+  if (!sweep_view(a, sv) || sv.dense || !sv.front) return;  // uniform
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int64_t c0 = (int64_t)blockIdx.x * kFrontierBlock; c0 < n; c0 += (int64_t)gridDim.x * kFrontierBlock) {
+    const int64_t v = c0 + threadIdx.x;
+    int t = -1;
+    if (v < n && sv.act[v] && !(a.gid && a.gdone[a.gid[v]])) {
+      t = tier_of(a.off[v + 1] - a.off[v], tb);
+      if (t == 0 || t == kNumTiers - 1) t = -1;  // no entries / a hub (the hub kernels read the flags)
+    }
+    int rank = 0;
+#pragma unroll
+    for (int k = 1; k < kNumTiers - 1; ++k) {
+      const unsigned long long m = __ballot(t == k);
+      if (t == k) rank = __popcll(m & below);
+      if (lane == 0) wcnt[wid][k] = __popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x > 0 && threadIdx.x < kNumTiers - 1) {
+      int total = 0;
+      for (int w = 0; w < W; ++w) total += wcnt[w][threadIdx.x];
+      base[threadIdx.x] = total ? atomicAdd(reinterpret_cast<unsigned long long *>(&fcount[threadIdx.x]),
+                                            (unsigned long long)total)
+                                : 0ull;
+    }
+    __syncthreads();
+    if (t >= 0) {
+      int before = 0;
+      for (int w = 0; w < wid; ++w) before += wcnt[w][t];
+      flist[start.b[t] + (int64_t)base[t] + before + rank] = (int32_t)v;
+    }
+    __syncthreads();  // wcnt and base are rewritten by the next chunk
+  }
+}
+
 __global__ void init_labels(int32_t *C, int32_t *Cn, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -628,6 +688,20 @@ hipError_t launch_reduce_counts(const unsigned long long *part, TierGrids g,
   return hipGetLastError();
 }
 
+hipError_t launch_frontier(const SweepArgs &a, int64_t n, const TierConfig &cfg, const int64_t *tier_start_h,
+                           int32_t *flist, int64_t *fcount, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  TierBounds tb, start;
+  for (int t = 0; t < kNumTiers; ++t) {
+    tb.b[t] = cfg.bound[t];
+    start.b[t] = tier_start_h[t];
+  }
+  const int64_t chunks = (n + kFrontierBlock - 1) / kFrontierBlock;
+  frontier_build<<<(unsigned)(chunks < kFrontierGrid ? chunks : kFrontierGrid), kFrontierBlock, 0, s>>>(
+      a, n, tb, start, flist, fcount);
+  return hipGetLastError();
+}
+
 hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, int64_t *gdn, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   apply_changes<<<grid_for((n + 3) / 4, 256, 256 * 32), 256, 0, s>>>(
@@ -642,7 +716,7 @@ namespace {
 // changed at most n/8 vertices; the sweep after a non-marking sweep runs
 // dense (pruning is exact, so processing extra vertices changes nothing).
 __global__ void sweep_end(SweepCtrl *c, const unsigned long long *dn, unsigned long long *marked_sweeps,
-                          const unsigned long long *overflow) {
+                          const unsigned long long *overflow, int64_t *fcount) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || c->done) return;
   const unsigned long long d = dn[c->it];
   marked_sweeps[c->it] = (unsigned long long)c->mark;
@@ -663,6 +737,12 @@ __global__ void sweep_end(SweepCtrl *c, const unsigned long long *dn, unsigned l
   c->done = stop ? 1 : 0;
   c->dense = (c->prune && marked) ? 0 : 1;
   c->mark = (c->prune && (int64_t)d * 8 <= c->n) ? 1 : 0;
+  // After a sweep with few changes the next sweep's active vertices are few
+  // too: a frontier of them beats scanning the tier lists (a sweep that
+  // changed a quarter of the vertices, as on road graphs, keeps the scan).
+  c->front = (int64_t)d * 16 <= c->n ? 1 : 0;
+  if (fcount)
+    for (int t = 0; t < kNumTiers; ++t) fcount[t] = 0;
 }
 
 // Sets up the loop state before the first sweep.  When the renumbering copy
@@ -676,6 +756,7 @@ __global__ void loop_init(SweepCtrl *c, const unsigned long long *first_flags, u
   c->active = 0;
   c->dense = 1;
   c->mark = 0;
+  c->front = 0;
   c->done = c->max_iters <= 0 ? 1 : 0;
   if (!first_flags || c->max_iters <= 0) return;
   const unsigned long long ff = *first_flags;
@@ -752,8 +833,8 @@ __global__ __launch_bounds__(256) void graph_end(SweepCtrl *c, int64_t *__restri
 }  // namespace
 
 hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsigned long long *marked_sweeps,
-                            const unsigned long long *overflow, hipStream_t s) {
-  sweep_end<<<1, 64, 0, s>>>(ctrl, dn, marked_sweeps, overflow);
+                            const unsigned long long *overflow, hipStream_t s, int64_t *fcount) {
+  sweep_end<<<1, 64, 0, s>>>(ctrl, dn, marked_sweeps, overflow, fcount);
   return hipGetLastError();
 }
 

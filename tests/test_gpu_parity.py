@@ -184,6 +184,43 @@ def test_row_loads_at_any_alignment(gsl, shift):
         gsl.gsl_set_tiers(None)
 
 
+def test_sparse_sweeps_process_exactly_the_active_vertices(gsl):
+    """Run to convergence (tolerance 0), so the late sweeps are sparse and,
+    after a sweep that changed at most n/16 vertices, walk a frontier of the
+    active vertices instead of scanning the tier lists.  Labels and changes
+    per sweep equal the oracle's, and every sparse sweep (t >= 2 after a
+    sweep t - 2 that changed at most n/8, the rule that lets sweep t - 1 mark
+    neighbours) processes exactly the oracle's vertices of that sweep (Alg. 3
+    pruning: the neighbours of the vertices changed in sweep t - 1); a dense
+    sweep processes at least those (the oracle also counts the vertices
+    without entries in sweep 0, which the GPU never lists).  Both layouts,
+    default and thread-heavy tier tables."""
+    graphs = [graphgen.planted(20000, 100, 0.1, 20000, 41), workloads.make(4, small=True),
+              graphgen.planted(8001, 40, 0.2, 4000, 43, wmin=1, wmax=7)]
+    try:
+        for levels in (None, THREAD_LEVELS):
+            gsl.gsl_set_tiers(levels)
+            for g in graphs:
+                r = oracle.lpa(g, 40, 0.0)
+                iso = int((np.diff(g.offsets) == 0).sum())
+                for layout in ("original", "renumbered"):
+                    lab, st = run_gpu(gsl, g, 40, 0.0, layout=layout)
+                    tag = (g.name, layout, levels)
+                    assert st["iterations"] == r.iterations, tag
+                    assert list(st["changed"]) == list(r.dn), tag
+                    np.testing.assert_array_equal(lab, r.labels, err_msg=str(tag))
+                    sparse = 0
+                    for t in range(r.iterations):
+                        if t >= 2 and r.dn[t - 2] * 8 <= g.n:
+                            assert st["processed"][t] == r.processed[t], (tag, t)
+                            sparse += 1
+                        else:
+                            assert st["processed"][t] >= r.processed[t] - iso, (tag, t)
+                    assert sparse > 0, tag
+    finally:
+        gsl.gsl_set_tiers(None)
+
+
 def test_deterministic_across_runs(gsl):
     g = workloads.make(2, small=True)
     first, _ = run_gpu(gsl, g)
