@@ -186,8 +186,9 @@ def test_row_loads_at_any_alignment(gsl, shift):
 
 def test_sparse_sweeps_process_exactly_the_active_vertices(gsl):
     """Run to convergence (tolerance 0), so the late sweeps are sparse and,
-    after a sweep that changed at most n/16 vertices, walk a frontier of the
-    active vertices instead of scanning the tier lists.  Labels and changes
+    on graphs of at least 2^20 vertices after a sweep that changed at most
+    n/16 of them, walk a frontier of the active vertices instead of scanning
+    the tier lists (the smaller graphs keep the scan).  Labels and changes
     per sweep equal the oracle's, and every sparse sweep (t >= 2 after a
     sweep t - 2 that changed at most n/8, the rule that lets sweep t - 1 mark
     neighbours) processes exactly the oracle's vertices of that sweep (Alg. 3
@@ -195,8 +196,8 @@ def test_sparse_sweeps_process_exactly_the_active_vertices(gsl):
     sweep processes at least those (the oracle also counts the vertices
     without entries in sweep 0, which the GPU never lists).  Both layouts,
     default and thread-heavy tier tables."""
-    graphs = [graphgen.planted(20000, 100, 0.1, 20000, 41), workloads.make(4, small=True),
-              graphgen.planted(8001, 40, 0.2, 4000, 43, wmin=1, wmax=7)]
+    graphs = [graphgen.planted((1 << 20) + 5, 8192, 0.08, 200000, 47), graphgen.planted(20000, 100, 0.1, 20000, 41),
+              workloads.make(4, small=True), graphgen.planted(8001, 40, 0.2, 4000, 43, wmin=1, wmax=7)]
     try:
         for levels in (None, THREAD_LEVELS):
             gsl.gsl_set_tiers(levels)
