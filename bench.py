@@ -68,10 +68,13 @@ def log(*a):
 def tier_bytes(t: dict, weighted: bool) -> int:
     """Algorithmic bytes a sweep kernel moves for one tier, summed over its
     launches: per listed vertex the 4 B list entry (+1 B active flag in sparse
-    launches); per processed vertex two 8 B offsets and its own 4 B label; per
-    row entry a 4 B column, a 4 B gathered label (+4 B weight); per changed
-    vertex its 4 B new label and 1 B change flag; 1 B per neighbour flag set."""
-    listed = t["vertices"] * t["launches"]
+    launches that scan the tier; a launch that walks a frontier reads 4 B per
+    frontier entry instead); per processed vertex two 8 B offsets and its own
+    4 B label; per row entry a 4 B column, a 4 B gathered label (+4 B weight);
+    per changed vertex its 4 B new label and 1 B change flag; 1 B per
+    neighbour flag set."""
+    scans = t["launches"] - t.get("frontier_launches", 0)
+    listed = t["vertices"] * scans + t.get("frontier_listed", 0)
     return (listed * 4 + t["vertices"] * t["sparse_launches"] * 1
             + t["processed"] * (16 + 4)
             + t["edges"] * (8 + (4 if weighted else 0))
@@ -416,7 +419,7 @@ def roofline_from_stats(stats, weighted, steps, wname, n):
     dom = max(range(1, NUM_TIERS), key=lambda t: ms_tier[t])
     agg = {key: sum(st["tiers"][dom][key] for st in stats)
            for key in ("vertices", "launches", "processed", "edges", "changed", "marked",
-                       "sparse_launches")}
+                       "sparse_launches", "frontier_launches", "frontier_listed")}
     agg["vertices"] = stats[0]["tiers"][dom]["vertices"]
     launches = agg["launches"]
     bytes_total = tier_bytes(agg, weighted)

@@ -93,11 +93,15 @@ typedef struct gsl_stats {
   int64_t tier_edges[GSL_STATS_TIERS];      /* row entries scanned */
   int64_t tier_changed[GSL_STATS_TIERS];    /* vertices that changed label */
   int64_t tier_marked[GSL_STATS_TIERS];     /* neighbour flags written */
-  int64_t tier_sparse[GSL_STATS_TIERS];     /* launches that read the active flags */
+  int64_t tier_sparse[GSL_STATS_TIERS];     /* launches that scanned the tier against the active flags */
   int32_t renumbered;                       /* 1 if the sweeps ran on the renumbered copy */
   float ms_reorder;                         /* time to build that copy (timing != 0) */
   float ms_hub_finish;                      /* hub table scan, decision, marking */
   float ms_tier[GSL_STATS_TIERS];           /* kernel time (timing != 0) */
+  /* Sparse sweeps after a sweep with few changes walk a frontier of the
+   * active vertices instead of scanning the tier: */
+  int64_t tier_frontier[GSL_STATS_TIERS];        /* such launches */
+  int64_t tier_frontier_listed[GSL_STATS_TIERS]; /* frontier entries they walked */
 } gsl_stats;
 
 /*

@@ -57,7 +57,9 @@ class _Stats(ctypes.Structure):
                 ("tier_sparse", ctypes.c_int64 * STATS_TIERS),
                 ("renumbered", ctypes.c_int32), ("ms_reorder", ctypes.c_float),
                 ("ms_hub_finish", ctypes.c_float),
-                ("ms_tier", ctypes.c_float * STATS_TIERS)]
+                ("ms_tier", ctypes.c_float * STATS_TIERS),
+                ("tier_frontier", ctypes.c_int64 * STATS_TIERS),
+                ("tier_frontier_listed", ctypes.c_int64 * STATS_TIERS)]
 
 
 TIER_LEVELS = 7
@@ -244,7 +246,8 @@ def _stats_dict(st):
             "tiers": [{"vertices": st.tier_vertices[t], "launches": st.tier_launches[t],
                        "processed": st.tier_processed[t], "edges": st.tier_edges[t],
                        "changed": st.tier_changed[t], "marked": st.tier_marked[t],
-                       "sparse_launches": st.tier_sparse[t], "ms": st.ms_tier[t]}
+                       "sparse_launches": st.tier_sparse[t], "frontier_launches": st.tier_frontier[t],
+                       "frontier_listed": st.tier_frontier_listed[t], "ms": st.ms_tier[t]}
                       for t in range(STATS_TIERS)]}
 
 

@@ -818,7 +818,8 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
     HIP_TRY(gsl::launch_apply(a, C, n_sweep, batch ? s.gdn : nullptr, cur));
     if (batch)
       HIP_TRY(gsl::launch_graph_end(s.ctrl, s.gdn, s.glimit, s.giters, s.gdone, batch->graphs, cur));
-    HIP_TRY(gsl::launch_sweep_end(s.ctrl, dn_arr, mk_arr, a.overflow, cur, frontier ? s.ctr->fcount : nullptr));
+    HIP_TRY(gsl::launch_sweep_end(s.ctrl, dn_arr, mk_arr, a.overflow, cur, frontier ? s.ctr->fcount : nullptr,
+                                  s.ctr->ftotal));
     if (timed && (rc = rec(nev++))) return rc;
     return GSL_OK;
   };
@@ -1014,8 +1015,13 @@ int lpa_impl(Scratch &s, hipStream_t st, const int64_t *offsets, const int32_t *
       if (t == 0 || plan.tier_count[t] <= 0) continue;
       for (int k = first_kernel_sweep; k < it; ++k) {
         stats->tier_launches[t] += 1;
-        stats->tier_sparse[t] += (k > 0 && o.prune && hm[k - 1]) ? 1 : 0;
+        const bool sparse = k > 0 && o.prune && hm[k - 1];
+        // the loop state's rule: after a sweep with at most n/16 changes
+        const bool front = sparse && frontier && t != gsl::kHubTier && (int64_t)hd[k - 1] * 16 <= n;
+        stats->tier_sparse[t] += sparse && !front ? 1 : 0;
+        stats->tier_frontier[t] += front ? 1 : 0;
       }
+      stats->tier_frontier_listed[t] = s.ctr_host->ftotal[t];
     }
     stats->renumbered = renumber ? 1 : 0;
     if (timed) {

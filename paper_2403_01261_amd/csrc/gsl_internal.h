@@ -97,6 +97,7 @@ struct Counters {
   uint64_t pad[3];
   int64_t tier_edges[16];   // row entries per tier
   int64_t fcount[16];       // sparse sweeps: active vertices of each tier (the frontier)
+  int64_t ftotal[16];       // frontier entries per tier, summed over the sweeps
   // per tier, summed over sweeps: processed, edges, changed, marked
   unsigned long long tier_stats[kNumTiers][4];
   // followed by per-sweep arrays dn[max_iters], processed[], edges[], marked[]
@@ -239,14 +240,15 @@ hipError_t launch_apply(const SweepArgs &a, int32_t *C, int64_t n, int64_t *gdn,
 // the loop state): the frontier of the sweep about to run -- each vertex of
 // [0, n) whose active flag is set, whose row is not empty and not a hub's, and
 // whose graph still runs -- into its tier's range [tier_start[t], +count) of
-// flist, the counts added to fcount[t] (cleared by the sweep_end before).
+// flist, the counts added to fcount[t] (which the sweep_end before cleared,
+// and the sweep_end after adds to the per-tier totals).
 // Other sweeps return at once.
 hipError_t launch_frontier(const SweepArgs &a, int64_t n, const TierConfig &cfg, const int64_t *tier_start_h,
                            int32_t *flist, int64_t *fcount, hipStream_t s);
 // Advances the loop state after a sweep.
 hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsigned long long *marked_sweeps,
                             const unsigned long long *overflow, hipStream_t s,
-                            int64_t *fcount = nullptr);
+                            int64_t *fcount = nullptr, int64_t *ftotal = nullptr);
 // Loop state before the first sweep; first_flags (NULL unless renumbered)
 // tells whether the renumbering copy already ran sweep 0.
 hipError_t launch_loop_init(SweepCtrl *ctrl, const unsigned long long *first_flags, unsigned long long *dn,

@@ -716,7 +716,7 @@ namespace {
 // changed at most n/8 vertices; the sweep after a non-marking sweep runs
 // dense (pruning is exact, so processing extra vertices changes nothing).
 __global__ void sweep_end(SweepCtrl *c, const unsigned long long *dn, unsigned long long *marked_sweeps,
-                          const unsigned long long *overflow, int64_t *fcount) {
+                          const unsigned long long *overflow, int64_t *fcount, int64_t *ftotal) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || c->done) return;
   const unsigned long long d = dn[c->it];
   marked_sweeps[c->it] = (unsigned long long)c->mark;
@@ -742,7 +742,10 @@ __global__ void sweep_end(SweepCtrl *c, const unsigned long long *dn, unsigned l
   // changed a quarter of the vertices, as on road graphs, keeps the scan).
   c->front = (int64_t)d * 16 <= c->n ? 1 : 0;
   if (fcount)
-    for (int t = 0; t < kNumTiers; ++t) fcount[t] = 0;
+    for (int t = 0; t < kNumTiers; ++t) {
+      if (ftotal) ftotal[t] += fcount[t];
+      fcount[t] = 0;
+    }
 }
 
 // Sets up the loop state before the first sweep.  When the renumbering copy
@@ -833,8 +836,9 @@ __global__ __launch_bounds__(256) void graph_end(SweepCtrl *c, int64_t *__restri
 }  // namespace
 
 hipError_t launch_sweep_end(SweepCtrl *ctrl, const unsigned long long *dn, unsigned long long *marked_sweeps,
-                            const unsigned long long *overflow, hipStream_t s, int64_t *fcount) {
-  sweep_end<<<1, 64, 0, s>>>(ctrl, dn, marked_sweeps, overflow, fcount);
+                            const unsigned long long *overflow, hipStream_t s, int64_t *fcount,
+                            int64_t *ftotal) {
+  sweep_end<<<1, 64, 0, s>>>(ctrl, dn, marked_sweeps, overflow, fcount, ftotal);
   return hipGetLastError();
 }
 

@@ -27,6 +27,10 @@ def test_tier_bytes_per_unit():
     # a tier listed in 3 launches, one of them sparse
     t = one(vertices=10, launches=3, sparse_launches=1, processed=25, edges=100, changed=7, marked=40)
     assert bench.tier_bytes(t, True) == 10 * 3 * 4 + 10 + 25 * 20 + 100 * 12 + 7 * 5 + 40
+    # two more launches walked frontiers of 3 and 2 vertices: 4 B per entry,
+    # no scan of the tier list and no flag reads
+    t = one(vertices=10, launches=5, sparse_launches=1, frontier_launches=2, frontier_listed=5)
+    assert bench.tier_bytes(t, False) == 10 * 3 * 4 + 10 + 5 * 4
 
 
 def _write(path, header, rows):

@@ -186,8 +186,8 @@ def test_row_loads_at_any_alignment(gsl, shift):
 
 def test_sparse_sweeps_process_exactly_the_active_vertices(gsl):
     """Run to convergence (tolerance 0), so the late sweeps are sparse and,
-    on graphs of at least 2^20 vertices after a sweep that changed at most
-    n/16 of them, walk a frontier of the active vertices instead of scanning
+    on graphs that sweep at least 2^20 vertices after a sweep that changed
+    at most n/16 of them, walk a frontier of the active vertices instead of scanning
     the tier lists (the smaller graphs keep the scan).  Labels and changes
     per sweep equal the oracle's, and every sparse sweep (t >= 2 after a
     sweep t - 2 that changed at most n/8, the rule that lets sweep t - 1 mark
@@ -196,7 +196,7 @@ def test_sparse_sweeps_process_exactly_the_active_vertices(gsl):
     sweep processes at least those (the oracle also counts the vertices
     without entries in sweep 0, which the GPU never lists).  Both layouts,
     default and thread-heavy tier tables."""
-    graphs = [graphgen.planted((1 << 20) + 5, 8192, 0.08, 200000, 47), graphgen.planted(20000, 100, 0.1, 20000, 41),
+    graphs = [graphgen.planted((1 << 20) + 5000, 8192, 0.08, 200000, 47), graphgen.planted(20000, 100, 0.1, 20000, 41),
               workloads.make(4, small=True), graphgen.planted(8001, 40, 0.2, 4000, 43, wmin=1, wmax=7)]
     try:
         for levels in (None, THREAD_LEVELS):
@@ -207,17 +207,27 @@ def test_sparse_sweeps_process_exactly_the_active_vertices(gsl):
                 for layout in ("original", "renumbered"):
                     lab, st = run_gpu(gsl, g, 40, 0.0, layout=layout)
                     tag = (g.name, layout, levels)
+                    swept = g.n - iso if st["renumbered"] else g.n  # the renumbered copy drops empty rows
                     assert st["iterations"] == r.iterations, tag
                     assert list(st["changed"]) == list(r.dn), tag
                     np.testing.assert_array_equal(lab, r.labels, err_msg=str(tag))
-                    sparse = 0
+                    sparse, front = 0, []
                     for t in range(r.iterations):
                         if t >= 2 and r.dn[t - 2] * 8 <= g.n:
                             assert st["processed"][t] == r.processed[t], (tag, t)
                             sparse += 1
+                            if swept >= 1 << 20 and r.dn[t - 1] * 16 <= g.n:
+                                front.append(t)
                         else:
                             assert st["processed"][t] >= r.processed[t] - iso, (tag, t)
                     assert sparse > 0, tag
+                    # the statistics: launches that walked a frontier, and its
+                    # entries -- every vertex those sweeps processed (no hubs here)
+                    tiers = st["tiers"]
+                    assert sum(x["frontier_launches"] > 0 for x in tiers) == 0 or front, tag
+                    assert sum(x["frontier_listed"] for x in tiers) == sum(st["processed"][t] for t in front), tag
+                    if swept >= 1 << 20:
+                        assert front and sum(x["frontier_launches"] for x in tiers) >= len(front), tag
     finally:
         gsl.gsl_set_tiers(None)
 
