@@ -74,11 +74,13 @@ __device__ __forceinline__ void flush_counts(const SweepArgs &a, const LocalCoun
 // and never becomes a candidate.  W: weighted rows; without it every entry
 // weighs 1.
 //
-// The sweep is bound by the latency of the label gathers, so registers are
-// kept few (more waves in flight): each label is loaded into the register
-// that held its column, and with O32 (fewer than 2^30 vertices) the gather
-// address is the label array's base plus a 32-bit byte offset, which needs
-// no 64-bit address registers.
+// The sweep waits on its vector memory instructions (row loads and label
+// gathers, one lane access each): with V4 a row comes in as 16-byte words
+// (load_row), each label is loaded into the register that held its column,
+// and with O32 (fewer than 2^30 vertices) the gather address is the label
+// array's base plus a 32-bit byte offset, which needs no 64-bit address
+// registers.  A sparse sweep after few changes walks the frontier instead of
+// the tier list.
 // ---------------------------------------------------------------------------
 __device__ const int32_t kZeroI32 = 0;
 __device__ const uint8_t kZeroU8 = 0;
@@ -282,8 +284,9 @@ void launch_thread(const SweepArgs &a, const int32_t *list, int64_t first, int64
 // the vertex takes part in this sweep (pruning flag, stopped graph of a
 // batch), the taken vertices are packed into LDS in list order, and the
 // groups then work through the packed vertices only.  A sparse sweep thus
-// costs one flag check per thread instead of one per group.  All groups of a
-// block move through the insert / read phases together.
+// costs one flag check per thread instead of one per group, and one after
+// few changes walks the frontier (every entry taken).  All groups of a block
+// move through the insert / read phases together.
 // ---------------------------------------------------------------------------
 template <int G, int LOG2S, int BLOCK, int K>
 __global__ __launch_bounds__(BLOCK) void sweep_lds(SweepArgs a, const int32_t *__restrict__ list,
